@@ -1,0 +1,354 @@
+"""CPU FP64 oracle (test infrastructure only).
+
+A plain, slow, obviously correct statement of what the domain-decomposed
+ILU0 path computes, used to check the GPU library.  Only the tests, the
+smoke check and the benchmark's CPU-baseline leg may import this package; the
+GPU library never does, and this package never imports the GPU library.
+
+The numerics live in ``oracle.c`` (plain sequential C loops, FP64), loaded
+through ctypes; the thin wrappers here only allocate numpy arrays.  Each
+function cites the part of arXiv 2508.04917 it follows.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+O_OK, O_EINVAL, O_ENOTDIV, O_EZEROPIVOT, O_EBREAKDOWN, O_ENOCONV = 0, -1, -2, -4, -5, -6
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (plain -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"]
+        )
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        _lib = C.CDLL(_LIB)
+        i64, i32, vp = C.c_int64, C.c_int32, C.c_void_p
+        sig = {
+            "o_block_inverse": (C.c_int, [C.c_int, vp, vp]),
+            "o_partition": (C.c_int, [C.c_int] * 6 + [vp]),
+            "o_permutation": (C.c_int, [i64, i32, vp, vp, vp]),
+            "o_reorder": (C.c_int, [i64, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp]),
+            "o_drop": (i64, [i64, C.c_int, i64, vp, vp, vp, vp, vp, vp]),
+            "o_levels": (C.c_int, [i64, vp, vp, C.c_int, vp]),
+            "o_level_lists": (i64, [i64, i64, vp, vp, vp, vp]),
+            "o_bilu0": (C.c_int, [i64, C.c_int, vp, vp, vp, vp]),
+            "o_ildu0": (C.c_int, [i64, C.c_int, vp, vp, vp, vp]),
+            "o_apply": (None, [i64, C.c_int, vp, vp, vp, vp, vp]),
+            "o_apply_ilu0": (C.c_int, [i64, C.c_int, vp, vp, vp, vp, vp]),
+            "o_apply_transpose": (None, [i64, C.c_int, vp, vp, vp, vp, vp]),
+            "o_spmv": (None, [i64, C.c_int, vp, vp, vp, vp, vp]),
+            "o_bicgstab": (C.c_int, [i64, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp,
+                                     C.c_double, i32, vp, vp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(_lib, name)
+            f.restype = res
+            f.argtypes = args
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+# ---------------------------------------------------------------- partition
+def subdomain_count(nx, ny, nz, sx, sy, sz):
+    return (nx // sx) * (ny // sy) * (nz // sz)
+
+
+def auto_subdims(nx, ny, nz, bs, lds_budget_bytes, n_cu):
+    """Automatic subdomain extents: the largest box whose FP64 vector
+    (S*bs*8 bytes) fits one workgroup's LDS budget (Section 4: the subdomain
+    is sized so that its vector data fits in shared memory).
+
+    Candidates are divisor triples (sx|nx, sy|ny, sz|nz).  If some candidate
+    gives at least n_cu subdomains, only those are kept (every compute unit
+    gets work).  Then: largest S, then smallest surface sx*sy+sy*sz+sz*sx
+    (fewest dropped couplings), then largest sz, then largest sy.
+    Returns None when nothing fits.
+    """
+    def divs(m):
+        return [d for d in range(1, m + 1) if m % d == 0]
+
+    cands = []
+    for sx in divs(nx):
+        for sy in divs(ny):
+            for sz in divs(nz):
+                S = sx * sy * sz
+                if S * bs * 8 <= lds_budget_bytes:
+                    cands.append((sx, sy, sz))
+    if not cands:
+        return None
+    full = [c for c in cands if subdomain_count(nx, ny, nz, *c) >= n_cu]
+    if full:
+        cands = full
+
+    def key(c):
+        sx, sy, sz = c
+        return (-(sx * sy * sz), sx * sy + sy * sz + sz * sx, -sz, -sy)
+
+    return min(cands, key=key)
+
+
+def partition(nx, ny, nz, sx, sy, sz):
+    """Section 3, Algorithm 2: part_id for every cell g = i + nx*(j + ny*k)."""
+    out = np.empty(nx * ny * nz, dtype=np.int32)
+    rc = lib().o_partition(nx, ny, nz, sx, sy, sz, _p(out))
+    if rc:
+        raise OracleError(rc, "partition")
+    return out
+
+
+def permutation(part_id, nsub):
+    """Section 3.1: group rows by label, stable in the old index.
+    Returns (new2old, old2new)."""
+    part_id = _i32(part_id)
+    n = part_id.shape[0]
+    n2o = np.empty(n, dtype=np.int32)
+    o2n = np.empty(n, dtype=np.int32)
+    rc = lib().o_permutation(n, nsub, _p(part_id), _p(n2o), _p(o2n))
+    if rc:
+        raise OracleError(rc, "permutation")
+    return n2o, o2n
+
+
+def reorder(n, bs, ptr, col, val, new2old, old2new):
+    """Section 3.1, Algorithm 3 in block form; val may be None (pattern only)."""
+    ptr, col = _i32(ptr), _i32(col)
+    nnzb = col.shape[0]
+    optr = np.empty(n + 1, dtype=np.int32)
+    ocol = np.empty(nnzb, dtype=np.int32)
+    oval = None
+    if val is not None:
+        val = _f64(val)
+        oval = np.empty_like(val)
+    lib().o_reorder(n, bs, _p(ptr), _p(col), _p(val), _p(_i32(new2old)), _p(_i32(old2new)),
+                    _p(optr), _p(ocol), _p(oval))
+    return optr, ocol, oval
+
+
+def drop(n, bs, S, ptr, col, val=None):
+    """Section 3.2: keep block (I,J) iff I and J lie in the same S-row window."""
+    ptr, col = _i32(ptr), _i32(col)
+    if val is not None:
+        val = _f64(val)
+    m = lib().o_drop(n, bs, S, _p(ptr), _p(col), None, None, None, None)
+    tptr = np.empty(n + 1, dtype=np.int32)
+    tcol = np.empty(m, dtype=np.int32)
+    tval = None if val is None else np.empty((m,) + val.shape[1:], dtype=np.float64)
+    lib().o_drop(n, bs, S, _p(ptr), _p(col), _p(val), _p(tptr), _p(tcol), _p(tval))
+    return tptr, tcol, tval
+
+
+def count_after_drop(n, S, ptr, col):
+    ptr, col = _i32(ptr), _i32(col)
+    return int(lib().o_drop(n, 1, S, _p(ptr), _p(col), None, None, None, None))
+
+
+# ------------------------------------------------------------------- levels
+def levels(ptr, col, which):
+    """Section 4.2.1: per-row longest-path level (which=0 lower, 1 upper)."""
+    ptr, col = _i32(ptr), _i32(col)
+    n = ptr.shape[0] - 1
+    lev = np.empty(n, dtype=np.int32)
+    rc = lib().o_levels(n, _p(ptr), _p(col), which, _p(lev))
+    if rc:
+        raise OracleError(rc, "levels")
+    return lev
+
+
+def level_lists(lev, S):
+    """Section 4.2.2 explicit per-subdomain DAG: (nlev[nsub], level_ptr, level_rows)."""
+    lev = _i32(lev)
+    n = lev.shape[0]
+    nsub = n // S
+    nlev = np.empty(nsub, dtype=np.int32)
+    lptr = np.empty(n + nsub, dtype=np.int32)
+    rows = np.empty(n, dtype=np.int32)
+    w = lib().o_level_lists(n, S, _p(lev), _p(nlev), _p(lptr), _p(rows))
+    if w < 0:
+        raise OracleError(int(w), "level_lists")
+    return nlev, lptr[:w].copy(), rows
+
+
+# ---------------------------------------------------------------- factorise
+def bilu0(n, bs, ptr, col, val):
+    """Section 4.3, Algorithm 5 (block IKJ ILU0); returns L\\U in val's pattern."""
+    f = _f64(val).copy()
+    bad = C.c_int64(-1)
+    rc = lib().o_bilu0(n, bs, _p(_i32(ptr)), _p(_i32(col)), _p(f), C.byref(bad))
+    if rc:
+        raise OracleError(rc, f"zero pivot at block row {bad.value}")
+    return f
+
+
+def ildu0(n, bs, ptr, col, lu):
+    """Section 4.3 ILDU0 post-pass: diagonal slot <- U_II^{-1}, upper <- inv_D U."""
+    f = _f64(lu).copy()
+    bad = C.c_int64(-1)
+    rc = lib().o_ildu0(n, bs, _p(_i32(ptr)), _p(_i32(col)), _p(f), C.byref(bad))
+    if rc:
+        raise OracleError(rc, f"zero pivot at block row {bad.value}")
+    return f
+
+
+def block_inverse(A):
+    A = _f64(A)
+    bs = A.shape[0]
+    out = np.empty_like(A)
+    rc = lib().o_block_inverse(bs, _p(A), _p(out))
+    if rc:
+        raise OracleError(rc, "singular block")
+    return out
+
+
+# -------------------------------------------------------------------- apply
+def apply(n, bs, ptr, col, f, r):
+    """Sections 4.2.2 and 4.4: z = (L D Uhat)^{-1} r (forward, scale, backward)."""
+    r = _f64(r)
+    z = np.empty_like(r)
+    lib().o_apply(n, bs, _p(_i32(ptr)), _p(_i32(col)), _p(_f64(f)), _p(r), _p(z))
+    return z
+
+
+def apply_ilu0(n, bs, ptr, col, lu, r):
+    """Algorithm 7 form: division by U_II inside the backward row."""
+    r = _f64(r)
+    z = np.empty_like(r)
+    rc = lib().o_apply_ilu0(n, bs, _p(_i32(ptr)), _p(_i32(col)), _p(_f64(lu)), _p(r), _p(z))
+    if rc:
+        raise OracleError(rc, "apply_ilu0")
+    return z
+
+
+def apply_transpose(n, bs, ptr, col, f, r):
+    """z = M^{-T} r for M = L D Uhat."""
+    r = _f64(r)
+    z = np.empty_like(r)
+    lib().o_apply_transpose(n, bs, _p(_i32(ptr)), _p(_i32(col)), _p(_f64(f)), _p(r), _p(z))
+    return z
+
+
+def spmv(n, bs, ptr, col, val, x):
+    x = _f64(x)
+    y = np.empty_like(x)
+    lib().o_spmv(n, bs, _p(_i32(ptr)), _p(_i32(col)), _p(_f64(val)), _p(x), _p(y))
+    return y
+
+
+@dataclass
+class SolveResult:
+    x: np.ndarray
+    iters: int
+    relres: float
+    status: int
+    history: np.ndarray
+
+
+def bicgstab(n, bs, aptr, acol, aval, fptr, fcol, fval, b, rtol=1e-8, maxit=10000, x0=None):
+    """Section 2, Algorithm 1 with K1 = I, K2 = M (right preconditioning)."""
+    b = _f64(b)
+    x = np.zeros_like(b) if x0 is None else _f64(x0).copy()
+    it = C.c_int32(0)
+    rr = C.c_double(0.0)
+    hist = np.full(maxit + 1, np.nan)
+    rc = lib().o_bicgstab(n, bs, _p(_i32(aptr)), _p(_i32(acol)), _p(_f64(aval)),
+                          _p(_i32(fptr)), _p(_i32(fcol)), _p(_f64(fval)),
+                          _p(b), _p(x), rtol, maxit, C.byref(it), C.byref(rr), _p(hist))
+    return SolveResult(x, it.value, rr.value, rc, hist[: it.value + 1])
+
+
+# --------------------------------------------------------- whole-path setup
+@dataclass
+class OracleSetup:
+    n: int
+    bs: int
+    sub: tuple
+    S: int
+    nsub: int
+    part_id: np.ndarray
+    new2old: np.ndarray
+    old2new: np.ndarray
+    aptr: np.ndarray   # full reordered A
+    acol: np.ndarray
+    aval: np.ndarray
+    tptr: np.ndarray   # dropped pattern A~
+    tcol: np.ndarray
+    tval: np.ndarray
+    lu: np.ndarray     # L\U on A~
+    f: np.ndarray      # L\inv_D\Uhat on A~ (ILDU0)
+
+    def apply(self, r):
+        return apply(self.n, self.bs, self.tptr, self.tcol, self.f, r)
+
+    def spmv(self, x):
+        return spmv(self.n, self.bs, self.aptr, self.acol, self.aval, x)
+
+    def levels(self, which):
+        return level_lists(levels(self.tptr, self.tcol, which), self.S)
+
+    def permute(self, v):
+        """original order -> reordered (block rows)."""
+        return np.asarray(v).reshape(self.n, self.bs)[self.new2old].reshape(-1)
+
+    def unpermute(self, v):
+        return np.asarray(v).reshape(self.n, self.bs)[self.old2new].reshape(-1)
+
+    def bicgstab(self, b_orig, rtol=1e-8, maxit=10000):
+        res = bicgstab(self.n, self.bs, self.aptr, self.acol, self.aval,
+                       self.tptr, self.tcol, self.f, self.permute(b_orig), rtol, maxit)
+        res.x = self.unpermute(res.x)
+        return res
+
+
+def setup(problem, sub):
+    """Partition, reorder, drop, BILU0 and ILDU0 for a problem (problems.Problem)."""
+    nx, ny, nz, bs = problem.nx, problem.ny, problem.nz, problem.bs
+    sx, sy, sz = sub
+    n = nx * ny * nz
+    S = sx * sy * sz
+    nsub = n // S
+    pid = partition(nx, ny, nz, sx, sy, sz)
+    n2o, o2n = permutation(pid, nsub)
+    aptr, acol, aval = reorder(n, bs, problem.brow_ptr, problem.bcol, problem.val, n2o, o2n)
+    tptr, tcol, tval = drop(n, bs, S, aptr, acol, aval)
+    lu = bilu0(n, bs, tptr, tcol, tval)
+    f = ildu0(n, bs, tptr, tcol, lu)
+    return OracleSetup(n, bs, tuple(sub), S, nsub, pid, n2o, o2n, aptr, acol, aval,
+                       tptr, tcol, tval, lu, f)

@@ -1,0 +1,551 @@
+/*
+ * CPU FP64 oracle for the domain-decomposed ILU0 path of
+ * "Mapping Sparse Triangular Solves to GPUs via Fine-grained Domain
+ * Decomposition" (arXiv 2508.04917).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
+ * GPU library is checked against.  Only the test suite, the smoke check and
+ * the benchmark's CPU-baseline leg may load it.  It shares no code, header or
+ * table with the GPU library and includes nothing from it.
+ *
+ * Every routine is a direct, sequential statement of the operation it names:
+ * loops in natural order, no blocking, no reordering beyond what the
+ * definition states.  Blocks are bs x bs (bs = 1 or 3), stored row-major;
+ * BSR arrays are (ptr[n+1], col[nnzb], val[nnzb*bs*bs]).
+ *
+ * Return codes: 0 ok, -1 invalid argument, -2 grid not divisible by the
+ * subdomain extents, -4 zero (or numerically singular) pivot block,
+ * -5 BiCGSTAB breakdown, -6 no convergence within maxit.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define O_OK 0
+#define O_EINVAL (-1)
+#define O_ENOTDIV (-2)
+#define O_EZEROPIVOT (-4)
+#define O_EBREAKDOWN (-5)
+#define O_ENOCONV (-6)
+
+/* ------------------------------------------------------------------ */
+/* small dense block helpers (bs x bs, row-major)                      */
+/* ------------------------------------------------------------------ */
+
+/* C = A * B */
+static void blk_mul(int bs, const double *A, const double *B, double *C) {
+    for (int i = 0; i < bs; ++i)
+        for (int j = 0; j < bs; ++j) {
+            double s = 0.0;
+            for (int k = 0; k < bs; ++k) s += A[i * bs + k] * B[k * bs + j];
+            C[i * bs + j] = s;
+        }
+}
+
+/* y -= A x */
+static void blk_matvec_sub(int bs, const double *A, const double *x, double *y) {
+    for (int i = 0; i < bs; ++i) {
+        double s = 0.0;
+        for (int k = 0; k < bs; ++k) s += A[i * bs + k] * x[k];
+        y[i] -= s;
+    }
+}
+
+/* y = A x */
+static void blk_matvec(int bs, const double *A, const double *x, double *y) {
+    for (int i = 0; i < bs; ++i) {
+        double s = 0.0;
+        for (int k = 0; k < bs; ++k) s += A[i * bs + k] * x[k];
+        y[i] = s;
+    }
+}
+
+static double blk_norm1(int bs, const double *A) {
+    double m = 0.0;
+    for (int j = 0; j < bs; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < bs; ++i) s += fabs(A[i * bs + j]);
+        if (s > m) m = s;
+    }
+    return m;
+}
+
+/* Inverse by Gauss-Jordan elimination with partial pivoting.
+ * Returns 0, or -4 when a pivot is zero/non-finite or cond_1 > 1e14. */
+int o_block_inverse(int bs, const double *A, double *Ainv) {
+    double a[9], inv[9];
+    if (bs < 1 || bs > 3) return O_EINVAL;
+    memcpy(a, A, sizeof(double) * bs * bs);
+    for (int i = 0; i < bs * bs; ++i) inv[i] = 0.0;
+    for (int i = 0; i < bs; ++i) inv[i * bs + i] = 1.0;
+    for (int c = 0; c < bs; ++c) {
+        int p = c;
+        for (int r = c + 1; r < bs; ++r)
+            if (fabs(a[r * bs + c]) > fabs(a[p * bs + c])) p = r;
+        double piv = a[p * bs + c];
+        if (!(fabs(piv) > 0.0) || !isfinite(piv)) return O_EZEROPIVOT;
+        if (p != c)
+            for (int k = 0; k < bs; ++k) {
+                double t = a[c * bs + k]; a[c * bs + k] = a[p * bs + k]; a[p * bs + k] = t;
+                t = inv[c * bs + k]; inv[c * bs + k] = inv[p * bs + k]; inv[p * bs + k] = t;
+            }
+        for (int k = 0; k < bs; ++k) { a[c * bs + k] /= piv; inv[c * bs + k] /= piv; }
+        for (int r = 0; r < bs; ++r) {
+            if (r == c) continue;
+            double f = a[r * bs + c];
+            for (int k = 0; k < bs; ++k) {
+                a[r * bs + k] -= f * a[c * bs + k];
+                inv[r * bs + k] -= f * inv[c * bs + k];
+            }
+        }
+    }
+    double cond = blk_norm1(bs, A) * blk_norm1(bs, inv);
+    if (!isfinite(cond) || cond > 1e14) return O_EZEROPIVOT;
+    memcpy(Ainv, inv, sizeof(double) * bs * bs);
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Section 3, Algorithm 2: partition labels by geometric cuts          */
+/* ------------------------------------------------------------------ */
+/* (sx, sy, sz) are subdomain EXTENTS in cells; the grid must divide evenly. */
+int o_partition(int nx, int ny, int nz, int sx, int sy, int sz, int32_t *part_id) {
+    if (nx <= 0 || ny <= 0 || nz <= 0 || sx <= 0 || sy <= 0 || sz <= 0) return O_EINVAL;
+    if (nx % sx || ny % sy || nz % sz) return O_ENOTDIV;
+    int bx = nx / sx, by = ny / sy;
+    for (int i = 0; i < nx; ++i) {
+        int ibx = i / sx;
+        for (int j = 0; j < ny; ++j) {
+            int jby = j / sy;
+            for (int k = 0; k < nz; ++k) {
+                int kbz = k / sz;
+                int64_t gidx = (int64_t)i + (int64_t)nx * ((int64_t)j + (int64_t)ny * k);
+                part_id[gidx] = ibx + bx * (jby + by * kbz);
+            }
+        }
+    }
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Section 3.1: renumber vertices by their label (stable in old index) */
+/* ------------------------------------------------------------------ */
+int o_permutation(int64_t n, int32_t nsub, const int32_t *part_id,
+                  int32_t *new2old, int32_t *old2new) {
+    int64_t *count = (int64_t *)calloc((size_t)nsub + 1, sizeof(int64_t));
+    if (!count) return O_EINVAL;
+    for (int64_t g = 0; g < n; ++g) {
+        if (part_id[g] < 0 || part_id[g] >= nsub) { free(count); return O_EINVAL; }
+        count[part_id[g] + 1]++;
+    }
+    for (int32_t s = 0; s < nsub; ++s) count[s + 1] += count[s];
+    for (int64_t g = 0; g < n; ++g) {
+        int64_t pos = count[part_id[g]]++;
+        new2old[pos] = (int32_t)g;
+        old2new[g] = (int32_t)pos;
+    }
+    free(count);
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Section 3.1, Algorithm 3 (block rows): reorder by row permutation   */
+/* Row i of the result is old row new2old[i]; columns map through      */
+/* old2new; each row's (column, block) pairs are sorted by column.     */
+/* val/oval may be NULL (pattern only).                                */
+/* ------------------------------------------------------------------ */
+int o_reorder(int64_t n, int bs, const int32_t *ptr, const int32_t *col, const double *val,
+              const int32_t *new2old, const int32_t *old2new,
+              int32_t *optr, int32_t *ocol, double *oval) {
+    int bb = bs * bs;
+    optr[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t k = new2old[i];
+        optr[i + 1] = ptr[k + 1] - ptr[k];
+    }
+    for (int64_t i = 0; i < n; ++i) optr[i + 1] += optr[i];
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t src = new2old[i];
+        int64_t start = m;
+        for (int64_t j = ptr[src]; j < ptr[src + 1]; ++j) {
+            ocol[m] = old2new[col[j]];
+            if (val) memcpy(oval + m * bb, val + j * bb, sizeof(double) * bb);
+            ++m;
+        }
+        /* insertion sort of the row's (column, block) pairs */
+        for (int64_t a = start + 1; a < m; ++a) {
+            int32_t c = ocol[a];
+            double blk[9];
+            if (val) memcpy(blk, oval + a * bb, sizeof(double) * bb);
+            int64_t b = a - 1;
+            while (b >= start && ocol[b] > c) {
+                ocol[b + 1] = ocol[b];
+                if (val) memcpy(oval + (b + 1) * bb, oval + b * bb, sizeof(double) * bb);
+                --b;
+            }
+            ocol[b + 1] = c;
+            if (val) memcpy(oval + (b + 1) * bb, blk, sizeof(double) * bb);
+        }
+    }
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Section 3.2: drop every block outside the S x S diagonal windows    */
+/* Returns the number of kept blocks.  With optr == NULL it only       */
+/* counts.  val/oval may be NULL (pattern only).                       */
+/* ------------------------------------------------------------------ */
+int64_t o_drop(int64_t n, int bs, int64_t S, const int32_t *ptr, const int32_t *col,
+               const double *val, int32_t *optr, int32_t *ocol, double *oval) {
+    int bb = bs * bs;
+    int64_t m = 0;
+    if (optr) optr[0] = 0;
+    for (int64_t I = 0; I < n; ++I) {
+        for (int64_t j = ptr[I]; j < ptr[I + 1]; ++j) {
+            if (col[j] / S == I / S) {
+                if (optr) {
+                    ocol[m] = col[j];
+                    if (val && oval) memcpy(oval + m * bb, val + j * bb, sizeof(double) * bb);
+                }
+                ++m;
+            }
+        }
+        if (optr) optr[I + 1] = (int32_t)m;
+    }
+    return m;
+}
+
+/* ------------------------------------------------------------------ */
+/* Section 4.2.1: level (longest dependency path) of each row.         */
+/* which = 0: lower factor, level(I) = 0 if row I has no J < I, else   */
+/*            1 + max level(J) over J < I in row I.                    */
+/* which = 1: upper factor, the mirror image over K > I.               */
+/* Computed sequentially (I ascending for L, descending for U).        */
+/* ------------------------------------------------------------------ */
+int o_levels(int64_t n, const int32_t *ptr, const int32_t *col, int which, int32_t *lev) {
+    if (which == 0) {
+        for (int64_t I = 0; I < n; ++I) {
+            int32_t l = 0;
+            for (int64_t j = ptr[I]; j < ptr[I + 1]; ++j)
+                if (col[j] < I && lev[col[j]] + 1 > l) l = lev[col[j]] + 1;
+            lev[I] = l;
+        }
+    } else if (which == 1) {
+        for (int64_t I = n - 1; I >= 0; --I) {
+            int32_t l = 0;
+            for (int64_t j = ptr[I]; j < ptr[I + 1]; ++j)
+                if (col[j] > I && lev[col[j]] + 1 > l) l = lev[col[j]] + 1;
+            lev[I] = l;
+        }
+    } else {
+        return O_EINVAL;
+    }
+    return O_OK;
+}
+
+/* Per-subdomain level lists (the explicit DAG of Section 4.2.2): for
+ * subdomain s, nlev[s] levels; level_ptr holds nlev[s]+1 offsets per
+ * subdomain (relative to the subdomain's first row), concatenated over s;
+ * level_rows holds the subdomain's local row indices grouped by level,
+ * ascending within a level.  level_ptr must have room for n + nsub entries.
+ * Returns the number of level_ptr entries written. */
+int64_t o_level_lists(int64_t n, int64_t S, const int32_t *lev, int32_t *nlev,
+                      int32_t *level_ptr, int32_t *level_rows) {
+    if (S <= 0 || n % S) return O_EINVAL;
+    int64_t nsub = n / S, w = 0;
+    int32_t *cnt = (int32_t *)malloc(sizeof(int32_t) * (size_t)(S + 1));
+    if (!cnt) return O_EINVAL;
+    for (int64_t s = 0; s < nsub; ++s) {
+        const int32_t *L = lev + s * S;
+        int32_t maxl = -1;
+        for (int64_t i = 0; i < S; ++i) if (L[i] > maxl) maxl = L[i];
+        int32_t nl = maxl + 1;
+        nlev[s] = nl;
+        for (int32_t l = 0; l <= nl; ++l) cnt[l] = 0;
+        for (int64_t i = 0; i < S; ++i) cnt[L[i] + 1]++;
+        for (int32_t l = 0; l < nl; ++l) cnt[l + 1] += cnt[l];
+        for (int32_t l = 0; l <= nl; ++l) level_ptr[w + l] = cnt[l];
+        for (int64_t i = 0; i < S; ++i) level_rows[s * S + cnt[L[i]]++] = (int32_t)i;
+        w += nl + 1;
+    }
+    free(cnt);
+    return w;
+}
+
+/* ------------------------------------------------------------------ */
+/* Section 4.3, Algorithm 5 (block form): ILU0 in IKJ order.           */
+/* In place on the values of a matrix whose pattern has every diagonal */
+/* block: afterwards the strictly lower blocks hold L (unit block      */
+/* diagonal implied) and the diagonal and upper blocks hold U.         */
+/* For each row I, for each J < I in row I (ascending):                */
+/*   L_IJ = U_IJ * U_JJ^{-1};                                          */
+/*   U_IK -= L_IJ * U_JK for every K > J present in both rows I and J. */
+/* (The listing's inner loop also visits K = J, which only cancels U's */
+/* copy of the lower entry; here that slot stores L_IJ instead.)       */
+/* ------------------------------------------------------------------ */
+static int64_t find_col(const int32_t *ptr, const int32_t *col, int64_t row, int32_t c) {
+    for (int64_t j = ptr[row]; j < ptr[row + 1]; ++j)
+        if (col[j] == c) return j;
+    return -1;
+}
+
+int o_bilu0(int64_t n, int bs, const int32_t *ptr, const int32_t *col, double *val,
+            int64_t *bad_row) {
+    int bb = bs * bs;
+    double inv[9], Lij[9], tmp[9];
+    for (int64_t I = 0; I < n; ++I) {
+        if (find_col(ptr, col, I, (int32_t)I) < 0) { if (bad_row) *bad_row = I; return O_EZEROPIVOT; }
+    }
+    for (int64_t I = 0; I < n; ++I) {
+        for (int64_t pj = ptr[I]; pj < ptr[I + 1]; ++pj) {
+            int32_t J = col[pj];
+            if (J >= I) continue;
+            int64_t djj = find_col(ptr, col, J, J);
+            if (o_block_inverse(bs, val + djj * bb, inv) != O_OK) {
+                if (bad_row) *bad_row = J;
+                return O_EZEROPIVOT;
+            }
+            blk_mul(bs, val + pj * bb, inv, Lij);
+            memcpy(val + pj * bb, Lij, sizeof(double) * bb);
+            for (int64_t pk = ptr[I]; pk < ptr[I + 1]; ++pk) {
+                int32_t K = col[pk];
+                if (K <= J) continue;
+                int64_t pjk = find_col(ptr, col, J, K);
+                if (pjk < 0) continue;
+                blk_mul(bs, Lij, val + pjk * bb, tmp);
+                for (int e = 0; e < bb; ++e) val[pk * bb + e] -= tmp[e];
+            }
+        }
+    }
+    /* the last pivots are never inverted above: check every diagonal block */
+    for (int64_t I = 0; I < n; ++I) {
+        if (o_block_inverse(bs, val + find_col(ptr, col, I, (int32_t)I) * bb, inv) != O_OK) {
+            if (bad_row) *bad_row = I;
+            return O_EZEROPIVOT;
+        }
+    }
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Section 4.3, ILDU0 post-pass: inv_D_I = U_II^{-1}, and the strictly */
+/* upper blocks are scaled from the left, Uhat_IK = inv_D_I U_IK, so   */
+/* U = D Uhat with unit block diagonal.  In place: the diagonal slot   */
+/* receives inv_D_I.                                                   */
+/* ------------------------------------------------------------------ */
+int o_ildu0(int64_t n, int bs, const int32_t *ptr, const int32_t *col, double *val,
+            int64_t *bad_row) {
+    int bb = bs * bs;
+    double inv[9], tmp[9];
+    for (int64_t I = 0; I < n; ++I) {
+        int64_t d = find_col(ptr, col, I, (int32_t)I);
+        if (d < 0 || o_block_inverse(bs, val + d * bb, inv) != O_OK) {
+            if (bad_row) *bad_row = I;
+            return O_EZEROPIVOT;
+        }
+        memcpy(val + d * bb, inv, sizeof(double) * bb);
+        for (int64_t pk = ptr[I]; pk < ptr[I + 1]; ++pk) {
+            if (col[pk] <= I) continue;
+            blk_mul(bs, inv, val + pk * bb, tmp);
+            memcpy(val + pk * bb, tmp, sizeof(double) * bb);
+        }
+    }
+    return O_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Section 4.2.2 (Algorithm 7) and 4.4: apply M^{-1} = (L D Uhat)^{-1} */
+/* f holds L (strictly lower), inv_D (diagonal) and Uhat (strictly     */
+/* upper) in one pattern.  Forward y_I = r_I - sum_{J<I} L_IJ y_J (I   */
+/* ascending), scale w_I = inv_D_I y_I, backward z_I = w_I -           */
+/* sum_{K>I} Uhat_IK z_K (I descending).  Rows sum in ascending        */
+/* column order.  r and z may not alias.                               */
+/* ------------------------------------------------------------------ */
+void o_apply(int64_t n, int bs, const int32_t *ptr, const int32_t *col, const double *f,
+             const double *r, double *z) {
+    int bb = bs * bs;
+    double *y = (double *)malloc(sizeof(double) * (size_t)(n * bs));
+    for (int64_t I = 0; I < n; ++I) {
+        for (int c = 0; c < bs; ++c) y[I * bs + c] = r[I * bs + c];
+        for (int64_t p = ptr[I]; p < ptr[I + 1]; ++p)
+            if (col[p] < I) blk_matvec_sub(bs, f + p * bb, y + (int64_t)col[p] * bs, y + I * bs);
+    }
+    for (int64_t I = 0; I < n; ++I) {
+        int64_t d = find_col(ptr, col, I, (int32_t)I);
+        blk_matvec(bs, f + d * bb, y + I * bs, z + I * bs);
+    }
+    for (int64_t I = n - 1; I >= 0; --I) {
+        for (int64_t p = ptr[I]; p < ptr[I + 1]; ++p)
+            if (col[p] > I) blk_matvec_sub(bs, f + p * bb, z + (int64_t)col[p] * bs, z + I * bs);
+    }
+    free(y);
+}
+
+/* ILU0 form of the same apply (Algorithm 7 with the division inside the
+ * row): f holds L and U (not the ILDU0 form); backward step
+ * z_I = U_II^{-1} (y_I - sum_{K>I} U_IK z_K).  Used to pin the ILDU0 pass. */
+int o_apply_ilu0(int64_t n, int bs, const int32_t *ptr, const int32_t *col, const double *f,
+                 const double *r, double *z) {
+    int bb = bs * bs;
+    double inv[9], t[3];
+    double *y = (double *)malloc(sizeof(double) * (size_t)(n * bs));
+    for (int64_t I = 0; I < n; ++I) {
+        for (int c = 0; c < bs; ++c) y[I * bs + c] = r[I * bs + c];
+        for (int64_t p = ptr[I]; p < ptr[I + 1]; ++p)
+            if (col[p] < I) blk_matvec_sub(bs, f + p * bb, y + (int64_t)col[p] * bs, y + I * bs);
+    }
+    for (int64_t I = n - 1; I >= 0; --I) {
+        for (int c = 0; c < bs; ++c) t[c] = y[I * bs + c];
+        int64_t d = -1;
+        for (int64_t p = ptr[I]; p < ptr[I + 1]; ++p) {
+            if (col[p] > I) blk_matvec_sub(bs, f + p * bb, z + (int64_t)col[p] * bs, t);
+            if (col[p] == I) d = p;
+        }
+        if (d < 0 || o_block_inverse(bs, f + d * bb, inv) != O_OK) { free(y); return O_EZEROPIVOT; }
+        blk_matvec(bs, inv, t, z + I * bs);
+    }
+    free(y);
+    return O_OK;
+}
+
+/* Adjoint apply z = M^{-T} r, with M^{-T} = L^{-T} inv_D^T Uhat^{-T}:
+ * solve Uhat^T a = r (unit lower: a_I = r_I - sum_{K<I} Uhat_KI^T a_K,
+ * I ascending), then w = inv_D^T a, then solve L^T z = w (unit upper:
+ * z_I = w_I - sum_{J>I} L_JI^T z_J, I descending).  The stored rows are
+ * read column-wise: once a_K (resp. z_J) is final it is pushed into the
+ * rows it couples. */
+void o_apply_transpose(int64_t n, int bs, const int32_t *ptr, const int32_t *col,
+                       const double *f, const double *r, double *z) {
+    int bb = bs * bs;
+    double *a = (double *)malloc(sizeof(double) * (size_t)(n * bs));
+    memcpy(a, r, sizeof(double) * (size_t)(n * bs));
+    /* Uhat^T a = r: a_I is final once every row K < I has pushed its
+     * contribution; push a_K into the rows I > K that Uhat_KI couples. */
+    for (int64_t K = 0; K < n; ++K) {
+        for (int64_t p = ptr[K]; p < ptr[K + 1]; ++p) {
+            int32_t I = col[p];
+            if (I <= K) continue;
+            for (int c = 0; c < bs; ++c) {
+                double s = 0.0;
+                for (int d = 0; d < bs; ++d) s += f[p * bb + d * bs + c] * a[K * bs + d];
+                a[(int64_t)I * bs + c] -= s;
+            }
+        }
+    }
+    for (int64_t I = 0; I < n; ++I) {
+        int64_t d = find_col(ptr, col, I, (int32_t)I);
+        for (int c = 0; c < bs; ++c) {
+            double s = 0.0;
+            for (int e = 0; e < bs; ++e) s += f[d * bb + e * bs + c] * a[I * bs + e];
+            z[I * bs + c] = s;
+        }
+    }
+    /* L^T z = w: backward, push z_J into rows I < J coupled by L_JI */
+    for (int64_t J = n - 1; J >= 0; --J) {
+        for (int64_t p = ptr[J]; p < ptr[J + 1]; ++p) {
+            int32_t I = col[p];
+            if (I >= J) continue;
+            for (int c = 0; c < bs; ++c) {
+                double s = 0.0;
+                for (int d = 0; d < bs; ++d) s += f[p * bb + d * bs + c] * z[J * bs + d];
+                z[(int64_t)I * bs + c] -= s;
+            }
+        }
+    }
+    free(a);
+}
+
+/* ------------------------------------------------------------------ */
+/* BSR sparse matrix-vector product y = A x                            */
+/* ------------------------------------------------------------------ */
+void o_spmv(int64_t n, int bs, const int32_t *ptr, const int32_t *col, const double *val,
+            const double *x, double *y) {
+    int bb = bs * bs;
+    for (int64_t I = 0; I < n; ++I) {
+        for (int c = 0; c < bs; ++c) y[I * bs + c] = 0.0;
+        for (int64_t p = ptr[I]; p < ptr[I + 1]; ++p)
+            for (int c = 0; c < bs; ++c) {
+                double s = 0.0;
+                for (int d = 0; d < bs; ++d) s += val[p * bb + c * bs + d] * x[(int64_t)col[p] * bs + d];
+                y[I * bs + c] += s;
+            }
+    }
+}
+
+static double dot(int64_t m, const double *a, const double *b) {
+    double s = 0.0;
+    for (int64_t i = 0; i < m; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/* ------------------------------------------------------------------ */
+/* Section 2, Algorithm 1 with K1 = I and K2 = M (right               */
+/* preconditioning), relative stop ||r|| <= rtol ||b||, x0 given.      */
+/* Because x = K2^{-1} y and K2^{-1} is linear, x is advanced by       */
+/* alpha*M^{-1}p + omega*M^{-1}s with the same preconditioned vectors  */
+/* that enter A; an exit after the half step (||s|| small) is added.   */
+/* history (may be NULL) receives ||r_j||/||b|| after each iteration   */
+/* (maxit+1 entries, entry 0 = initial).                               */
+/* iters counts loop trips started.                                    */
+/* ------------------------------------------------------------------ */
+int o_bicgstab(int64_t n, int bs, const int32_t *aptr, const int32_t *acol, const double *aval,
+               const int32_t *fptr, const int32_t *fcol, const double *fval,
+               const double *b, double *x, double rtol, int32_t maxit,
+               int32_t *iters, double *relres, double *history) {
+    int64_t m = n * bs;
+    size_t sz = sizeof(double) * (size_t)m;
+    double *r = malloc(sz), *r0 = malloc(sz), *p = malloc(sz), *ph = malloc(sz), *v = malloc(sz);
+    double *s = malloc(sz), *sh = malloc(sz), *t = malloc(sz);
+    int status = O_ENOCONV;
+    double bnorm = sqrt(dot(m, b, b));
+    if (bnorm == 0.0) bnorm = 1.0;
+    o_spmv(n, bs, aptr, acol, aval, x, t);
+    for (int64_t i = 0; i < m; ++i) { r[i] = b[i] - t[i]; r0[i] = r[i]; p[i] = r[i]; }
+    double rho = dot(m, r0, r);
+    double res = sqrt(dot(m, r, r)) / bnorm;
+    if (history) history[0] = res;
+    int32_t it = 0;
+    if (res <= rtol) { status = O_OK; goto done; }
+    for (it = 1; it <= maxit; ++it) {
+        o_apply(n, bs, fptr, fcol, fval, p, ph);
+        o_spmv(n, bs, aptr, acol, aval, ph, v);
+        double r0v = dot(m, r0, v);
+        if (r0v == 0.0 || !isfinite(r0v) || rho == 0.0) { status = O_EBREAKDOWN; break; }
+        double alpha = rho / r0v;
+        for (int64_t i = 0; i < m; ++i) s[i] = r[i] - alpha * v[i];
+        double snorm = sqrt(dot(m, s, s)) / bnorm;
+        if (snorm <= rtol) {
+            for (int64_t i = 0; i < m; ++i) x[i] += alpha * ph[i];
+            res = snorm;
+            if (history) history[it] = res;
+            status = O_OK;
+            break;
+        }
+        o_apply(n, bs, fptr, fcol, fval, s, sh);
+        o_spmv(n, bs, aptr, acol, aval, sh, t);
+        double ts = dot(m, t, s), tt = dot(m, t, t);
+        if (tt == 0.0 || !isfinite(tt)) { status = O_EBREAKDOWN; break; }
+        double omega = ts / tt;
+        for (int64_t i = 0; i < m; ++i) {
+            x[i] += alpha * ph[i] + omega * sh[i];
+            r[i] = s[i] - omega * t[i];
+        }
+        res = sqrt(dot(m, r, r)) / bnorm;
+        if (history) history[it] = res;
+        if (!isfinite(res)) { status = O_EBREAKDOWN; break; }
+        if (res <= rtol) { status = O_OK; break; }
+        if (omega == 0.0) { status = O_EBREAKDOWN; break; }
+        double rho_new = dot(m, r0, r);
+        double beta = (rho_new / rho) * (alpha / omega);
+        rho = rho_new;
+        for (int64_t i = 0; i < m; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+    }
+    if (it > maxit) it = maxit;
+done:
+    *iters = it;
+    *relres = res;
+    free(r); free(r0); free(p); free(ph); free(v); free(s); free(sh); free(t);
+    return status;
+}
