@@ -1,0 +1,219 @@
+/*
+ * ddilu: domain-decomposed ILU0 preconditioning on MI355X (gfx950).
+ *
+ * C ABI of the GPU library.  It follows the problem statement of
+ * "Mapping Sparse Triangular Solves to GPUs via Fine-grained Domain
+ * Decomposition" (arXiv 2508.04917):
+ *   - Section 3, Algorithm 2: geometric-cut partition of an nx*ny*nz grid;
+ *   - Section 3.1, Algorithm 3: row permutation and reorder of the matrix;
+ *   - Section 3.2: removal of the inter-subdomain couplings;
+ *   - Section 4.2.1 / 4.2.2: per-subdomain level sets (the DAG);
+ *   - Section 4.3, Algorithm 5: ILU0 and the ILDU0 post-pass;
+ *   - Sections 4.2.2, 4.4: the fused lower solve, diagonal scaling and upper
+ *     solve, one workgroup per subdomain with the vector held in LDS;
+ *   - Section 2, Algorithm 1: preconditioned BiCGSTAB.
+ *
+ * Conventions for every entry point:
+ *   - Matrices are block sparse row (BSR) with square blocks of size bs
+ *     (1 or 3), each block stored row-major: brow_ptr int32[n+1],
+ *     bcol int32[nnzb], val double[nnzb*bs*bs].  Blocks of a row may come in
+ *     any column order.  Cell (block row) g of the grid is
+ *     g = i + nx*(j + ny*k).
+ *   - "device" pointers are HIP device allocations owned by the caller; the
+ *     library never frees them.  "host" pointers are ordinary memory.
+ *   - Every device operation is enqueued on the caller's stream
+ *     (hip_stream, a hipStream_t passed as void*; NULL = the null stream).
+ *     Calls that must look at a result on the host (setup status,
+ *     convergence) synchronise that stream; the others do not.
+ *   - Return value: DD_OK (0) or a negative dd_status code; a message is
+ *     available from dd_last_error(handle) (or dd_last_error(NULL) for
+ *     errors raised before a handle exists).
+ *   - A handle is not thread-safe; use one handle per host thread.
+ */
+#ifndef DDILU_H
+#define DDILU_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dd_ctx *dd_handle;
+
+enum dd_status {
+    DD_OK = 0,
+    DD_EINVAL = -1,      /* bad argument or unsupported input               */
+    DD_ENOTDIV = -2,     /* grid not divisible by the subdomain extents     */
+    DD_ELDS = -3,        /* subdomain vector does not fit the LDS budget    */
+    DD_EZEROPIVOT = -4,  /* singular or ill-conditioned pivot block         */
+    DD_EBREAKDOWN = -5,  /* BiCGSTAB breakdown (zero denominator, NaN/Inf)  */
+    DD_ENOCONV = -6,     /* BiCGSTAB reached maxit                          */
+    DD_EHIP = -7,        /* a HIP runtime call failed                       */
+    DD_ENOMEM = -8,      /* device allocation failed                        */
+    DD_ESTATE = -9       /* call out of order (e.g. apply before factor)    */
+};
+
+enum dd_precision {
+    DD_FP64 = 0, /* factors, LDS vector and trisolve arithmetic in FP64       */
+    DD_FP32 = 1  /* factors, LDS vector and trisolve arithmetic in FP32;
+                    apply input and output stay FP64                         */
+};
+
+/* Partition request.  sx = sy = sz = 0 selects the automatic rule of
+ * dd_auto_subdims(); lds_budget_bytes = 0 uses the device's maximum LDS
+ * per workgroup; n_cu = 0 uses the device's compute-unit count. */
+typedef struct {
+    int32_t nx, ny, nz;        /* grid extents in cells (block rows)     */
+    int32_t bs;                /* block size: 1 or 3                     */
+    int32_t sx, sy, sz;        /* subdomain extents, or 0,0,0 for auto   */
+    int32_t n_cu;              /* compute units, or 0                    */
+    int64_t lds_budget_bytes;  /* LDS per workgroup, or 0                */
+} dd_partition_desc;
+
+/* Sizes of a handle's problem and setup products. */
+typedef struct {
+    int64_t n;                 /* block rows                              */
+    int64_t nnzb;              /* blocks of the full reordered matrix A   */
+    int64_t nnzb_dropped;      /* blocks of A~ after the drop (0 before
+                                  ilu0_factor)                            */
+    int64_t nnzb_lower;        /* strictly lower blocks of A~ (L)         */
+    int64_t nnzb_upper;        /* strictly upper blocks of A~ (Uhat)      */
+    int32_t bs, S, nsub;       /* block size, rows per subdomain, count   */
+    int32_t sx, sy, sz;        /* subdomain extents in use                */
+    int32_t level_ptr_len[2];  /* entries of level_ptr for L (0), U (1)   */
+    int32_t max_levels[2];     /* most levels of any subdomain, L and U   */
+    int32_t factored;          /* 1 after a successful ilu0_factor        */
+    int32_t precision;         /* dd_precision of dd_trsv_apply           */
+    int64_t apply_bytes;       /* algorithmic bytes one dd_trsv_apply moves
+                                  (factor blocks + int32 columns, inv_D,
+                                  int32 row pointers of L and Uhat, FP64 r
+                                  in and z out)                           */
+    int64_t lds_bytes;         /* LDS per workgroup used by the apply     */
+} dd_info;
+
+/* Result of bicgstab_solve. */
+typedef struct {
+    int32_t iters;             /* BiCGSTAB iterations started             */
+    int32_t status;            /* DD_OK, DD_EBREAKDOWN or DD_ENOCONV      */
+    double rel_res;            /* recurrence ||r||/||b|| at exit          */
+    double rel_res_true;       /* ||b - A x||/||b|| recomputed at exit    */
+    double solve_seconds;      /* wall time of the solve on the stream    */
+    int32_t applies;           /* preconditioner applies that did work    */
+    int32_t pad;
+    double apply_seconds;      /* summed duration of those applies (event
+                                  pairs on the stream; 0 unless profiling
+                                  was switched on with dd_set_profiling)  */
+} dd_solve_info;
+
+/* Automatic subdomain extents (host only, no device access).
+ * Section 4: a subdomain is sized so that its FP64 vector (S*bs*8 bytes)
+ * fits in one workgroup's LDS.  Among divisor triples sx|nx, sy|ny, sz|nz
+ * fitting lds_budget_bytes, keep those giving at least n_cu subdomains if
+ * any do; then take the largest S, then the smallest surface
+ * sx*sy + sy*sz + sz*sx, then the largest sz, then the largest sy.
+ * out: host int32[3].  Returns DD_ELDS when no box fits. */
+int dd_auto_subdims(int32_t nx, int32_t ny, int32_t nz, int32_t bs,
+                    int64_t lds_budget_bytes, int32_t n_cu, int32_t *out);
+
+/* Device limits used by the automatic rule: compute units and maximum LDS
+ * bytes per workgroup of the current device.  Host pointers. */
+int dd_device_caps(int32_t *n_cu, int64_t *lds_per_workgroup);
+
+/* Section 3 (Algorithm 2) and Section 3.1 (Algorithm 3): label every cell
+ * with its subdomain, renumber cells subdomain by subdomain (stable in the
+ * old index, i.e. local lexicographic order inside each box), and build the
+ * reordered matrix P A P^T with each row's blocks sorted by column.  The
+ * full reordered matrix is kept for SpMV (Section 3.2).
+ * brow_ptr, bcol, val: device, the matrix in grid order, nnzb blocks,
+ * at most 64 blocks per row.  The library copies what it needs; the caller
+ * may free them after the call returns.
+ * out: host, receives a new handle (release with dd_destroy). */
+int dd_partition(const dd_partition_desc *desc, const int32_t *brow_ptr,
+                 const int32_t *bcol, const double *val, int64_t nnzb,
+                 void *hip_stream, dd_handle *out);
+
+/* Sizes of the handle's products (host struct). */
+int dd_get_info(dd_handle h, dd_info *info);
+
+/* Copies of the partition (device int32[n] each, any may be NULL):
+ * part_id in grid order, new2old[i] = grid cell of reordered row i,
+ * old2new[g] = reordered row of grid cell g. */
+int dd_get_partition(dd_handle h, int32_t *part_id, int32_t *new2old,
+                     int32_t *old2new, void *hip_stream);
+
+/* Copy of the reordered full matrix (device; ptr int32[n+1], col
+ * int32[nnzb], val double[nnzb*bs*bs]; any may be NULL). */
+int dd_get_reordered(dd_handle h, int32_t *ptr, int32_t *col, double *val,
+                     void *hip_stream);
+
+/* Section 3.2 drop, Section 4.2.1 level sets, Section 4.3 block ILU0
+ * (IKJ order, level-scheduled inside each subdomain) and ILDU0 post-pass;
+ * then packs the factors in the streaming layout of the apply.
+ * precision: dd_precision the apply will use (FP32 also keeps the FP64
+ * factors for dd_get_factors).  Synchronises the stream; returns
+ * DD_EZEROPIVOT if a pivot block is singular or has 1-norm condition
+ * number above 1e14 (the message names the block row). */
+int ilu0_factor(dd_handle h, int32_t precision, void *hip_stream);
+
+/* Choose the apply precision after factoring (DD_FP32 builds the FP32
+ * copies on first use). */
+int dd_set_precision(dd_handle h, int32_t precision, void *hip_stream);
+
+/* Level sets (Section 4.2.2 explicit DAG).  which = 0: lower factor, 1:
+ * upper factor.  Device buffers: nlev int32[nsub] levels per subdomain;
+ * level_ptr int32[level_ptr_len[which]] holding nlev[s]+1 offsets per
+ * subdomain (relative to the subdomain's first row), concatenated over
+ * subdomains; level_rows int32[n]: per subdomain, its S local row indices
+ * grouped by level, ascending within a level.  Any pointer may be NULL. */
+int dd_get_levels(dd_handle h, int32_t which, int32_t *nlev, int32_t *level_ptr,
+                  int32_t *level_rows, void *hip_stream);
+
+/* The dropped pattern A~ and its ILDU0 factors in one array (device):
+ * ptr int32[n+1], col int32[nnzb_dropped]; f double[nnzb_dropped*bs*bs]
+ * holds L in the strictly lower blocks, inv_D = U_II^{-1} in the diagonal
+ * blocks and Uhat = inv_D U in the strictly upper blocks.  Any may be NULL. */
+int dd_get_factors(dd_handle h, int32_t *ptr, int32_t *col, double *f,
+                   void *hip_stream);
+
+/* Sections 4.2.2 and 4.4: z = M_DD^{-1} r with M_DD = L D Uhat of A~, one
+ * workgroup per subdomain, the subdomain's vector resident in LDS:
+ * forward y_I = r_I - sum_{J<I} L_IJ y_J, then
+ * z_I = inv_D_I y_I - sum_{K>I} Uhat_IK z_K (the scaling is fused into the
+ * upper sweep).  r, z: device double[n*bs] in REORDERED order; r != z.
+ * With a learned correction set (lic_set_params), r is first replaced by
+ * r + C r, C the per-face interface coupling.  Does not synchronise. */
+int dd_trsv_apply(dd_handle h, const double *r, double *z, void *hip_stream);
+
+/* y = A x with the full reordered matrix (device double[n*bs], reordered
+ * order, x != y).  Does not synchronise. */
+int dd_spmv(dd_handle h, const double *x, double *y, void *hip_stream);
+
+/* Section 2, Algorithm 1 with K1 = I, K2 = M_DD (right preconditioning):
+ * solves A x = b to ||r||/||b|| <= rtol on the recurrence residual (an exit
+ * after the half step when ||s||/||b|| <= rtol), at most maxit iterations.
+ * b, x: device double[n*bs] in GRID order; x holds the initial guess on
+ * entry and the solution on exit.  Krylov vectors, dot products and the
+ * stopping test are FP64 whatever the apply precision.  Synchronises.
+ * info: host, may be NULL.  Returns DD_OK, DD_EBREAKDOWN or DD_ENOCONV (x
+ * then holds the last iterate). */
+int bicgstab_solve(dd_handle h, const double *b, double *x, double rtol,
+                   int32_t maxit, void *hip_stream, dd_solve_info *info);
+
+/* Switch per-apply timing inside bicgstab_solve on (1) or off (0): a HIP
+ * event pair on the solve's stream brackets every preconditioner apply and
+ * the summed durations are reported in dd_solve_info.apply_seconds. */
+int dd_set_profiling(dd_handle h, int32_t on);
+
+/* Message of the last failed call on h (or of the last failure before a
+ * handle existed when h is NULL).  Owned by the library. */
+const char *dd_last_error(dd_handle h);
+
+/* Releases every device buffer of the handle. */
+void dd_destroy(dd_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDILU_H */

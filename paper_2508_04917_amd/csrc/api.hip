@@ -1,0 +1,451 @@
+// C ABI entry points of the ddilu library: handle lifetime, setup
+// orchestration and argument checking.  Every numerical step runs in the
+// kernels of setup.hip, apply.hip and krylov.hip.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.h"
+
+using namespace ddilu;
+
+static thread_local std::string g_err;
+
+static int set_global_error(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int dd_ctx::fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    err = buf;
+    g_err = buf;
+    return code;
+}
+
+dd_ctx::~dd_ctx() {
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    for (void *q : allocs) (void)hipFree(q);
+    if (ks_host) (void)hipHostFree(ks_host);
+}
+
+static void release(dd_ctx *h, void *q) {
+    if (!q) return;
+    auto it = std::find(h->allocs.begin(), h->allocs.end(), q);
+    if (it != h->allocs.end()) {
+        (void)hipFree(q);
+        h->allocs.erase(it);
+    }
+}
+
+#define HCHK(x)                                                                             \
+    do {                                                                                    \
+        hipError_t e_ = (x);                                                                \
+        if (e_ != hipSuccess) return h->fail(DD_EHIP, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+#define RCHK(x)              \
+    do {                     \
+        int r_ = (x);        \
+        if (r_) return r_;   \
+    } while (0)
+
+static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------- sizing
+extern "C" int dd_auto_subdims(int32_t nx, int32_t ny, int32_t nz, int32_t bs, int64_t lds_budget_bytes,
+                               int32_t n_cu, int32_t *out) {
+    if (nx <= 0 || ny <= 0 || nz <= 0 || (bs != 1 && bs != 3) || !out)
+        return set_global_error(DD_EINVAL, "dd_auto_subdims: bad arguments");
+    struct Cand {
+        int sx, sy, sz;
+    };
+    std::vector<Cand> all, full;
+    for (int sx = 1; sx <= nx; ++sx) {
+        if (nx % sx) continue;
+        for (int sy = 1; sy <= ny; ++sy) {
+            if (ny % sy) continue;
+            for (int sz = 1; sz <= nz; ++sz) {
+                if (nz % sz) continue;
+                const int64_t S = (int64_t)sx * sy * sz;
+                if (S * bs * 8 > lds_budget_bytes) continue;
+                all.push_back({sx, sy, sz});
+                const int64_t nsub = (int64_t)(nx / sx) * (ny / sy) * (nz / sz);
+                if (nsub >= n_cu) full.push_back({sx, sy, sz});
+            }
+        }
+    }
+    if (all.empty()) return set_global_error(DD_ELDS, "no subdomain box fits %lld bytes of LDS", (long long)lds_budget_bytes);
+    const std::vector<Cand> &c = full.empty() ? all : full;
+    auto better = [](const Cand &a, const Cand &b) {
+        const int64_t Sa = (int64_t)a.sx * a.sy * a.sz, Sb = (int64_t)b.sx * b.sy * b.sz;
+        if (Sa != Sb) return Sa > Sb;
+        const int64_t fa = (int64_t)a.sx * a.sy + (int64_t)a.sy * a.sz + (int64_t)a.sz * a.sx;
+        const int64_t fb = (int64_t)b.sx * b.sy + (int64_t)b.sy * b.sz + (int64_t)b.sz * b.sx;
+        if (fa != fb) return fa < fb;
+        if (a.sz != b.sz) return a.sz > b.sz;
+        return a.sy > b.sy;
+    };
+    Cand best = c[0];
+    for (const Cand &x : c)
+        if (better(x, best)) best = x;
+    out[0] = best.sx;
+    out[1] = best.sy;
+    out[2] = best.sz;
+    return DD_OK;
+}
+
+extern "C" int dd_device_caps(int32_t *n_cu, int64_t *lds_per_workgroup) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_global_error(DD_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    int cu = 0, lds = 0;
+    e = hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return set_global_error(DD_EHIP, "device attribute: %s", hipGetErrorString(e));
+    e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return set_global_error(DD_EHIP, "device attribute: %s", hipGetErrorString(e));
+    if (n_cu) *n_cu = cu;
+    if (lds_per_workgroup) *lds_per_workgroup = lds;
+    return DD_OK;
+}
+
+// -------------------------------------------------------------- partition
+extern "C" int dd_partition(const dd_partition_desc *d, const int32_t *brow_ptr, const int32_t *bcol,
+                            const double *val, int64_t nnzb, void *hip_stream, dd_handle *out) {
+    if (!d || !brow_ptr || !bcol || !val || !out) return set_global_error(DD_EINVAL, "dd_partition: null argument");
+    *out = nullptr;
+    if (d->nx <= 0 || d->ny <= 0 || d->nz <= 0) return set_global_error(DD_EINVAL, "dd_partition: empty grid");
+    if (d->bs != 1 && d->bs != 3) return set_global_error(DD_EINVAL, "dd_partition: bs must be 1 or 3");
+    const int64_t n = (int64_t)d->nx * d->ny * d->nz;
+    if (n >= (int64_t)1 << 31) return set_global_error(DD_EINVAL, "dd_partition: too many block rows");
+    if (nnzb < n || nnzb >= ((int64_t)1 << 31)) return set_global_error(DD_EINVAL, "dd_partition: bad nnzb %lld", (long long)nnzb);
+    int32_t n_cu = d->n_cu;
+    int64_t lds = d->lds_budget_bytes;
+    if (n_cu <= 0 || lds <= 0) {
+        int32_t c;
+        int64_t l;
+        int rc = dd_device_caps(&c, &l);
+        if (rc) return rc;
+        if (n_cu <= 0) n_cu = c;
+        if (lds <= 0) lds = l;
+    }
+    int32_t sub[3] = {d->sx, d->sy, d->sz};
+    if (sub[0] == 0 && sub[1] == 0 && sub[2] == 0) {
+        int rc = dd_auto_subdims(d->nx, d->ny, d->nz, d->bs, lds, n_cu, sub);
+        if (rc) return rc;
+    }
+    if (sub[0] <= 0 || sub[1] <= 0 || sub[2] <= 0) return set_global_error(DD_EINVAL, "dd_partition: bad subdomain extents");
+    if (d->nx % sub[0] || d->ny % sub[1] || d->nz % sub[2])
+        return set_global_error(DD_ENOTDIV, "grid %dx%dx%d not divisible by subdomain %dx%dx%d", d->nx, d->ny, d->nz,
+                                sub[0], sub[1], sub[2]);
+    const int64_t S = (int64_t)sub[0] * sub[1] * sub[2];
+    if (S * d->bs * 8 > lds)
+        return set_global_error(DD_ELDS, "subdomain vector of %lld bytes exceeds the LDS budget %lld",
+                                (long long)(S * d->bs * 8), (long long)lds);
+    if (S > 65535) return set_global_error(DD_EINVAL, "subdomain of %lld rows exceeds 65535", (long long)S);
+
+    dd_ctx *h = new dd_ctx();
+    h->nx = d->nx; h->ny = d->ny; h->nz = d->nz; h->bs = d->bs;
+    h->sx = sub[0]; h->sy = sub[1]; h->sz = sub[2];
+    h->S = (int32_t)S;
+    h->n = n;
+    h->nsub = (int32_t)(n / S);
+    h->nnzb = nnzb;
+    hipStream_t st = as_stream(hip_stream);
+    const int bb = h->bs * h->bs;
+    int rc = 0;
+    int32_t *len = nullptr, *src = nullptr;
+    auto bail = [&](int code) {
+        g_err = h->err;
+        delete h;
+        return code;
+    };
+    if ((rc = h->alloc(&h->status, 8))) return bail(rc);
+    h->scan_tmp_len = scan_tmp_elems(std::max<int64_t>(n, nnzb) + 1);
+    if ((rc = h->alloc(&h->scan_tmp, h->scan_tmp_len))) return bail(rc);
+    if ((rc = h->alloc(&h->part_id, n)) || (rc = h->alloc(&h->new2old, n)) || (rc = h->alloc(&h->old2new, n)) ||
+        (rc = h->alloc(&h->aptr, n + 1)) || (rc = h->alloc(&h->acol, nnzb)) ||
+        (rc = h->alloc(&h->aval, nnzb * bb)) || (rc = h->alloc(&len, n)) || (rc = h->alloc(&src, nnzb)))
+        return bail(rc);
+    int32_t init_status[8] = {0, 0x7fffffff, 0x7fffffff, 0, 0, 0, 0, 0};
+    hipError_t e;
+#define PCHK(x)                                                                   \
+    do {                                                                          \
+        e = (x);                                                                  \
+        if (e != hipSuccess) {                                                    \
+            h->fail(DD_EHIP, "%s: %s", #x, hipGetErrorString(e));                 \
+            return bail(DD_EHIP);                                                 \
+        }                                                                         \
+    } while (0)
+    PCHK(hipMemcpyAsync(h->status, init_status, sizeof(init_status), hipMemcpyHostToDevice, st));
+    PCHK(launch_partition(h, st));
+    PCHK(launch_row_len(h, brow_ptr, len, st));
+    PCHK(exclusive_scan(len, h->aptr, n, h->scan_tmp, st));
+    int32_t total = 0, status[8];
+    PCHK(hipMemcpyAsync(&total, h->aptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    PCHK(hipMemcpyAsync(status, h->status, sizeof(status), hipMemcpyDeviceToHost, st));
+    PCHK(hipStreamSynchronize(st));
+    if (status[0]) {
+        h->fail(DD_EINVAL, "a row holds more than %d blocks (or brow_ptr is not monotone)", kMaxRowBlocks);
+        return bail(DD_EINVAL);
+    }
+    if (total != nnzb) {
+        h->fail(DD_EINVAL, "brow_ptr describes %d blocks, nnzb says %lld", total, (long long)nnzb);
+        return bail(DD_EINVAL);
+    }
+    PCHK(launch_reorder_fill(h, brow_ptr, bcol, val, src, st));
+    PCHK(hipStreamSynchronize(st));
+    release(h, len);
+    release(h, src);
+    *out = h;
+    return DD_OK;
+}
+
+extern "C" int dd_get_info(dd_handle h, dd_info *info) {
+    if (!h || !info) return set_global_error(DD_EINVAL, "dd_get_info: null argument");
+    std::memset(info, 0, sizeof(*info));
+    info->n = h->n;
+    info->nnzb = h->nnzb;
+    info->nnzb_dropped = h->nnzt;
+    info->nnzb_lower = h->nlow;
+    info->nnzb_upper = h->nupp;
+    info->bs = h->bs;
+    info->S = h->S;
+    info->nsub = h->nsub;
+    info->sx = h->sx; info->sy = h->sy; info->sz = h->sz;
+    for (int w = 0; w < 2; ++w) {
+        info->level_ptr_len[w] = h->lev[w].ptr_len;
+        info->max_levels[w] = h->lev[w].max_levels;
+    }
+    info->factored = h->factored;
+    info->precision = h->precision;
+    const int64_t wsz = h->precision == DD_FP32 ? 4 : 8;
+    const int64_t bb = h->bs * h->bs;
+    info->apply_bytes = (h->nlow + h->nupp) * (bb * wsz + 4) + h->n * bb * wsz + 2 * 4 * (h->n + 1) +
+                        2 * h->n * h->bs * 8;
+    info->lds_bytes = apply_lds_bytes(h, h->precision);
+    return DD_OK;
+}
+
+extern "C" int dd_get_partition(dd_handle h, int32_t *part_id, int32_t *new2old, int32_t *old2new,
+                                void *hip_stream) {
+    if (!h) return set_global_error(DD_EINVAL, "dd_get_partition: null handle");
+    hipStream_t st = as_stream(hip_stream);
+    const size_t b = h->n * sizeof(int32_t);
+    if (part_id) HCHK(hipMemcpyAsync(part_id, h->part_id, b, hipMemcpyDeviceToDevice, st));
+    if (new2old) HCHK(hipMemcpyAsync(new2old, h->new2old, b, hipMemcpyDeviceToDevice, st));
+    if (old2new) HCHK(hipMemcpyAsync(old2new, h->old2new, b, hipMemcpyDeviceToDevice, st));
+    return DD_OK;
+}
+
+extern "C" int dd_get_reordered(dd_handle h, int32_t *ptr, int32_t *col, double *val, void *hip_stream) {
+    if (!h) return set_global_error(DD_EINVAL, "dd_get_reordered: null handle");
+    hipStream_t st = as_stream(hip_stream);
+    if (ptr) HCHK(hipMemcpyAsync(ptr, h->aptr, (h->n + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    if (col) HCHK(hipMemcpyAsync(col, h->acol, h->nnzb * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    if (val)
+        HCHK(hipMemcpyAsync(val, h->aval, h->nnzb * h->bs * h->bs * sizeof(double), hipMemcpyDeviceToDevice, st));
+    return DD_OK;
+}
+
+// ----------------------------------------------------------------- factor
+static int build_levels(dd_ctx *h, int which, hipStream_t st, int32_t *tmp_i) {
+    Levels &L = h->lev[which];
+    if (!L.lev) {
+        RCHK(h->alloc(&L.lev, h->n));
+        RCHK(h->alloc(&L.nlev, h->nsub));
+        RCHK(h->alloc(&L.off, h->nsub + 1));
+        RCHK(h->alloc(&L.rows, h->n));
+    }
+    HCHK(launch_levels(h, which, st));
+    HCHK(launch_plus_one(h->nsub, L.nlev, tmp_i, st));
+    HCHK(exclusive_scan(tmp_i, L.off, h->nsub, h->scan_tmp, st));
+    int32_t total = 0;
+    HCHK(hipMemcpyAsync(&total, L.off + h->nsub, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    if (L.ptr) release(h, L.ptr);
+    RCHK(h->alloc(&L.ptr, total));
+    L.ptr_len = total;
+    HCHK(launch_level_lists(h, which, st));
+    // host copies of the level offsets: largest level count and widest level
+    std::vector<int32_t> off(h->nsub + 1), lp(total);
+    HCHK(hipMemcpyAsync(off.data(), L.off, off.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HCHK(hipMemcpyAsync(lp.data(), L.ptr, lp.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    int maxl = 0, maxw = 0;
+    for (int s = 0; s < h->nsub; ++s) {
+        const int nl = off[s + 1] - off[s] - 1;
+        maxl = std::max(maxl, nl);
+        for (int l = 0; l < nl; ++l) maxw = std::max(maxw, lp[off[s] + l + 1] - lp[off[s] + l]);
+    }
+    L.max_levels = maxl;
+    h->max_level_width = std::max(h->max_level_width, maxw);
+    return DD_OK;
+}
+
+static int build_sweep(dd_ctx *h, int which, hipStream_t st, int32_t *cnt) {
+    Sweep &w = h->sw[which];
+    const int bb = h->bs * h->bs;
+    if (!w.prow) {
+        RCHK(h->alloc(&w.prow, h->n));
+        RCHK(h->alloc(&w.bptr, h->n + 1));
+    }
+    HCHK(launch_pack_count(h, which, cnt, st));
+    HCHK(exclusive_scan(cnt, w.bptr, h->n, h->scan_tmp, st));
+    int32_t total = 0;
+    HCHK(hipMemcpyAsync(&total, w.bptr + h->n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    if (w.bcol) { release(h, w.bcol); release(h, w.val64); w.bcol = nullptr; w.val64 = nullptr; }
+    if (w.val32) { release(h, w.val32); w.val32 = nullptr; }
+    w.nblk = total;
+    RCHK(h->alloc(&w.bcol, total));
+    RCHK(h->alloc(&w.val64, (int64_t)total * bb));
+    if (which == 1 && !w.d64) RCHK(h->alloc(&w.d64, h->n * bb));
+    HCHK(launch_pack_fill(h, which, st));
+    return DD_OK;
+}
+
+static int ensure_fp32(dd_ctx *h, hipStream_t st) {
+    const int bb = h->bs * h->bs;
+    if (h->sw[0].val32 && h->sw[1].val32 && h->sw[1].d32) return DD_OK;
+    for (int w = 0; w < 2; ++w)
+        if (!h->sw[w].val32) RCHK(h->alloc(&h->sw[w].val32, h->sw[w].nblk * bb));
+    if (!h->sw[1].d32) RCHK(h->alloc(&h->sw[1].d32, h->n * bb));
+    HCHK(launch_cast32(h, st));
+    return DD_OK;
+}
+
+extern "C" int ilu0_factor(dd_handle h, int32_t precision, void *hip_stream) {
+    if (!h) return set_global_error(DD_EINVAL, "ilu0_factor: null handle");
+    if (precision != DD_FP64 && precision != DD_FP32) return h->fail(DD_EINVAL, "ilu0_factor: bad precision");
+    hipStream_t st = as_stream(hip_stream);
+    const int bb = h->bs * h->bs;
+    h->factored = 0;
+    int32_t *tbeg = nullptr, *tlen = nullptr, *tsrc = nullptr;
+    RCHK(h->alloc(&tbeg, h->n));
+    RCHK(h->alloc(&tlen, h->n + 1));
+    int32_t init_status[8] = {0, 0x7fffffff, 0x7fffffff, 0, 0, 0, 0, 0};
+    HCHK(hipMemcpyAsync(h->status, init_status, sizeof(init_status), hipMemcpyHostToDevice, st));
+    // drop (Section 3.2)
+    HCHK(launch_drop_count(h, tbeg, tlen, st));
+    if (!h->tptr) RCHK(h->alloc(&h->tptr, h->n + 1));
+    HCHK(exclusive_scan(tlen, h->tptr, h->n, h->scan_tmp, st));
+    int32_t total = 0, status[8];
+    HCHK(hipMemcpyAsync(&total, h->tptr + h->n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HCHK(hipMemcpyAsync(status, h->status, sizeof(status), hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    if (status[1] != 0x7fffffff) {
+        release(h, tbeg); release(h, tlen);
+        return h->fail(DD_EZEROPIVOT, "block row %d has no diagonal block", status[1]);
+    }
+    h->nnzt = total;
+    h->nlow = h->nupp = (total - h->n) / 2;  // refined below from the sweeps
+    if (h->tcol) { release(h, h->tcol); release(h, h->lu); }
+    RCHK(h->alloc(&h->tcol, total));
+    RCHK(h->alloc(&h->lu, (int64_t)total * bb));
+    if (!h->tdiag) RCHK(h->alloc(&h->tdiag, h->n));
+    if (!h->invd) RCHK(h->alloc(&h->invd, h->n * bb));
+    RCHK(h->alloc(&tsrc, total));
+    HCHK(launch_drop_rows(h, tbeg, tsrc, st));
+    // level sets (Section 4.2.1) for both factors
+    h->max_level_width = 0;
+    RCHK(build_levels(h, 0, st, tlen));
+    RCHK(build_levels(h, 1, st, tlen));
+    // block ILU0 (Algorithm 5), level-scheduled per subdomain
+    HCHK(launch_bilu0(h, st));
+    HCHK(hipMemcpyAsync(status, h->status, sizeof(status), hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    if (status[2] != 0x7fffffff) {
+        release(h, tbeg); release(h, tlen); release(h, tsrc);
+        return h->fail(DD_EZEROPIVOT, "singular or ill-conditioned pivot block at reordered block row %d", status[2]);
+    }
+    // ILDU0 post-pass folded into the packing of the two sweeps
+    RCHK(build_sweep(h, 0, st, tlen));
+    RCHK(build_sweep(h, 1, st, tlen));
+    h->nlow = h->sw[0].nblk;
+    h->nupp = h->sw[1].nblk;
+    h->precision = precision;
+    if (precision == DD_FP32) RCHK(ensure_fp32(h, st));
+    HCHK(hipStreamSynchronize(st));
+    release(h, tbeg);
+    release(h, tlen);
+    release(h, tsrc);
+    h->factored = 1;
+    return DD_OK;
+}
+
+extern "C" int dd_set_precision(dd_handle h, int32_t precision, void *hip_stream) {
+    if (!h) return set_global_error(DD_EINVAL, "dd_set_precision: null handle");
+    if (!h->factored) return h->fail(DD_ESTATE, "dd_set_precision before ilu0_factor");
+    if (precision != DD_FP64 && precision != DD_FP32) return h->fail(DD_EINVAL, "bad precision");
+    if (precision == DD_FP32) RCHK(ensure_fp32(h, as_stream(hip_stream)));
+    h->precision = precision;
+    return DD_OK;
+}
+
+extern "C" int dd_get_levels(dd_handle h, int32_t which, int32_t *nlev, int32_t *level_ptr, int32_t *level_rows,
+                             void *hip_stream) {
+    if (!h) return set_global_error(DD_EINVAL, "dd_get_levels: null handle");
+    if (which != 0 && which != 1) return h->fail(DD_EINVAL, "dd_get_levels: which must be 0 or 1");
+    if (!h->factored) return h->fail(DD_ESTATE, "dd_get_levels before ilu0_factor");
+    hipStream_t st = as_stream(hip_stream);
+    const Levels &L = h->lev[which];
+    if (nlev) HCHK(hipMemcpyAsync(nlev, L.nlev, h->nsub * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    if (level_ptr) HCHK(hipMemcpyAsync(level_ptr, L.ptr, L.ptr_len * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    if (level_rows) HCHK(hipMemcpyAsync(level_rows, L.rows, h->n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    return DD_OK;
+}
+
+extern "C" int dd_get_factors(dd_handle h, int32_t *ptr, int32_t *col, double *f, void *hip_stream) {
+    if (!h) return set_global_error(DD_EINVAL, "dd_get_factors: null handle");
+    if (!h->factored) return h->fail(DD_ESTATE, "dd_get_factors before ilu0_factor");
+    hipStream_t st = as_stream(hip_stream);
+    if (ptr) HCHK(hipMemcpyAsync(ptr, h->tptr, (h->n + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    if (col) HCHK(hipMemcpyAsync(col, h->tcol, h->nnzt * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    if (f) HCHK(launch_export_factors(h, f, st));
+    return DD_OK;
+}
+
+// ------------------------------------------------------------------ apply
+extern "C" int dd_trsv_apply(dd_handle h, const double *r, double *z, void *hip_stream) {
+    if (!h) return set_global_error(DD_EINVAL, "dd_trsv_apply: null handle");
+    if (!h->factored) return h->fail(DD_ESTATE, "dd_trsv_apply before ilu0_factor");
+    if (!r || !z || r == z) return h->fail(DD_EINVAL, "dd_trsv_apply: r and z must be distinct device buffers");
+    HCHK(launch_apply(h, r, z, nullptr, as_stream(hip_stream)));
+    return DD_OK;
+}
+
+extern "C" int dd_spmv(dd_handle h, const double *x, double *y, void *hip_stream) {
+    if (!h) return set_global_error(DD_EINVAL, "dd_spmv: null handle");
+    if (!x || !y || x == y) return h->fail(DD_EINVAL, "dd_spmv: x and y must be distinct device buffers");
+    HCHK(launch_spmv(h, x, y, as_stream(hip_stream)));
+    return DD_OK;
+}
+
+extern "C" int bicgstab_solve(dd_handle h, const double *b, double *x, double rtol, int32_t maxit, void *hip_stream,
+                              dd_solve_info *info) {
+    if (!h) return set_global_error(DD_EINVAL, "bicgstab_solve: null handle");
+    if (!h->factored) return h->fail(DD_ESTATE, "bicgstab_solve before ilu0_factor");
+    if (!b || !x || b == x) return h->fail(DD_EINVAL, "bicgstab_solve: b and x must be distinct device buffers");
+    if (!(rtol > 0.0) || maxit < 0) return h->fail(DD_EINVAL, "bicgstab_solve: bad rtol or maxit");
+    return bicgstab_run(h, b, x, rtol, maxit, as_stream(hip_stream), info);
+}
+
+extern "C" int dd_set_profiling(dd_handle h, int32_t on) {
+    if (!h) return set_global_error(DD_EINVAL, "dd_set_profiling: null handle");
+    h->profile = on ? 1 : 0;
+    return DD_OK;
+}
+
+extern "C" const char *dd_last_error(dd_handle h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+extern "C" void dd_destroy(dd_handle h) { delete h; }

@@ -1,0 +1,149 @@
+// Internal declarations of the ddilu GPU library (gfx950 / CDNA4).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ddilu.h"
+
+namespace ddilu {
+
+constexpr int kMaxRowBlocks = 64;   // blocks per row accepted by the reorder
+constexpr int kWave = 64;           // CDNA wavefront width
+
+// Streaming layout of one triangular sweep.  Positions are the rows of each
+// subdomain in sweep order (level by level, ascending local row inside a
+// level); subdomain s owns positions [s*S, (s+1)*S).  Everything a sweep
+// reads is laid out in that order so one workgroup streams its factor data
+// front to back.
+struct Sweep {
+    uint16_t *prow = nullptr;   // [n] local row of each position
+    int32_t *bptr = nullptr;    // [n+1] first block of each position
+    uint16_t *bcol = nullptr;   // [nblk] local column of each block
+    double *val64 = nullptr;    // [nblk*bb] L blocks (lower) or Uhat (upper)
+    float *val32 = nullptr;     // FP32 copy (built on demand)
+    double *d64 = nullptr;      // upper only: inv_D per position [n*bb]
+    float *d32 = nullptr;
+    int64_t nblk = 0;
+};
+
+// Level sets of one factor, per subdomain.
+struct Levels {
+    int32_t *lev = nullptr;     // [n] level of each row (reordered numbering)
+    int32_t *nlev = nullptr;    // [nsub]
+    int32_t *off = nullptr;     // [nsub+1] start of each subdomain in ptr
+    int32_t *ptr = nullptr;     // [ptr_len] level offsets relative to the subdomain
+    int32_t *rows = nullptr;    // [n] local rows grouped by level
+    int32_t ptr_len = 0;
+    int32_t max_levels = 0;
+};
+
+// Device scalars of one BiCGSTAB run (all FP64 except the control words).
+struct KrylovScalars {
+    double rho, alpha, omega, beta;
+    double bnorm, rnorm, snorm;
+    double tol;                  // rtol * ||b||
+    int32_t state;               // 0 running, 1 converged, 2 half-step exit pending,
+                                 // -5 breakdown, -6 no convergence
+    int32_t iters;
+    int32_t maxit;
+    int32_t half;                // 1 when the solve stopped after a half step
+};
+
+}  // namespace ddilu
+
+struct dd_ctx {
+    // problem and partition
+    int32_t nx = 0, ny = 0, nz = 0, bs = 0;
+    int32_t sx = 0, sy = 0, sz = 0;
+    int32_t S = 0, nsub = 0;
+    int64_t n = 0, nnzb = 0;
+    int32_t *part_id = nullptr, *new2old = nullptr, *old2new = nullptr;
+    // full reordered matrix
+    int32_t *aptr = nullptr, *acol = nullptr;
+    double *aval = nullptr;
+    // dropped pattern and factors
+    int64_t nnzt = 0, nlow = 0, nupp = 0;
+    int32_t *tptr = nullptr, *tcol = nullptr, *tdiag = nullptr;
+    double *lu = nullptr;       // L\U in the dropped pattern
+    double *invd = nullptr;     // [n*bb] inv(U_II), reordered row order
+    ddilu::Levels lev[2];
+    ddilu::Sweep sw[2];
+    int32_t factored = 0;
+    int32_t precision = DD_FP64;
+    int32_t max_level_width = 0;  // widest level of any subdomain, L or U
+    int32_t profile = 0;          // time every apply inside bicgstab_solve
+    std::vector<hipEvent_t> events;
+    // scratch
+    int32_t *status = nullptr;  // [4] device status words
+    int32_t *scan_tmp = nullptr;
+    int64_t scan_tmp_len = 0;
+    // Krylov workspace (allocated on first solve)
+    double *kv = nullptr;       // 9 vectors of n*bs
+    double *partials = nullptr; // [kMaxPartials * 3]
+    ddilu::KrylovScalars *ks = nullptr;
+    ddilu::KrylovScalars *ks_host = nullptr;  // pinned
+    std::vector<void *> allocs;
+    std::string err;
+
+    int fail(int code, const char *fmt, ...);
+    // hipMalloc of count elements, recorded for dd_destroy
+    template <typename T>
+    int alloc(T **p, int64_t count) {
+        void *q = nullptr;
+        const size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+        hipError_t e = hipMalloc(&q, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(DD_ENOMEM, "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+        }
+        allocs.push_back(q);
+        *p = static_cast<T *>(q);
+        return DD_OK;
+    }
+    ~dd_ctx();
+};
+
+namespace ddilu {
+
+// exclusive scan of int32 counts: out[0] = 0, out[i+1] = out[i] + in[i];
+// returns the total in *total (synchronises the stream).  tmp: scratch of
+// at least scan_tmp_elems(n) int32.
+int64_t scan_tmp_elems(int64_t n);
+hipError_t exclusive_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *tmp,
+                          hipStream_t st);
+
+}  // namespace ddilu
+
+// kernel launchers implemented in the .hip files
+namespace ddilu {
+hipError_t launch_partition(dd_ctx *h, hipStream_t st);
+hipError_t launch_row_len(dd_ctx *h, const int32_t *ptr, int32_t *len, hipStream_t st);
+hipError_t launch_reorder_fill(dd_ctx *h, const int32_t *ptr, const int32_t *col,
+                               const double *val, int32_t *src, hipStream_t st);
+hipError_t launch_drop_count(dd_ctx *h, int32_t *tbeg, int32_t *tlen, hipStream_t st);
+hipError_t launch_drop_rows(dd_ctx *h, const int32_t *tbeg, int32_t *tsrc, hipStream_t st);
+hipError_t launch_levels(dd_ctx *h, int which, hipStream_t st);
+hipError_t launch_plus_one(int64_t m, const int32_t *in, int32_t *out, hipStream_t st);
+hipError_t launch_level_lists(dd_ctx *h, int which, hipStream_t st);
+hipError_t launch_bilu0(dd_ctx *h, hipStream_t st);
+hipError_t launch_pack_count(dd_ctx *h, int which, int32_t *cnt, hipStream_t st);
+hipError_t launch_pack_fill(dd_ctx *h, int which, hipStream_t st);
+hipError_t launch_cast32(dd_ctx *h, hipStream_t st);
+hipError_t launch_export_factors(dd_ctx *h, double *f, hipStream_t st);
+
+hipError_t launch_apply(dd_ctx *h, const double *r, double *z, const int32_t *state,
+                        hipStream_t st);
+int apply_lds_bytes(const dd_ctx *h, int precision);
+
+// Krylov
+hipError_t launch_spmv(dd_ctx *h, const double *x, double *y, hipStream_t st);
+hipError_t launch_permute(int64_t n, int bs, const int32_t *map, const double *in, double *out,
+                          hipStream_t st);
+int bicgstab_run(dd_ctx *h, const double *b, double *x, double rtol, int32_t maxit,
+                 hipStream_t st, dd_solve_info *info);
+}  // namespace ddilu

@@ -1,0 +1,448 @@
+// BSR SpMV, fused FP64 vector kernels and the BiCGSTAB driver
+// (Section 2, Algorithm 1, right preconditioned: K1 = I, K2 = M_DD).
+//
+// Every dot product is reduced deterministically: each workgroup of a fixed
+// grid writes one partial sum (fixed in-wave shuffle tree, then waves in
+// order), and a one-workgroup kernel sums the partials in a fixed order and
+// performs the scalar step of the algorithm on the device.  No floating
+// point atomics, so a solve is bit-reproducible and its iteration count does
+// not vary from run to run.
+//
+// The scalars (rho, alpha, omega, beta, norms) and the state word stay on the
+// device.  Every kernel of an iteration first reads the state word and
+// returns at once when the solve has finished, so the host enqueues a batch
+// of iterations and only synchronises once per batch.
+#include "internal.h"
+
+namespace ddilu {
+
+constexpr int kRedT = 256;        // threads of reducing kernels
+constexpr int kMaxGrid = 2048;    // workgroups of grid-stride vector kernels
+constexpr int kStride = 8;        // partial-sum slots per reduction (2048 each)
+
+enum : int32_t { ST_RUN = 0, ST_CONV = 1, ST_HALF = 2 };
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+    return v;
+}
+
+// Sums NV values over the workgroup in a fixed order and writes them to
+// out[k*kMaxGrid + blockIdx.x].
+template <int NV>
+__device__ __forceinline__ void block_partials(double (&v)[NV], double *out) {
+    __shared__ double sh[NV][16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double t = wave_sum(v[k]);
+        if (lane == 0) sh[k][w] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double t = 0.0;
+            for (int i = 0; i < nw; ++i) t += sh[k][i];
+            out[k * kMaxGrid + blockIdx.x] = t;
+        }
+    }
+}
+
+// --------------------------------------------------------------- SpMV
+// BS lanes of one wavefront per block row, lane c computes component c.
+template <int BS>
+__device__ __forceinline__ double bsr_row(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                          const double *__restrict__ val, const double *__restrict__ x,
+                                          int64_t row, int c) {
+    constexpr int BB = BS * BS;
+    double acc = 0.0;
+    const int32_t b1 = ptr[row + 1];
+    for (int32_t b = ptr[row]; b < b1; ++b) {
+        const int64_t J = col[b];
+        const double *blk = val + (int64_t)b * BB + c * BS;
+#pragma unroll
+        for (int d = 0; d < BS; ++d) acc += blk[d] * x[J * BS + d];
+    }
+    return acc;
+}
+
+template <int BS>
+__global__ __launch_bounds__(kRedT) void k_spmv(int64_t n, const int32_t *__restrict__ ptr,
+                                               const int32_t *__restrict__ col, const double *__restrict__ val,
+                                               const double *__restrict__ x, double *__restrict__ y) {
+    constexpr int RPW = kWave / BS;
+    const int lane = threadIdx.x & 63;
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int c = lane % BS;
+    const int64_t row = gw * RPW + lane / BS;
+    if (lane / BS < RPW && row < n) y[row * BS + c] = bsr_row<BS>(ptr, col, val, x, row, c);
+}
+
+hipError_t launch_spmv(dd_ctx *h, const double *x, double *y, hipStream_t st) {
+    const int rpb = (kWave / h->bs) * (kRedT / kWave);
+    const unsigned g = (unsigned)((h->n + rpb - 1) / rpb);
+    if (h->bs == 3)
+        k_spmv<3><<<g, kRedT, 0, st>>>(h->n, h->aptr, h->acol, h->aval, x, y);
+    else
+        k_spmv<1><<<g, kRedT, 0, st>>>(h->n, h->aptr, h->acol, h->aval, x, y);
+    return hipGetLastError();
+}
+
+// y = A x, grid-stride over wavefront row groups; partials of w.y (and y.y
+// when NV == 2, or w2.y ... see mode).  mode 0: v = A p^, dot r0.v.
+// mode 1: t = A s^, dots t.s and t.t.  mode 2: t = A x, r = b - t (init),
+// dots r.r and b.b.  mode 3: t = A x, dot (b-t).(b-t) (true residual).
+template <int BS, int MODE>
+__global__ __launch_bounds__(kRedT) void k_spmv_dots(int64_t n, const int32_t *__restrict__ ptr,
+                                                    const int32_t *__restrict__ col,
+                                                    const double *__restrict__ val, const double *__restrict__ x,
+                                                    double *__restrict__ y, const double *__restrict__ w,
+                                                    double *__restrict__ r_out, double *__restrict__ r0_out,
+                                                    double *__restrict__ p_out, double *__restrict__ part,
+                                                    const int32_t *__restrict__ state) {
+    if (state != nullptr && *state != ST_RUN) return;
+    constexpr int RPW = kWave / BS;
+    constexpr int NV = MODE == 0 ? 1 : (MODE == 3 ? 1 : 2);
+    const int lane = threadIdx.x & 63;
+    const int c = lane % BS;
+    const int64_t nwaves_total = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    for (int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; gw * RPW < n; gw += nwaves_total) {
+        const int64_t row = gw * RPW + lane / BS;
+        if (lane / BS < RPW && row < n) {
+            const int64_t e = row * BS + c;
+            const double t = bsr_row<BS>(ptr, col, val, x, row, c);
+            if constexpr (MODE == 0) {
+                y[e] = t;
+                acc[0] += w[e] * t;
+            } else if constexpr (MODE == 1) {
+                y[e] = t;
+                acc[0] += t * w[e];
+                acc[1] += t * t;
+            } else if constexpr (MODE == 2) {
+                const double rr = w[e] - t;
+                r_out[e] = rr;
+                r0_out[e] = rr;
+                p_out[e] = rr;
+                acc[0] += rr * rr;
+                acc[1] += w[e] * w[e];
+            } else {
+                const double rr = w[e] - t;
+                acc[0] += rr * rr;
+            }
+        }
+    }
+    block_partials<NV>(acc, part);
+}
+
+// s = r - alpha v; partial s.s
+__global__ __launch_bounds__(kRedT) void k_axpy_s(int64_t m, const double *__restrict__ r,
+                                                 const double *__restrict__ v, double *__restrict__ s,
+                                                 const KrylovScalars *__restrict__ ks, double *__restrict__ part) {
+    if (ks->state != ST_RUN) return;
+    const double alpha = ks->alpha;
+    double acc[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const double t = r[i] - alpha * v[i];
+        s[i] = t;
+        acc[0] += t * t;
+    }
+    block_partials<1>(acc, part);
+}
+
+// x += alpha p^ when the half step converged
+__global__ __launch_bounds__(kRedT) void k_half(int64_t m, double *__restrict__ x, const double *__restrict__ ph,
+                                               KrylovScalars *__restrict__ ks) {
+    if (ks->state != ST_HALF) return;
+    const double alpha = ks->alpha;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] += alpha * ph[i];
+}
+
+// x += alpha p^ + omega s^;  r = s - omega t;  partials r.r and r0.r
+__global__ __launch_bounds__(kRedT) void k_update(int64_t m, double *__restrict__ x, const double *__restrict__ ph,
+                                                 const double *__restrict__ sh, double *__restrict__ r,
+                                                 const double *__restrict__ s, const double *__restrict__ t,
+                                                 const double *__restrict__ r0, const KrylovScalars *__restrict__ ks,
+                                                 double *__restrict__ part) {
+    if (ks->state != ST_RUN) return;
+    const double alpha = ks->alpha, omega = ks->omega;
+    double acc[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] += alpha * ph[i] + omega * sh[i];
+        const double rn = s[i] - omega * t[i];
+        r[i] = rn;
+        acc[0] += rn * rn;
+        acc[1] += r0[i] * rn;
+    }
+    block_partials<2>(acc, part);
+}
+
+// p = r + beta (p - omega v)
+__global__ __launch_bounds__(kRedT) void k_pupdate(int64_t m, double *__restrict__ p, const double *__restrict__ r,
+                                                  const double *__restrict__ v, const KrylovScalars *__restrict__ ks) {
+    if (ks->state != ST_RUN) return;
+    const double beta = ks->beta, omega = ks->omega;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = r[i] + beta * (p[i] - omega * v[i]);
+}
+
+// Fixed-order sum of nblk partials of slot k.
+__device__ double reduce_slot(const double *part, int k, int nblk) {
+    __shared__ double sh[kRedT];
+    double t = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += kRedT) t += part[k * kMaxGrid + i];
+    sh[threadIdx.x] = t;
+    __syncthreads();
+    for (int w = kRedT / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double res = sh[0];
+    __syncthreads();
+    return res;
+}
+
+enum : int { SC_INIT = 0, SC_ALPHA = 1, SC_S = 2, SC_OMEGA = 3, SC_BETA = 4, SC_TRUE = 5 };
+
+// Scalar steps of Algorithm 1 (one workgroup).
+__global__ __launch_bounds__(kRedT) void k_scalars(int stage, int it, const double *part, int nblk,
+                                                  KrylovScalars *ks) {
+    const int32_t st0 = ks->state;
+    if (stage != SC_INIT && stage != SC_TRUE && st0 != ST_RUN) return;
+    const double a = reduce_slot(part, 0, nblk);
+    const double b = (stage == SC_INIT || stage == SC_OMEGA || stage == SC_BETA) ? reduce_slot(part, 1, nblk) : 0.0;
+    if (threadIdx.x != 0) return;
+    switch (stage) {
+        case SC_INIT: {  // a = r.r (= r0.r), b = b.b
+            double bn = sqrt(b);
+            if (bn == 0.0) bn = 1.0;
+            ks->bnorm = bn;
+            ks->tol = ks->tol * bn;  // tol holds rtol on entry
+            ks->rho = a;
+            ks->rnorm = sqrt(a);
+            ks->iters = 0;
+            ks->state = (sqrt(a) <= ks->tol) ? ST_CONV : ST_RUN;
+            if (!isfinite(a)) ks->state = DD_EBREAKDOWN;
+            break;
+        }
+        case SC_ALPHA: {  // a = r0.v
+            ks->iters = it;
+            if (a == 0.0 || !isfinite(a) || ks->rho == 0.0) {
+                ks->state = DD_EBREAKDOWN;
+            } else {
+                ks->alpha = ks->rho / a;
+            }
+            break;
+        }
+        case SC_S: {  // a = s.s
+            const double sn = sqrt(a);
+            ks->snorm = sn;
+            if (sn <= ks->tol) {
+                ks->rnorm = sn;
+                ks->state = ST_HALF;
+                ks->half = 1;
+            }
+            break;
+        }
+        case SC_OMEGA: {  // a = t.s, b = t.t
+            if (b == 0.0 || !isfinite(b)) {
+                ks->state = DD_EBREAKDOWN;
+            } else {
+                ks->omega = a / b;
+            }
+            break;
+        }
+        case SC_BETA: {  // a = r.r, b = r0.r
+            const double rn = sqrt(a);
+            ks->rnorm = rn;
+            if (!isfinite(rn)) {
+                ks->state = DD_EBREAKDOWN;
+            } else if (rn <= ks->tol) {
+                ks->state = ST_CONV;
+            } else if (ks->omega == 0.0) {
+                ks->state = DD_EBREAKDOWN;
+            } else {
+                ks->beta = (b / ks->rho) * (ks->alpha / ks->omega);
+                ks->rho = b;
+                if (it >= ks->maxit) ks->state = DD_ENOCONV;
+            }
+            break;
+        }
+        case SC_TRUE: {  // a = ||b - A x||^2
+            ks->snorm = sqrt(a);  // reused slot: true residual norm
+            break;
+        }
+    }
+}
+
+__global__ void k_half_to_conv(KrylovScalars *ks) {
+    if (ks->state == ST_HALF) ks->state = ST_CONV;
+}
+
+// out[i] = in[map[i]] per block row
+__global__ void k_permute(int64_t n, int bs, const int32_t *map, const double *in, double *out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * bs) return;
+    const int64_t i = e / bs;
+    const int c = (int)(e - i * bs);
+    out[e] = in[(int64_t)map[i] * bs + c];
+}
+
+hipError_t launch_permute(int64_t n, int bs, const int32_t *map, const double *in, double *out, hipStream_t st) {
+    const int T = 256;
+    k_permute<<<(unsigned)((n * bs + T - 1) / T), T, 0, st>>>(n, bs, map, in, out);
+    return hipGetLastError();
+}
+
+#define KCHK(x)                                                                             \
+    do {                                                                                    \
+        hipError_t e_ = (x);                                                                \
+        if (e_ != hipSuccess) return h->fail(DD_EHIP, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+template <int BS>
+static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t maxit, hipStream_t st,
+                     dd_solve_info *info) {
+    const int64_t n = h->n;
+    const int64_t m = n * BS;
+    double *V = h->kv;
+    double *bp = V + 0 * m, *xp = V + 1 * m, *r = V + 2 * m, *r0 = V + 3 * m, *p = V + 4 * m;
+    double *ph = V + 5 * m, *v = V + 6 * m, *s = V + 7 * m, *shat = V + 8 * m, *t = V + 9 * m;
+    double *part = h->partials;
+    KrylovScalars *ks = h->ks;
+    const int32_t *state = &ks->state;
+
+    const int rpb = (kWave / BS) * (kRedT / kWave);
+    const int gsp = (int)std::min<int64_t>((n + rpb - 1) / rpb, kMaxGrid);
+    const int gvec = (int)std::min<int64_t>((m + kRedT - 1) / kRedT, kMaxGrid);
+
+    hipEvent_t e0, e1;
+    KCHK(hipEventCreate(&e0));
+    KCHK(hipEventCreate(&e1));
+    KCHK(hipEventRecord(e0, st));
+
+    KrylovScalars init{};
+    init.tol = rtol;
+    init.maxit = maxit;
+    init.state = ST_RUN;
+    *h->ks_host = init;
+    KCHK(hipMemcpyAsync(ks, h->ks_host, sizeof(KrylovScalars), hipMemcpyHostToDevice, st));
+    KCHK(launch_permute(n, BS, h->new2old, b, bp, st));
+    KCHK(launch_permute(n, BS, h->new2old, x, xp, st));
+    // r = b - A x0, r0 = p = r; rho = r0.r
+    k_spmv_dots<BS, 2><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, xp, t, bp, r, r0, p, part, nullptr);
+    k_scalars<<<1, kRedT, 0, st>>>(SC_INIT, 0, part, gsp, ks);
+    KCHK(hipGetLastError());
+
+    const int chunk = 8;
+    if (h->profile && (int)h->events.size() < 4 * chunk) {
+        while ((int)h->events.size() < 4 * chunk) {
+            hipEvent_t ev;
+            KCHK(hipEventCreate(&ev));
+            h->events.push_back(ev);
+        }
+    }
+    int it = 0, applies = 0, chunk_first = 1, chunk_todo = 0;
+    double apply_ms = 0.0;
+    int32_t final_state = ST_RUN;
+    while (true) {
+        KCHK(hipMemcpyAsync(h->ks_host, ks, sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
+        KCHK(hipStreamSynchronize(st));
+        final_state = h->ks_host->state;
+        if (h->profile) {  // applies of the finished chunk that did work
+            const KrylovScalars &hk = *h->ks_host;
+            for (int k = 0; k < chunk_todo; ++k) {
+                const int itk = chunk_first + k;
+                if (itk > hk.iters) break;
+                for (int a = 0; a < 2; ++a) {
+                    if (a == 1 && itk == hk.iters && final_state != ST_RUN && hk.half) continue;
+                    float ms = 0.f;
+                    KCHK(hipEventElapsedTime(&ms, h->events[4 * k + 2 * a], h->events[4 * k + 2 * a + 1]));
+                    apply_ms += ms;
+                    ++applies;
+                }
+            }
+        }
+        if (final_state != ST_RUN || it >= maxit) break;
+        const int todo = std::min(chunk, maxit - it);
+        chunk_first = it + 1;
+        chunk_todo = todo;
+        for (int k = 0; k < todo; ++k) {
+            ++it;
+            if (h->profile) KCHK(hipEventRecord(h->events[4 * k], st));
+            KCHK(launch_apply(h, p, ph, state, st));                       // p^ = M^{-1} p
+            if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 1], st));
+            k_spmv_dots<BS, 0><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, ph, v, r0, nullptr,
+                                                      nullptr, nullptr, part, state);  // v = A p^, r0.v
+            k_scalars<<<1, kRedT, 0, st>>>(SC_ALPHA, it, part, gsp, ks);
+            k_axpy_s<<<gvec, kRedT, 0, st>>>(m, r, v, s, ks, part);        // s = r - alpha v
+            k_scalars<<<1, kRedT, 0, st>>>(SC_S, it, part, gvec, ks);
+            k_half<<<gvec, kRedT, 0, st>>>(m, xp, ph, ks);
+            if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 2], st));
+            KCHK(launch_apply(h, s, shat, state, st));                     // s^ = M^{-1} s
+            if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 3], st));
+            k_spmv_dots<BS, 1><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, shat, t, s, nullptr,
+                                                      nullptr, nullptr, part, state);  // t = A s^, t.s, t.t
+            k_scalars<<<1, kRedT, 0, st>>>(SC_OMEGA, it, part, gsp, ks);
+            k_update<<<gvec, kRedT, 0, st>>>(m, xp, ph, shat, r, s, t, r0, ks, part);
+            k_scalars<<<1, kRedT, 0, st>>>(SC_BETA, it, part, gvec, ks);
+            k_pupdate<<<gvec, kRedT, 0, st>>>(m, p, r, v, ks);
+            k_half_to_conv<<<1, 1, 0, st>>>(ks);
+            KCHK(hipGetLastError());
+        }
+    }
+    KCHK(hipEventRecord(e1, st));
+    // true residual ||b - A x|| / ||b||
+    k_spmv_dots<BS, 3><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, xp, t, bp, nullptr, nullptr, nullptr,
+                                              part, nullptr);
+    k_scalars<<<1, kRedT, 0, st>>>(SC_TRUE, 0, part, gsp, ks);
+    KCHK(launch_permute(n, BS, h->old2new, xp, x, st));
+    KCHK(hipMemcpyAsync(h->ks_host, ks, sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
+    KCHK(hipStreamSynchronize(st));
+    float ms = 0.f;
+    KCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const KrylovScalars &hk = *h->ks_host;
+    int status = DD_OK;
+    if (hk.state == ST_CONV) status = DD_OK;
+    else if (hk.state == DD_EBREAKDOWN) status = DD_EBREAKDOWN;
+    else status = DD_ENOCONV;
+    if (info) {
+        info->iters = hk.iters;
+        info->status = status;
+        info->rel_res = hk.rnorm / hk.bnorm;
+        info->rel_res_true = hk.snorm / hk.bnorm;
+        info->solve_seconds = ms * 1e-3;
+        info->applies = applies;
+        info->pad = 0;
+        info->apply_seconds = apply_ms * 1e-3;
+    }
+    if (status == DD_EBREAKDOWN) return h->fail(DD_EBREAKDOWN, "BiCGSTAB breakdown at iteration %d", hk.iters);
+    if (status == DD_ENOCONV)
+        return h->fail(DD_ENOCONV, "BiCGSTAB did not reach rtol within %d iterations (rel res %.3e)", maxit,
+                       hk.rnorm / hk.bnorm);
+    return DD_OK;
+}
+
+int bicgstab_run(dd_ctx *h, const double *b, double *x, double rtol, int32_t maxit, hipStream_t st,
+                 dd_solve_info *info) {
+    if (!h->kv) {
+        int rc = h->alloc(&h->kv, 10 * h->n * h->bs);
+        if (rc) return rc;
+        rc = h->alloc(&h->partials, (int64_t)kStride * kMaxGrid);
+        if (rc) return rc;
+        rc = h->alloc(&h->ks, 1);
+        if (rc) return rc;
+        hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&h->ks_host), sizeof(KrylovScalars));
+        if (e != hipSuccess) return h->fail(DD_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+    }
+    return h->bs == 3 ? run_typed<3>(h, b, x, rtol, maxit, st, info) : run_typed<1>(h, b, x, rtol, maxit, st, info);
+}
+
+}  // namespace ddilu

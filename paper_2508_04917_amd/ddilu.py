@@ -1,0 +1,262 @@
+"""Python binding of the ddilu C ABI (include/ddilu.h).
+
+Argument marshalling only: every function here forwards torch tensors'
+device pointers and the current HIP stream to the library of the same name;
+all computation runs in the library's kernels.  torch provides device
+memory and streams.  There is no fallback: if libddilu.so is missing or fails
+to load, every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libddilu.so")
+
+DD_OK, DD_EINVAL, DD_ENOTDIV, DD_ELDS, DD_EZEROPIVOT = 0, -1, -2, -3, -4
+DD_EBREAKDOWN, DD_ENOCONV, DD_EHIP, DD_ENOMEM, DD_ESTATE = -5, -6, -7, -8, -9
+DD_FP64, DD_FP32 = 0, 1
+
+STATUS_NAMES = {0: "DD_OK", -1: "DD_EINVAL", -2: "DD_ENOTDIV", -3: "DD_ELDS", -4: "DD_EZEROPIVOT",
+                -5: "DD_EBREAKDOWN", -6: "DD_ENOCONV", -7: "DD_EHIP", -8: "DD_ENOMEM", -9: "DD_ESTATE"}
+
+# every symbol include/ddilu.h declares
+EXPORTS = ("dd_auto_subdims", "dd_device_caps", "dd_partition", "dd_get_info", "dd_get_partition",
+           "dd_get_reordered", "ilu0_factor", "dd_set_precision", "dd_get_levels", "dd_get_factors",
+           "dd_trsv_apply", "dd_spmv", "bicgstab_solve", "dd_set_profiling", "dd_last_error",
+           "dd_destroy")
+
+
+class PartitionDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("bs", C.c_int32),
+                ("sx", C.c_int32), ("sy", C.c_int32), ("sz", C.c_int32), ("n_cu", C.c_int32),
+                ("lds_budget_bytes", C.c_int64)]
+
+
+class Info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnzb", C.c_int64), ("nnzb_dropped", C.c_int64),
+                ("nnzb_lower", C.c_int64), ("nnzb_upper", C.c_int64),
+                ("bs", C.c_int32), ("S", C.c_int32), ("nsub", C.c_int32),
+                ("sx", C.c_int32), ("sy", C.c_int32), ("sz", C.c_int32),
+                ("level_ptr_len", C.c_int32 * 2), ("max_levels", C.c_int32 * 2),
+                ("factored", C.c_int32), ("precision", C.c_int32),
+                ("apply_bytes", C.c_int64), ("lds_bytes", C.c_int64)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("rel_res", C.c_double),
+                ("rel_res_true", C.c_double), ("solve_seconds", C.c_double),
+                ("applies", C.c_int32), ("pad", C.c_int32), ("apply_seconds", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        sig = {
+            "dd_auto_subdims": (C.c_int, [i32, i32, i32, i32, i64, i32, vp]),
+            "dd_device_caps": (C.c_int, [vp, vp]),
+            "dd_partition": (C.c_int, [C.POINTER(PartitionDesc), vp, vp, vp, i64, vp, C.POINTER(vp)]),
+            "dd_get_info": (C.c_int, [vp, C.POINTER(Info)]),
+            "dd_get_partition": (C.c_int, [vp, vp, vp, vp, vp]),
+            "dd_get_reordered": (C.c_int, [vp, vp, vp, vp, vp]),
+            "ilu0_factor": (C.c_int, [vp, i32, vp]),
+            "dd_set_precision": (C.c_int, [vp, i32, vp]),
+            "dd_get_levels": (C.c_int, [vp, i32, vp, vp, vp, vp]),
+            "dd_get_factors": (C.c_int, [vp, vp, vp, vp, vp]),
+            "dd_trsv_apply": (C.c_int, [vp, vp, vp, vp]),
+            "dd_spmv": (C.c_int, [vp, vp, vp, vp]),
+            "bicgstab_solve": (C.c_int, [vp, vp, vp, C.c_double, i32, vp, C.POINTER(SolveInfo)]),
+            "dd_set_profiling": (C.c_int, [vp, i32]),
+            "dd_last_error": (C.c_char_p, [vp]),
+            "dd_destroy": (None, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class DDError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(rc: int, h=None):
+    if rc != DD_OK:
+        raise DDError(rc, dd_last_error(h))
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev_check(t, dtype, numel, name):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous() and t.numel() == numel):
+        raise ValueError(f"{name}: expected a contiguous {dtype} CUDA tensor of {numel} elements")
+
+
+class Handle:
+    """Owns a dd_handle; released by close() or garbage collection."""
+
+    def __init__(self, ptr: int):
+        self.ptr = C.c_void_p(ptr)
+
+    def close(self):
+        if self.ptr:
+            lib().dd_destroy(self.ptr)
+            self.ptr = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def info(self):
+        return dd_get_info(self)
+
+
+def dd_last_error(h=None) -> str:
+    s = lib().dd_last_error(h.ptr if h is not None else None)
+    return s.decode() if s else ""
+
+
+def dd_auto_subdims(nx, ny, nz, bs, lds_budget_bytes, n_cu):
+    out = (C.c_int32 * 3)()
+    _check(lib().dd_auto_subdims(nx, ny, nz, bs, lds_budget_bytes, n_cu, out))
+    return tuple(out)
+
+
+def dd_device_caps():
+    cu = C.c_int32(0)
+    lds = C.c_int64(0)
+    _check(lib().dd_device_caps(C.byref(cu), C.byref(lds)))
+    return cu.value, lds.value
+
+
+def dd_partition(nx, ny, nz, bs, brow_ptr, bcol, val, sub=(0, 0, 0), n_cu=0, lds_budget_bytes=0,
+                 stream=None) -> Handle:
+    n = nx * ny * nz
+    nnzb = bcol.numel()
+    _dev_check(brow_ptr, torch.int32, n + 1, "brow_ptr")
+    _dev_check(bcol, torch.int32, nnzb, "bcol")
+    _dev_check(val, torch.float64, nnzb * bs * bs, "val")
+    d = PartitionDesc(nx, ny, nz, bs, sub[0], sub[1], sub[2], n_cu, lds_budget_bytes)
+    out = C.c_void_p(None)
+    _check(lib().dd_partition(C.byref(d), _ptr(brow_ptr), _ptr(bcol), _ptr(val), nnzb, _stream(stream),
+                              C.byref(out)))
+    return Handle(out.value)
+
+
+def dd_get_info(h: Handle) -> dict:
+    inf = Info()
+    _check(lib().dd_get_info(h.ptr, C.byref(inf)), h)
+    d = {k: getattr(inf, k) for k, _ in Info._fields_}
+    d["level_ptr_len"] = tuple(inf.level_ptr_len)
+    d["max_levels"] = tuple(inf.max_levels)
+    return d
+
+
+def _i32(n, device="cuda"):
+    return torch.empty(n, dtype=torch.int32, device=device)
+
+
+def dd_get_partition(h: Handle, stream=None):
+    n = dd_get_info(h)["n"]
+    pid, n2o, o2n = _i32(n), _i32(n), _i32(n)
+    _check(lib().dd_get_partition(h.ptr, _ptr(pid), _ptr(n2o), _ptr(o2n), _stream(stream)), h)
+    return pid, n2o, o2n
+
+
+def dd_get_reordered(h: Handle, stream=None):
+    inf = dd_get_info(h)
+    n, nnzb, bs = inf["n"], inf["nnzb"], inf["bs"]
+    ptr, col = _i32(n + 1), _i32(nnzb)
+    val = torch.empty(nnzb * bs * bs, dtype=torch.float64, device="cuda")
+    _check(lib().dd_get_reordered(h.ptr, _ptr(ptr), _ptr(col), _ptr(val), _stream(stream)), h)
+    return ptr, col, val
+
+
+def ilu0_factor(h: Handle, precision=DD_FP64, stream=None):
+    _check(lib().ilu0_factor(h.ptr, precision, _stream(stream)), h)
+
+
+def dd_set_precision(h: Handle, precision, stream=None):
+    _check(lib().dd_set_precision(h.ptr, precision, _stream(stream)), h)
+
+
+def dd_get_levels(h: Handle, which: int, stream=None):
+    inf = dd_get_info(h)
+    nlev = _i32(inf["nsub"])
+    lptr = _i32(inf["level_ptr_len"][which])
+    rows = _i32(inf["n"])
+    _check(lib().dd_get_levels(h.ptr, which, _ptr(nlev), _ptr(lptr), _ptr(rows), _stream(stream)), h)
+    return nlev, lptr, rows
+
+
+def dd_get_factors(h: Handle, stream=None):
+    inf = dd_get_info(h)
+    n, m, bs = inf["n"], inf["nnzb_dropped"], inf["bs"]
+    ptr, col = _i32(n + 1), _i32(m)
+    f = torch.empty(m * bs * bs, dtype=torch.float64, device="cuda")
+    _check(lib().dd_get_factors(h.ptr, _ptr(ptr), _ptr(col), _ptr(f), _stream(stream)), h)
+    return ptr, col, f
+
+
+def dd_trsv_apply(h: Handle, r, z=None, stream=None):
+    if z is None:
+        z = torch.empty_like(r)
+    _dev_check(r, torch.float64, z.numel(), "r")
+    _check(lib().dd_trsv_apply(h.ptr, _ptr(r), _ptr(z), _stream(stream)), h)
+    return z
+
+
+def dd_spmv(h: Handle, x, y=None, stream=None):
+    if y is None:
+        y = torch.empty_like(x)
+    _dev_check(x, torch.float64, y.numel(), "x")
+    _check(lib().dd_spmv(h.ptr, _ptr(x), _ptr(y), _stream(stream)), h)
+    return y
+
+
+def bicgstab_solve(h: Handle, b, x=None, rtol=1e-8, maxit=10000, stream=None):
+    """Returns (x, info).  info['status'] is DD_OK, DD_EBREAKDOWN or DD_ENOCONV;
+    other failures raise."""
+    if x is None:
+        x = torch.zeros_like(b)
+    _dev_check(b, torch.float64, x.numel(), "b")
+    si = SolveInfo()
+    rc = lib().bicgstab_solve(h.ptr, _ptr(b), _ptr(x), rtol, maxit, _stream(stream), C.byref(si))
+    if rc not in (DD_OK, DD_EBREAKDOWN, DD_ENOCONV):
+        raise DDError(rc, dd_last_error(h))
+    return x, {k: getattr(si, k) for k, _ in SolveInfo._fields_}
+
+
+def dd_set_profiling(h: Handle, on: bool):
+    _check(lib().dd_set_profiling(h.ptr, 1 if on else 0), h)
+
+
+def dd_destroy(h: Handle):
+    h.close()
