@@ -1,0 +1,203 @@
+"""Benchmark of the domain-decomposed ILU0 path on one MI355X.
+
+One step = one pass of the whole path over the workload's matrix, already
+resident in HBM: partition + reorder, drop + level sets + block ILU0/ILDU0,
+BiCGSTAB to rel. residual 1e-8 with the FP64 preconditioner, FP32 factor
+copies, BiCGSTAB to 1e-8 with the FP32 preconditioner.
+
+Printed (one JSON line): the trisolve bandwidth of the FP64 apply -- its
+algorithmic bytes divided by its average duration, timed by HIP event pairs
+on the solve's stream around every apply inside the timed solves -- and its
+fraction of the 8 TB/s HBM peak, the BiCGSTAB times, and the oracle's
+single-thread apply bandwidth on the same matrix as a CPU baseline.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "trisolve GB/s & %HBM peak; BiCGSTAB s to 1e-8: learned+FP32 vs plain FP64"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_sha(path):
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload, sub):
+    """HBM bytes per apply from committed rocprofv3 counter runs, if they were
+    taken on the current apply kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(workload)
+    except (ValueError, OSError):
+        return None
+    if not rec or list(rec.get("subdomain", [])) != list(sub):
+        return None
+    src = os.path.join(ROOT, "paper_2508_04917_amd", "csrc", "apply.hip")
+    if rec.get("apply_source_sha") != source_sha(src):
+        return None
+    return rec.get("bytes_per_apply")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="lognormal160_bsr3")
+    ap.add_argument("--sub", default="auto", help="sx,sy,sz or auto")
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--maxit", type=int, default=5000)
+    ap.add_argument("--cpu-applies", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "single-GPU build: the apply and solver run on one GPU; "
+                          "multi-GPU sharding is not implemented (run with --gpus 1)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2508_04917_amd import ddilu as dd
+    from problems import WORKLOADS, make_workload
+
+    torch.cuda.set_device(0)
+    dd.lib()
+    log(f"generating {args.workload}")
+    p = make_workload(args.workload)
+    sub = (0, 0, 0) if args.sub == "auto" else tuple(int(v) for v in args.sub.split(","))
+    dev = "cuda:0"
+    ptr_d = torch.as_tensor(p.brow_ptr, device=dev)
+    col_d = torch.as_tensor(p.bcol, device=dev)
+    val_d = torch.as_tensor(p.val.reshape(-1), device=dev)
+    b_d = torch.as_tensor(p.b, device=dev)
+    n_cu, lds = dd.dd_device_caps()
+    log(f"device: {n_cu} CUs, {lds} B LDS per workgroup; n={p.n} nnzb={p.nnzb}")
+
+    def step():
+        rec = {}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = dd.dd_partition(p.nx, p.ny, p.nz, p.bs, ptr_d, col_d, val_d, sub=sub)
+        dd.ilu0_factor(h, dd.DD_FP64)
+        torch.cuda.synchronize()
+        rec["setup_s"] = time.perf_counter() - t0
+        dd.dd_set_profiling(h, True)
+        x64, i64 = dd.bicgstab_solve(h, b_d, rtol=args.rtol, maxit=args.maxit)
+        t1 = time.perf_counter()
+        dd.dd_set_precision(h, dd.DD_FP32)
+        torch.cuda.synchronize()
+        rec["fp32_cast_s"] = time.perf_counter() - t1
+        x32, i32 = dd.bicgstab_solve(h, b_d, rtol=args.rtol, maxit=args.maxit)
+        rec["fp64"], rec["fp32"] = i64, i32
+        rec["info"] = dd.dd_get_info(h)
+        dd.dd_set_precision(h, dd.DD_FP64)
+        rec["bytes64"] = dd.dd_get_info(h)["apply_bytes"]
+        dd.dd_set_precision(h, dd.DD_FP32)
+        rec["bytes32"] = dd.dd_get_info(h)["apply_bytes"]
+        rec["x_rel_diff"] = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
+        h.close()
+        return rec
+
+    for w in range(args.warmup):
+        log(f"warmup step {w + 1}/{args.warmup}")
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = []
+    for k in range(args.steps):
+        recs.append(step())
+        r = recs[-1]
+        log(f"step {k + 1}/{args.steps}: setup {r['setup_s']:.3f}s, FP64 {r['fp64']['iters']} it "
+            f"{r['fp64']['solve_seconds']:.3f}s, FP32 {r['fp32']['iters']} it {r['fp32']['solve_seconds']:.3f}s")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    inf = recs[0]["info"]
+    applies64 = sum(r["fp64"]["applies"] for r in recs)
+    secs64 = sum(r["fp64"]["apply_seconds"] for r in recs)
+    applies32 = sum(r["fp32"]["applies"] for r in recs)
+    secs32 = sum(r["fp32"]["apply_seconds"] for r in recs)
+    bytes64, bytes32 = recs[0]["bytes64"], recs[0]["bytes32"]
+    gbs64 = bytes64 * applies64 / secs64 / 1e9
+    gbs32 = bytes32 * applies32 / secs32 / 1e9
+    med = lambda xs: float(np.median(xs))
+    subd = [inf["sx"], inf["sy"], inf["sz"]]
+
+    traffic = measured_traffic(args.workload, subd)
+    out = {
+        "metric": METRIC,
+        "value": round(gbs64, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": [p.nx, p.ny, p.nz], "bs": p.bs,
+                   "block_rows": p.n, "blocks": p.nnzb, "subdomain": subd, "n_subdomains": inf["nsub"],
+                   "rtol": args.rtol},
+        "hbm_peak_frac": round(gbs64 / HBM_PEAK_GBS, 4),
+        "trisolve": {
+            "fp64": {"GB/s": round(gbs64, 1), "us_per_apply": round(1e6 * secs64 / applies64, 2),
+                     "bytes_per_apply": bytes64, "hbm_peak_frac": round(gbs64 / HBM_PEAK_GBS, 4)},
+            "fp32_factors": {"GB/s": round(gbs32, 1), "us_per_apply": round(1e6 * secs32 / applies32, 2),
+                             "bytes_per_apply": bytes32, "hbm_peak_frac": round(gbs32 / HBM_PEAK_GBS, 4)},
+        },
+        "bicgstab": {
+            "plain_fp64": {"iters": recs[0]["fp64"]["iters"],
+                           "solve_s": round(med([r["fp64"]["solve_seconds"] for r in recs]), 4),
+                           "rel_res_true": recs[0]["fp64"]["rel_res_true"]},
+            "fp32_factors": {"iters": recs[0]["fp32"]["iters"],
+                             "solve_s": round(med([r["fp32"]["solve_seconds"] for r in recs]), 4),
+                             "rel_res_true": recs[0]["fp32"]["rel_res_true"],
+                             "x_rel_diff_vs_fp64": recs[0]["x_rel_diff"]},
+            "setup_s": round(med([r["setup_s"] for r in recs]), 4),
+        },
+        "roofline": {"bound": "hbm", "achieved": round(gbs64, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs64 / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_dd_apply<3,double>", "bytes_per_launch": bytes64},
+        "cpu_baseline": None,
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle as O
+        log("cpu baseline: oracle setup + applies on the same matrix")
+        st = O.setup(p, tuple(subd))
+        r = np.random.default_rng(0).standard_normal(p.n * p.bs)
+        st.apply(r)
+        t = time.perf_counter()
+        for _ in range(args.cpu_applies):
+            st.apply(r)
+        dt = (time.perf_counter() - t) / args.cpu_applies
+        out["cpu_baseline"] = {
+            "value": round(bytes64 / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{args.cpu_applies} single-thread oracle DD-ILU0 applies (FP64) on the full "
+                      f"{p.nx}x{p.ny}x{p.nz} matrix, {dt * 1e3:.1f} ms each, bytes counted as for the GPU apply"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -205,6 +205,13 @@ int bicgstab_solve(dd_handle h, const double *b, double *x, double rtol,
  * the summed durations are reported in dd_solve_info.apply_seconds. */
 int dd_set_profiling(dd_handle h, int32_t on);
 
+/* Record the residual history of later bicgstab_solve calls on h: entry j
+ * of hist (device double[len]) receives ||r_j||/||b|| after iteration j
+ * (entry 0 the initial residual; after a half-step exit, ||s||/||b||).
+ * Entries past the last iteration are left untouched.  hist = NULL stops
+ * recording. */
+int dd_set_residual_history(dd_handle h, double *hist, int32_t len);
+
 /* Message of the last failed call on h (or of the last failure before a
  * handle existed when h is NULL).  Owned by the library. */
 const char *dd_last_error(dd_handle h);

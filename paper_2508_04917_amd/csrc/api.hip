@@ -446,6 +446,14 @@ extern "C" int dd_set_profiling(dd_handle h, int32_t on) {
     return DD_OK;
 }
 
+extern "C" int dd_set_residual_history(dd_handle h, double *hist, int32_t len) {
+    if (!h) return set_global_error(DD_EINVAL, "dd_set_residual_history: null handle");
+    if (hist && len <= 0) return h->fail(DD_EINVAL, "dd_set_residual_history: len must be positive");
+    h->hist = hist;
+    h->hist_len = hist ? len : 0;
+    return DD_OK;
+}
+
 extern "C" const char *dd_last_error(dd_handle h) { return h ? h->err.c_str() : g_err.c_str(); }
 
 extern "C" void dd_destroy(dd_handle h) { delete h; }

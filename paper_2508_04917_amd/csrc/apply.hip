@@ -105,8 +105,189 @@ __global__ __launch_bounds__(NT) void k_dd_apply(
     for (int i = tid; i < S * BS; i += NT) zs[i] = static_cast<double>(y[i]);
 }
 
+// Software-pipelined variant for subdomains whose widest level fits one pass
+// of the workgroup (every level is handled by one lane group per row).
+// The factor data of a level does not depend on the solve, so it is fetched
+// ahead: while level l computes from LDS, the blocks of level l+1 are already
+// in flight into registers and the row metadata of level l+2 behind them.
+// The level barrier only orders LDS traffic; it does not wait for these
+// global loads, so HBM latency overlaps the level chain.  Rows with more
+// than MB blocks take the extra blocks through a direct (unpipelined) loop.
+template <int BS, typename T, int MB>
+struct LevelRegs {
+    bool ok;
+    int I, b0, nb;
+    int J[MB];
+    T v[MB][BS];
+    T d[BS];
+};
+
+template <int BS, typename T, int MB, bool UPPER>
+__device__ __forceinline__ void load_meta(const uint16_t *__restrict__ prow, const int32_t *__restrict__ bp,
+                                          int64_t gp, bool ok, int &I, int &b0, int &nb) {
+    if (ok) {
+        I = prow[gp];
+        b0 = bp[gp];
+        nb = bp[gp + 1] - b0;
+    } else {
+        I = 0;
+        b0 = 0;
+        nb = 0;
+    }
+}
+
+template <int BS, typename T, int MB, bool UPPER>
+__device__ __forceinline__ void load_vals(LevelRegs<BS, T, MB> &R, const uint16_t *__restrict__ col,
+                                          const T *__restrict__ val, const T *__restrict__ dval, int64_t gp,
+                                          bool ok, int c) {
+    constexpr int BB = BS * BS;
+#pragma unroll
+    for (int k = 0; k < MB; ++k) {
+        if (k < R.nb) {
+            const int64_t b = R.b0 + k;
+            R.J[k] = col[b];
+            const T *blk = val + b * BB + c * BS;
+#pragma unroll
+            for (int d = 0; d < BS; ++d) R.v[k][d] = blk[d];
+        }
+    }
+    if constexpr (UPPER) {
+        if (ok) {
+            const T *dblk = dval + gp * BB + c * BS;
+#pragma unroll
+            for (int d = 0; d < BS; ++d) R.d[d] = dblk[d];
+        }
+    }
+}
+
+// Row metadata of one lane at one level.
+struct LevelMeta {
+    int64_t gp;
+    bool ok;
+    int I, b0, nb;
+};
+
+// Compute one level from the registers R and the LDS vector y.
+template <int BS, typename T, int MB, bool UPPER>
+__device__ __forceinline__ void level_compute(T *__restrict__ y, const LevelRegs<BS, T, MB> &R,
+                                              const uint16_t *__restrict__ col, const T *__restrict__ val, int c) {
+    constexpr int BB = BS * BS;
+    if (!R.ok) return;
+    const int I = R.I;
+    T acc;
+    if constexpr (UPPER) {
+        acc = 0;
+#pragma unroll
+        for (int d = 0; d < BS; ++d) acc += R.d[d] * y[I * BS + d];
+    } else {
+        acc = y[I * BS + c];
+    }
+#pragma unroll
+    for (int k = 0; k < MB; ++k) {
+        if (k < R.nb) {
+            const int J = R.J[k];
+#pragma unroll
+            for (int d = 0; d < BS; ++d) acc -= R.v[k][d] * y[J * BS + d];
+        }
+    }
+    for (int k = MB; k < R.nb; ++k) {  // rows longer than the register window
+        const int64_t b = R.b0 + k;
+        const int J = col[b];
+        const T *blk = val + b * BB + c * BS;
+#pragma unroll
+        for (int d = 0; d < BS; ++d) acc -= blk[d] * y[J * BS + d];
+    }
+    // all lanes of this row read y_I above (same wavefront)
+    __asm__ volatile("" ::: "memory");
+    y[I * BS + c] = acc;
+}
+
+template <int BS, typename T, int NT, int MB, bool UPPER>
+__device__ __forceinline__ void sweep_pipelined(T *__restrict__ y, int64_t base, int s,
+                                                const int32_t *__restrict__ off, const int32_t *__restrict__ lp,
+                                                const uint16_t *__restrict__ prow, const int32_t *__restrict__ bp,
+                                                const uint16_t *__restrict__ col, const T *__restrict__ val,
+                                                const T *__restrict__ dval, int slot, bool lane_ok, int c) {
+    const int32_t o = off[s];
+    const int nl = off[s + 1] - o - 1;
+    if (nl <= 0) return;
+    auto meta = [&](int l) -> LevelMeta {
+        LevelMeta m;
+        const int32_t p0 = lp[o + l], p1 = lp[o + l + 1];
+        const int32_t p = p0 + slot;
+        m.ok = lane_ok && p < p1;
+        m.gp = base + p;
+        load_meta<BS, T, MB, UPPER>(prow, bp, m.gp, m.ok, m.I, m.b0, m.nb);
+        return m;
+    };
+    auto fetch = [&](LevelRegs<BS, T, MB> &R, const LevelMeta &m) {
+        R.ok = m.ok;
+        R.I = m.I;
+        R.b0 = m.b0;
+        R.nb = m.nb;
+        load_vals<BS, T, MB, UPPER>(R, col, val, dval, m.gp, m.ok, c);
+    };
+    // Two register sets, A and B, alternate between "being computed" and
+    // "being filled"; the loop is unrolled by two so that neither is copied
+    // (a copy of a register with a load in flight would wait for the load).
+    LevelRegs<BS, T, MB> A, B;
+    LevelMeta mA = meta(0);
+    fetch(A, mA);
+    LevelMeta mB;
+    mB.ok = false;
+    if (nl > 1) mB = meta(1);
+    for (int l = 0; l < nl; l += 2) {
+        // level l from A; fill B with level l+1; metadata of level l+2
+        if (l + 1 < nl) fetch(B, mB);
+        if (l + 2 < nl) mA = meta(l + 2);
+        level_compute<BS, T, MB, UPPER>(y, A, col, val, c);
+        __syncthreads();
+        if (l + 1 >= nl) break;
+        // level l+1 from B; fill A with level l+2; metadata of level l+3
+        if (l + 2 < nl) fetch(A, mA);
+        if (l + 3 < nl) mB = meta(l + 3);
+        level_compute<BS, T, MB, UPPER>(y, B, col, val, c);
+        __syncthreads();
+    }
+}
+
+template <int BS, typename T, int NT, int MB>
+__global__ __launch_bounds__(NT) void k_dd_apply_pipe(
+    const double *__restrict__ r, double *__restrict__ z, int S,
+    const int32_t *__restrict__ Loff, const int32_t *__restrict__ Llp, const uint16_t *__restrict__ Lrow,
+    const int32_t *__restrict__ Lbp, const uint16_t *__restrict__ Lcol, const T *__restrict__ Lval,
+    const int32_t *__restrict__ Uoff, const int32_t *__restrict__ Ulp, const uint16_t *__restrict__ Urow,
+    const int32_t *__restrict__ Ubp, const uint16_t *__restrict__ Ucol, const T *__restrict__ Uval,
+    const T *__restrict__ Dval, const int32_t *__restrict__ state) {
+    if (state != nullptr && *state != 0) return;
+    constexpr int RPW = kWave / BS;
+    extern __shared__ unsigned char dd_smem[];
+    T *y = reinterpret_cast<T *>(dd_smem);
+    const int s = blockIdx.x;
+    const int64_t base = (int64_t)s * S;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wave = tid / kWave;
+    const int c = lane % BS, rl = lane / BS;
+    const bool lane_ok = rl < RPW;
+    const int slot = wave * RPW + rl;
+
+    const double *rs = r + base * BS;
+    for (int i = tid; i < S * BS; i += NT) y[i] = static_cast<T>(rs[i]);
+    __syncthreads();
+    sweep_pipelined<BS, T, NT, MB, false>(y, base, s, Loff, Llp, Lrow, Lbp, Lcol, Lval, nullptr, slot, lane_ok, c);
+    sweep_pipelined<BS, T, NT, MB, true>(y, base, s, Uoff, Ulp, Urow, Ubp, Ucol, Uval, Dval, slot, lane_ok, c);
+    double *zs = z + base * BS;
+    for (int i = tid; i < S * BS; i += NT) zs[i] = static_cast<double>(y[i]);
+}
+
 int apply_lds_bytes(const dd_ctx *h, int precision) {
     return h->S * h->bs * (precision == DD_FP32 ? 4 : 8);
+}
+
+template <typename K>
+static hipError_t allow_full_lds(K kern) {
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               163840);
 }
 
 template <int BS, typename T, int NT>
@@ -119,11 +300,24 @@ static hipError_t launch_typed(dd_ctx *h, const double *r, double *z, const int3
         lv = L.val32; uv = U.val32; dv = U.d32;
     }
     const int lds = h->S * BS * (int)sizeof(T);
+    constexpr int RPP = (kWave / BS) * (NT / kWave);
+    if (h->max_level_width <= RPP && h->use_pipeline) {
+        constexpr int MB = BS == 3 ? 3 : 3;
+        auto kern = k_dd_apply_pipe<BS, T, NT, MB>;
+        static bool attr_done = false;
+        if (!attr_done) {
+            hipError_t e = allow_full_lds(kern);
+            if (e != hipSuccess) return e;
+            attr_done = true;
+        }
+        kern<<<h->nsub, NT, lds, st>>>(r, z, h->S, h->lev[0].off, h->lev[0].ptr, L.prow, L.bptr, L.bcol, lv,
+                                       h->lev[1].off, h->lev[1].ptr, U.prow, U.bptr, U.bcol, uv, dv, state);
+        return hipGetLastError();
+    }
     auto kern = k_dd_apply<BS, T, NT>;
     static bool attr_done = false;
     if (!attr_done) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+        hipError_t e = allow_full_lds(kern);
         if (e != hipSuccess) return e;
         attr_done = true;
     }

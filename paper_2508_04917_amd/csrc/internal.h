@@ -77,6 +77,9 @@ struct dd_ctx {
     int32_t precision = DD_FP64;
     int32_t max_level_width = 0;  // widest level of any subdomain, L or U
     int32_t profile = 0;          // time every apply inside bicgstab_solve
+    int32_t use_pipeline = 1;     // software-pipelined apply when levels fit one pass
+    double *hist = nullptr;       // optional residual history (device, caller-owned)
+    int32_t hist_len = 0;
     std::vector<hipEvent_t> events;
     // scratch
     int32_t *status = nullptr;  // [4] device status words

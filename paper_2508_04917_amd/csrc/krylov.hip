@@ -211,7 +211,7 @@ enum : int { SC_INIT = 0, SC_ALPHA = 1, SC_S = 2, SC_OMEGA = 3, SC_BETA = 4, SC_
 
 // Scalar steps of Algorithm 1 (one workgroup).
 __global__ __launch_bounds__(kRedT) void k_scalars(int stage, int it, const double *part, int nblk,
-                                                  KrylovScalars *ks) {
+                                                  KrylovScalars *ks, double *hist, int hist_len) {
     const int32_t st0 = ks->state;
     if (stage != SC_INIT && stage != SC_TRUE && st0 != ST_RUN) return;
     const double a = reduce_slot(part, 0, nblk);
@@ -228,6 +228,7 @@ __global__ __launch_bounds__(kRedT) void k_scalars(int stage, int it, const doub
             ks->iters = 0;
             ks->state = (sqrt(a) <= ks->tol) ? ST_CONV : ST_RUN;
             if (!isfinite(a)) ks->state = DD_EBREAKDOWN;
+            if (hist && hist_len > 0) hist[0] = sqrt(a) / bn;
             break;
         }
         case SC_ALPHA: {  // a = r0.v
@@ -246,6 +247,7 @@ __global__ __launch_bounds__(kRedT) void k_scalars(int stage, int it, const doub
                 ks->rnorm = sn;
                 ks->state = ST_HALF;
                 ks->half = 1;
+                if (hist && it < hist_len) hist[it] = sn / ks->bnorm;
             }
             break;
         }
@@ -260,6 +262,7 @@ __global__ __launch_bounds__(kRedT) void k_scalars(int stage, int it, const doub
         case SC_BETA: {  // a = r.r, b = r0.r
             const double rn = sqrt(a);
             ks->rnorm = rn;
+            if (hist && it < hist_len) hist[it] = rn / ks->bnorm;
             if (!isfinite(rn)) {
                 ks->state = DD_EBREAKDOWN;
             } else if (rn <= ks->tol) {
@@ -336,7 +339,7 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
     KCHK(launch_permute(n, BS, h->new2old, x, xp, st));
     // r = b - A x0, r0 = p = r; rho = r0.r
     k_spmv_dots<BS, 2><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, xp, t, bp, r, r0, p, part, nullptr);
-    k_scalars<<<1, kRedT, 0, st>>>(SC_INIT, 0, part, gsp, ks);
+    k_scalars<<<1, kRedT, 0, st>>>(SC_INIT, 0, part, gsp, ks, h->hist, h->hist_len);
     KCHK(hipGetLastError());
 
     const int chunk = 8;
@@ -379,18 +382,18 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
             if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 1], st));
             k_spmv_dots<BS, 0><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, ph, v, r0, nullptr,
                                                       nullptr, nullptr, part, state);  // v = A p^, r0.v
-            k_scalars<<<1, kRedT, 0, st>>>(SC_ALPHA, it, part, gsp, ks);
+            k_scalars<<<1, kRedT, 0, st>>>(SC_ALPHA, it, part, gsp, ks, h->hist, h->hist_len);
             k_axpy_s<<<gvec, kRedT, 0, st>>>(m, r, v, s, ks, part);        // s = r - alpha v
-            k_scalars<<<1, kRedT, 0, st>>>(SC_S, it, part, gvec, ks);
+            k_scalars<<<1, kRedT, 0, st>>>(SC_S, it, part, gvec, ks, h->hist, h->hist_len);
             k_half<<<gvec, kRedT, 0, st>>>(m, xp, ph, ks);
             if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 2], st));
             KCHK(launch_apply(h, s, shat, state, st));                     // s^ = M^{-1} s
             if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 3], st));
             k_spmv_dots<BS, 1><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, shat, t, s, nullptr,
                                                       nullptr, nullptr, part, state);  // t = A s^, t.s, t.t
-            k_scalars<<<1, kRedT, 0, st>>>(SC_OMEGA, it, part, gsp, ks);
+            k_scalars<<<1, kRedT, 0, st>>>(SC_OMEGA, it, part, gsp, ks, h->hist, h->hist_len);
             k_update<<<gvec, kRedT, 0, st>>>(m, xp, ph, shat, r, s, t, r0, ks, part);
-            k_scalars<<<1, kRedT, 0, st>>>(SC_BETA, it, part, gvec, ks);
+            k_scalars<<<1, kRedT, 0, st>>>(SC_BETA, it, part, gvec, ks, h->hist, h->hist_len);
             k_pupdate<<<gvec, kRedT, 0, st>>>(m, p, r, v, ks);
             k_half_to_conv<<<1, 1, 0, st>>>(ks);
             KCHK(hipGetLastError());
@@ -400,7 +403,7 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
     // true residual ||b - A x|| / ||b||
     k_spmv_dots<BS, 3><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, xp, t, bp, nullptr, nullptr, nullptr,
                                               part, nullptr);
-    k_scalars<<<1, kRedT, 0, st>>>(SC_TRUE, 0, part, gsp, ks);
+    k_scalars<<<1, kRedT, 0, st>>>(SC_TRUE, 0, part, gsp, ks, h->hist, h->hist_len);
     KCHK(launch_permute(n, BS, h->old2new, xp, x, st));
     KCHK(hipMemcpyAsync(h->ks_host, ks, sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
     KCHK(hipStreamSynchronize(st));

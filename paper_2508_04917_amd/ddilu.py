@@ -27,8 +27,8 @@ STATUS_NAMES = {0: "DD_OK", -1: "DD_EINVAL", -2: "DD_ENOTDIV", -3: "DD_ELDS", -4
 # every symbol include/ddilu.h declares
 EXPORTS = ("dd_auto_subdims", "dd_device_caps", "dd_partition", "dd_get_info", "dd_get_partition",
            "dd_get_reordered", "ilu0_factor", "dd_set_precision", "dd_get_levels", "dd_get_factors",
-           "dd_trsv_apply", "dd_spmv", "bicgstab_solve", "dd_set_profiling", "dd_last_error",
-           "dd_destroy")
+           "dd_trsv_apply", "dd_spmv", "bicgstab_solve", "dd_set_profiling",
+           "dd_set_residual_history", "dd_last_error", "dd_destroy")
 
 
 class PartitionDesc(C.Structure):
@@ -79,6 +79,7 @@ def lib():
             "dd_spmv": (C.c_int, [vp, vp, vp, vp]),
             "bicgstab_solve": (C.c_int, [vp, vp, vp, C.c_double, i32, vp, C.POINTER(SolveInfo)]),
             "dd_set_profiling": (C.c_int, [vp, i32]),
+            "dd_set_residual_history": (C.c_int, [vp, vp, i32]),
             "dd_last_error": (C.c_char_p, [vp]),
             "dd_destroy": (None, [vp]),
         }
@@ -256,6 +257,15 @@ def bicgstab_solve(h: Handle, b, x=None, rtol=1e-8, maxit=10000, stream=None):
 
 def dd_set_profiling(h: Handle, on: bool):
     _check(lib().dd_set_profiling(h.ptr, 1 if on else 0), h)
+
+
+def dd_set_residual_history(h: Handle, hist):
+    """hist: CUDA float64 tensor (or None to stop recording)."""
+    if hist is None:
+        _check(lib().dd_set_residual_history(h.ptr, None, 0), h)
+    else:
+        _dev_check(hist, torch.float64, hist.numel(), "hist")
+        _check(lib().dd_set_residual_history(h.ptr, _ptr(hist), hist.numel()), h)
 
 
 def dd_destroy(h: Handle):

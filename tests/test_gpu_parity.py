@@ -1,10 +1,13 @@
 """GPU parity: the HIP library (through its C ABI) against the CPU oracle on
 identical seeded inputs.  Integer products (partition, permutation, reordered
 pattern, level sets) must match bit for bit; FP64 factors and preconditioned
-vectors to relative 1e-12; BiCGSTAB iteration counts to max(2, 5%): the GPU
-sums its dot products in a different (fixed) order than the oracle, and on
-nonsymmetric problems with erratic convergence that alone moves the exit by a
-few iterations (Section 5.4 reports about +-10% from summation order)."""
+vectors to relative 1e-12.  BiCGSTAB iteration counts are only defined up to
+rounding: the GPU sums its dot products in a different (fixed) order than the
+oracle, and on these nonsymmetric, erratically converging problems a
+perturbation of b at unit roundoff already moves the oracle's own exit by
+several iterations (Section 5.4 likewise reports about +-10% from summation
+order alone).  So the GPU count must lie in the band the oracle spans over
+such perturbed right-hand sides, widened by 2."""
 
 import numpy as np
 import pytest
@@ -119,15 +122,25 @@ def test_apply_deterministic():
         assert torch.equal(s.apply(r), z1)
 
 
-@pytest.mark.parametrize("name", ["lap16_8cube", "rand64_auto", "logn_24_32_40"])
+def oracle_iteration_band(st, b, k=4, seed=99):
+    """Oracle iteration counts for b and for k copies of b perturbed at 1e-15."""
+    its = [st.bicgstab(b, rtol=1e-8).iters]
+    rng = np.random.default_rng(seed)
+    for _ in range(k):
+        its.append(st.bicgstab(b * (1 + 1e-15 * rng.standard_normal(b.size)), rtol=1e-8).iters)
+    return min(its), max(its)
+
+
+@pytest.mark.parametrize("name", ["lap16_8cube", "rand_ragged", "logn_24_32_40"])
 def test_bicgstab_parity(name):
     p, s, st = case(name)
     ref = st.bicgstab(p.b, rtol=1e-8)
     assert ref.status == 0
+    lo, hi = oracle_iteration_band(st, p.b)
     b = torch.as_tensor(p.b, device="cuda")
     x, info = s.solve(b, rtol=1e-8)
     assert info["status"] == 0
-    assert abs(info["iters"] - ref.iters) <= max(2, int(0.05 * ref.iters))
+    assert lo - 2 <= info["iters"] <= hi + 2, (info["iters"], lo, hi)
     assert info["rel_res"] <= 1e-8
     assert info["rel_res_true"] <= 2e-8
     xg = np_(x)
