@@ -3,7 +3,8 @@
 One step = one pass of the whole path over the workload's matrix, already
 resident in HBM: partition + reorder, drop + level sets + block ILU0/ILDU0,
 BiCGSTAB to rel. residual 1e-8 with the FP64 preconditioner, FP32 factor
-copies, BiCGSTAB to 1e-8 with the FP32 preconditioner.
+copies, BiCGSTAB to 1e-8 with FP32-stored factors and FP64 trisolve
+arithmetic (DD_MIXED), and BiCGSTAB to 1e-8 with FP32 trisolves (DD_FP32).
 
 Printed (one JSON line): the trisolve bandwidth of the FP64 apply -- its
 algorithmic bytes divided by its average duration, timed by HIP event pairs
@@ -102,19 +103,24 @@ def main():
         rec["setup_s"] = time.perf_counter() - t0
         dd.dd_set_profiling(h, True)
         x64, i64 = dd.bicgstab_solve(h, b_d, rtol=args.rtol, maxit=args.maxit)
+        rec["bytes64"] = dd.dd_get_info(h)["apply_bytes"]
         t1 = time.perf_counter()
-        dd.dd_set_precision(h, dd.DD_FP32)
+        dd.dd_set_precision(h, dd.DD_MIXED)
         torch.cuda.synchronize()
         rec["fp32_cast_s"] = time.perf_counter() - t1
-        x32, i32 = dd.bicgstab_solve(h, b_d, rtol=args.rtol, maxit=args.maxit)
-        rec["fp64"], rec["fp32"] = i64, i32
-        rec["info"] = dd.dd_get_info(h)
-        dd.dd_set_precision(h, dd.DD_FP64)
-        rec["bytes64"] = dd.dd_get_info(h)["apply_bytes"]
+        xm, im = dd.bicgstab_solve(h, b_d, rtol=args.rtol, maxit=args.maxit)
         dd.dd_set_precision(h, dd.DD_FP32)
-        rec["bytes32"] = dd.dd_get_info(h)["apply_bytes"]
-        rec["x_rel_diff"] = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
+        x32, i32 = dd.bicgstab_solve(h, b_d, rtol=args.rtol, maxit=args.maxit)
+        rec["fp64"], rec["mixed"], rec["fp32"] = i64, im, i32
+        rec["info"] = dd.dd_get_info(h)
+        rec["bytes32"] = rec["info"]["apply_bytes"]
+        nx64 = torch.linalg.norm(x64)
+        rec["x_rel_diff_mixed"] = float(torch.linalg.norm(xm - x64) / nx64)
+        rec["x_rel_diff_fp32"] = float(torch.linalg.norm(x32 - x64) / nx64)
         h.close()
+        for k in ("fp64", "mixed", "fp32"):
+            if rec[k]["status"] != 0:
+                log(f"WARNING: {k} solve ended with status {rec[k]['status']}")
         return rec
 
     for w in range(args.warmup):
@@ -127,7 +133,8 @@ def main():
         recs.append(step())
         r = recs[-1]
         log(f"step {k + 1}/{args.steps}: setup {r['setup_s']:.3f}s, FP64 {r['fp64']['iters']} it "
-            f"{r['fp64']['solve_seconds']:.3f}s, FP32 {r['fp32']['iters']} it {r['fp32']['solve_seconds']:.3f}s")
+            f"{r['fp64']['solve_seconds']:.3f}s, mixed {r['mixed']['iters']} it {r['mixed']['solve_seconds']:.3f}s, "
+            f"FP32 {r['fp32']['iters']} it {r['fp32']['solve_seconds']:.3f}s")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
@@ -136,9 +143,12 @@ def main():
     secs64 = sum(r["fp64"]["apply_seconds"] for r in recs)
     applies32 = sum(r["fp32"]["applies"] for r in recs)
     secs32 = sum(r["fp32"]["apply_seconds"] for r in recs)
+    appliesm = sum(r["mixed"]["applies"] for r in recs)
+    secsm = sum(r["mixed"]["apply_seconds"] for r in recs)
     bytes64, bytes32 = recs[0]["bytes64"], recs[0]["bytes32"]
     gbs64 = bytes64 * applies64 / secs64 / 1e9
     gbs32 = bytes32 * applies32 / secs32 / 1e9
+    gbsm = bytes32 * appliesm / secsm / 1e9
     med = lambda xs: float(np.median(xs))
     subd = [inf["sx"], inf["sy"], inf["sz"]]
 
@@ -163,17 +173,23 @@ def main():
         "trisolve": {
             "fp64": {"GB/s": round(gbs64, 1), "us_per_apply": round(1e6 * secs64 / applies64, 2),
                      "bytes_per_apply": bytes64, "hbm_peak_frac": round(gbs64 / HBM_PEAK_GBS, 4)},
-            "fp32_factors": {"GB/s": round(gbs32, 1), "us_per_apply": round(1e6 * secs32 / applies32, 2),
-                             "bytes_per_apply": bytes32, "hbm_peak_frac": round(gbs32 / HBM_PEAK_GBS, 4)},
+            "mixed_fp32_factors_fp64_math": {"GB/s": round(gbsm, 1), "us_per_apply": round(1e6 * secsm / appliesm, 2),
+                                             "bytes_per_apply": bytes32, "hbm_peak_frac": round(gbsm / HBM_PEAK_GBS, 4)},
+            "fp32": {"GB/s": round(gbs32, 1), "us_per_apply": round(1e6 * secs32 / applies32, 2),
+                     "bytes_per_apply": bytes32, "hbm_peak_frac": round(gbs32 / HBM_PEAK_GBS, 4)},
         },
         "bicgstab": {
-            "plain_fp64": {"iters": recs[0]["fp64"]["iters"],
+            "plain_fp64": {"iters": recs[0]["fp64"]["iters"], "status": recs[0]["fp64"]["status"],
                            "solve_s": round(med([r["fp64"]["solve_seconds"] for r in recs]), 4),
                            "rel_res_true": recs[0]["fp64"]["rel_res_true"]},
-            "fp32_factors": {"iters": recs[0]["fp32"]["iters"],
-                             "solve_s": round(med([r["fp32"]["solve_seconds"] for r in recs]), 4),
-                             "rel_res_true": recs[0]["fp32"]["rel_res_true"],
-                             "x_rel_diff_vs_fp64": recs[0]["x_rel_diff"]},
+            "mixed_fp32_factors": {"iters": recs[0]["mixed"]["iters"], "status": recs[0]["mixed"]["status"],
+                                   "solve_s": round(med([r["mixed"]["solve_seconds"] for r in recs]), 4),
+                                   "rel_res_true": recs[0]["mixed"]["rel_res_true"],
+                                   "x_rel_diff_vs_fp64": recs[0]["x_rel_diff_mixed"]},
+            "fp32": {"iters": recs[0]["fp32"]["iters"], "status": recs[0]["fp32"]["status"],
+                     "solve_s": round(med([r["fp32"]["solve_seconds"] for r in recs]), 4),
+                     "rel_res_true": recs[0]["fp32"]["rel_res_true"],
+                     "x_rel_diff_vs_fp64": recs[0]["x_rel_diff_fp32"]},
             "setup_s": round(med([r["setup_s"] for r in recs]), 4),
         },
         "roofline": {"bound": "hbm", "achieved": round(gbs64, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

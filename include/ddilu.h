@@ -55,9 +55,12 @@ enum dd_status {
 };
 
 enum dd_precision {
-    DD_FP64 = 0, /* factors, LDS vector and trisolve arithmetic in FP64       */
-    DD_FP32 = 1  /* factors, LDS vector and trisolve arithmetic in FP32;
-                    apply input and output stay FP64                         */
+    DD_FP64 = 0,  /* factors, LDS vector and trisolve arithmetic in FP64      */
+    DD_FP32 = 1,  /* factors, LDS vector and trisolve arithmetic in FP32     */
+    DD_MIXED = 2  /* factors stored in FP32 (half the factor bytes), widened
+                     exactly on load; LDS vector and arithmetic in FP64      */
+    /* In every precision the apply reads r and writes z in FP64, and the
+       FP32 factors are the FP64 factors rounded to nearest even.          */
 };
 
 /* Partition request.  sx = sy = sz = 0 selects the automatic rule of
@@ -150,14 +153,14 @@ int dd_get_reordered(dd_handle h, int32_t *ptr, int32_t *col, double *val,
 /* Section 3.2 drop, Section 4.2.1 level sets, Section 4.3 block ILU0
  * (IKJ order, level-scheduled inside each subdomain) and ILDU0 post-pass;
  * then packs the factors in the streaming layout of the apply.
- * precision: dd_precision the apply will use (FP32 also keeps the FP64
- * factors for dd_get_factors).  Synchronises the stream; returns
+ * precision: dd_precision the apply will use (the FP64 factors are always
+ * kept, for dd_get_factors and for switching precision).  Synchronises the stream; returns
  * DD_EZEROPIVOT if a pivot block is singular or has 1-norm condition
  * number above 1e14 (the message names the block row). */
 int ilu0_factor(dd_handle h, int32_t precision, void *hip_stream);
 
-/* Choose the apply precision after factoring (DD_FP32 builds the FP32
- * copies on first use). */
+/* Choose the apply precision after factoring (DD_FP32 and DD_MIXED build
+ * the FP32 factor copies on first use). */
 int dd_set_precision(dd_handle h, int32_t precision, void *hip_stream);
 
 /* Level sets (Section 4.2.2 explicit DAG).  which = 0: lower factor, 1:
@@ -199,6 +202,16 @@ int dd_spmv(dd_handle h, const double *x, double *y, void *hip_stream);
  * then holds the last iterate). */
 int bicgstab_solve(dd_handle h, const double *b, double *x, double rtol,
                    int32_t maxit, void *hip_stream, dd_solve_info *info);
+
+/* Choose the kernel dd_trsv_apply uses (all compute the same z; they differ
+ * in how factor data is fetched): 0 = automatic (the fastest one the
+ * handle's shape allows), 1 = plain level loop (levels of any width),
+ * 2 = level loop with the next level's blocks prefetched into registers
+ * (levels no wider than one workgroup pass), 3 = as 2 with fixed per-row
+ * block slots so that loads run two levels ahead (rows of at most 4
+ * blocks).  A variant the shape does not allow falls back to 1.  Returns
+ * DD_EINVAL for other values. */
+int dd_set_apply_variant(dd_handle h, int32_t variant);
 
 /* Switch per-apply timing inside bicgstab_solve on (1) or off (0): a HIP
  * event pair on the solve's stream brackets every preconditioner apply and

@@ -317,6 +317,16 @@ class OracleSetup:
     def apply(self, r):
         return apply(self.n, self.bs, self.tptr, self.tcol, self.f, r)
 
+    def apply_fp32_factors(self, r, round_input=True):
+        """FP32-factor variants (task addition, not in the paper): the FP64
+        apply run with L, inv_D and Uhat rounded to FP32 (round to nearest
+        even) and, when round_input, with r rounded to FP32 as well."""
+        f32 = np.asarray(self.f, dtype=np.float64).astype(np.float32).astype(np.float64)
+        r = np.asarray(r, dtype=np.float64)
+        if round_input:
+            r = r.astype(np.float32).astype(np.float64)
+        return apply(self.n, self.bs, self.tptr, self.tcol, f32, r)
+
     def spmv(self, x):
         return spmv(self.n, self.bs, self.aptr, self.acol, self.aval, x)
 

@@ -228,7 +228,7 @@ extern "C" int dd_get_info(dd_handle h, dd_info *info) {
     }
     info->factored = h->factored;
     info->precision = h->precision;
-    const int64_t wsz = h->precision == DD_FP32 ? 4 : 8;
+    const int64_t wsz = h->precision == DD_FP64 ? 8 : 4;  // factor storage
     const int64_t bb = h->bs * h->bs;
     info->apply_bytes = (h->nlow + h->nupp) * (bb * wsz + 4) + h->n * bb * wsz + 2 * 4 * (h->n + 1) +
                         2 * h->n * h->bs * 8;
@@ -300,13 +300,17 @@ static int build_sweep(dd_ctx *h, int which, hipStream_t st, int32_t *cnt) {
         RCHK(h->alloc(&w.bptr, h->n + 1));
     }
     HCHK(launch_pack_count(h, which, cnt, st));
+    HCHK(hipMemsetAsync(h->status + 4, 0, sizeof(int32_t), st));
+    HCHK(launch_max_count(h->n, cnt, h->status + 4, st));
     HCHK(exclusive_scan(cnt, w.bptr, h->n, h->scan_tmp, st));
-    int32_t total = 0;
+    int32_t total = 0, maxrow = 0;
     HCHK(hipMemcpyAsync(&total, w.bptr + h->n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HCHK(hipMemcpyAsync(&maxrow, h->status + 4, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HCHK(hipStreamSynchronize(st));
     if (w.bcol) { release(h, w.bcol); release(h, w.val64); w.bcol = nullptr; w.val64 = nullptr; }
     if (w.val32) { release(h, w.val32); w.val32 = nullptr; }
     w.nblk = total;
+    w.max_row = maxrow;
     RCHK(h->alloc(&w.bcol, total));
     RCHK(h->alloc(&w.val64, (int64_t)total * bb));
     if (which == 1 && !w.d64) RCHK(h->alloc(&w.d64, h->n * bb));
@@ -314,11 +318,34 @@ static int build_sweep(dd_ctx *h, int which, hipStream_t st, int32_t *cnt) {
     return DD_OK;
 }
 
+// Slot layout for both sweeps when no row has more than kMaxSlots blocks.
+static int build_slots(dd_ctx *h, hipStream_t st) {
+    const int bb = h->bs * h->bs;
+    for (int w = 0; w < 2; ++w) {
+        Sweep &s = h->sw[w];
+        if (s.desc) { release(h, s.desc); release(h, s.sval64); }
+        if (s.sval32) release(h, s.sval32);
+        s.desc = nullptr; s.sval64 = nullptr; s.sval32 = nullptr;
+    }
+    const int mr = std::max(h->sw[0].max_row, h->sw[1].max_row);
+    h->slots = mr <= kMaxSlots ? std::max(mr, 1) : 0;
+    if (!h->slots) return DD_OK;
+    for (int w = 0; w < 2; ++w) {
+        Sweep &s = h->sw[w];
+        RCHK(h->alloc(&s.desc, h->n));
+        RCHK(h->alloc(&s.sval64, h->n * h->slots * bb));
+        HCHK(launch_pack_slots(h, w, st));
+    }
+    return DD_OK;
+}
+
 static int ensure_fp32(dd_ctx *h, hipStream_t st) {
     const int bb = h->bs * h->bs;
-    if (h->sw[0].val32 && h->sw[1].val32 && h->sw[1].d32) return DD_OK;
-    for (int w = 0; w < 2; ++w)
+    if (h->sw[0].val32 && h->sw[1].val32 && h->sw[1].d32 && (!h->slots || h->sw[0].sval32)) return DD_OK;
+    for (int w = 0; w < 2; ++w) {
         if (!h->sw[w].val32) RCHK(h->alloc(&h->sw[w].val32, h->sw[w].nblk * bb));
+        if (h->slots && !h->sw[w].sval32) RCHK(h->alloc(&h->sw[w].sval32, h->n * h->slots * bb));
+    }
     if (!h->sw[1].d32) RCHK(h->alloc(&h->sw[1].d32, h->n * bb));
     HCHK(launch_cast32(h, st));
     return DD_OK;
@@ -326,7 +353,8 @@ static int ensure_fp32(dd_ctx *h, hipStream_t st) {
 
 extern "C" int ilu0_factor(dd_handle h, int32_t precision, void *hip_stream) {
     if (!h) return set_global_error(DD_EINVAL, "ilu0_factor: null handle");
-    if (precision != DD_FP64 && precision != DD_FP32) return h->fail(DD_EINVAL, "ilu0_factor: bad precision");
+    if (precision != DD_FP64 && precision != DD_FP32 && precision != DD_MIXED)
+        return h->fail(DD_EINVAL, "ilu0_factor: bad precision");
     hipStream_t st = as_stream(hip_stream);
     const int bb = h->bs * h->bs;
     h->factored = 0;
@@ -371,10 +399,11 @@ extern "C" int ilu0_factor(dd_handle h, int32_t precision, void *hip_stream) {
     // ILDU0 post-pass folded into the packing of the two sweeps
     RCHK(build_sweep(h, 0, st, tlen));
     RCHK(build_sweep(h, 1, st, tlen));
+    RCHK(build_slots(h, st));
     h->nlow = h->sw[0].nblk;
     h->nupp = h->sw[1].nblk;
     h->precision = precision;
-    if (precision == DD_FP32) RCHK(ensure_fp32(h, st));
+    if (precision != DD_FP64) RCHK(ensure_fp32(h, st));
     HCHK(hipStreamSynchronize(st));
     release(h, tbeg);
     release(h, tlen);
@@ -386,8 +415,9 @@ extern "C" int ilu0_factor(dd_handle h, int32_t precision, void *hip_stream) {
 extern "C" int dd_set_precision(dd_handle h, int32_t precision, void *hip_stream) {
     if (!h) return set_global_error(DD_EINVAL, "dd_set_precision: null handle");
     if (!h->factored) return h->fail(DD_ESTATE, "dd_set_precision before ilu0_factor");
-    if (precision != DD_FP64 && precision != DD_FP32) return h->fail(DD_EINVAL, "bad precision");
-    if (precision == DD_FP32) RCHK(ensure_fp32(h, as_stream(hip_stream)));
+    if (precision != DD_FP64 && precision != DD_FP32 && precision != DD_MIXED)
+        return h->fail(DD_EINVAL, "bad precision");
+    if (precision != DD_FP64) RCHK(ensure_fp32(h, as_stream(hip_stream)));
     h->precision = precision;
     return DD_OK;
 }
@@ -438,6 +468,13 @@ extern "C" int bicgstab_solve(dd_handle h, const double *b, double *x, double rt
     if (!b || !x || b == x) return h->fail(DD_EINVAL, "bicgstab_solve: b and x must be distinct device buffers");
     if (!(rtol > 0.0) || maxit < 0) return h->fail(DD_EINVAL, "bicgstab_solve: bad rtol or maxit");
     return bicgstab_run(h, b, x, rtol, maxit, as_stream(hip_stream), info);
+}
+
+extern "C" int dd_set_apply_variant(dd_handle h, int32_t variant) {
+    if (!h) return set_global_error(DD_EINVAL, "dd_set_apply_variant: null handle");
+    if (variant < 0 || variant > 3) return h->fail(DD_EINVAL, "dd_set_apply_variant: variant must be 0..3");
+    h->variant = variant;
+    return DD_OK;
 }
 
 extern "C" int dd_set_profiling(dd_handle h, int32_t on) {

@@ -14,24 +14,30 @@
 // in the upper sweep belong to the same wavefront: all of its lanes issue
 // their LDS reads before any lane issues the store.  64/BS rows per
 // wavefront (21 for 3x3 blocks; the 64th lane idles).
+//
+// Types: TS is the storage type of the factor blocks (double or float), TC
+// the type of the LDS vector and of the arithmetic (double for DD_FP64 and
+// DD_MIXED, float for DD_FP32).  Input r and output z are always FP64.
 #include "internal.h"
 
 namespace ddilu {
 
-template <int BS, typename T, int NT>
+// ------------------------------------------------------------------------
+// Variant 1: plain level loop (levels of any width, rows of any length).
+template <int BS, typename TS, typename TC, int NT>
 __global__ __launch_bounds__(NT) void k_dd_apply(
     const double *__restrict__ r, double *__restrict__ z, int S,
     const int32_t *__restrict__ Loff, const int32_t *__restrict__ Llp, const uint16_t *__restrict__ Lrow,
-    const int32_t *__restrict__ Lbp, const uint16_t *__restrict__ Lcol, const T *__restrict__ Lval,
+    const int32_t *__restrict__ Lbp, const uint16_t *__restrict__ Lcol, const TS *__restrict__ Lval,
     const int32_t *__restrict__ Uoff, const int32_t *__restrict__ Ulp, const uint16_t *__restrict__ Urow,
-    const int32_t *__restrict__ Ubp, const uint16_t *__restrict__ Ucol, const T *__restrict__ Uval,
-    const T *__restrict__ Dval, const int32_t *__restrict__ state) {
+    const int32_t *__restrict__ Ubp, const uint16_t *__restrict__ Ucol, const TS *__restrict__ Uval,
+    const TS *__restrict__ Dval, const int32_t *__restrict__ state) {
     if (state != nullptr && *state != 0) return;  // enclosing solve already finished
     constexpr int BB = BS * BS;
-    constexpr int RPW = kWave / BS;         // block rows per wavefront
-    constexpr int RPP = RPW * (NT / kWave); // block rows per pass of the workgroup
+    constexpr int RPW = kWave / BS;          // block rows per wavefront
+    constexpr int RPP = RPW * (NT / kWave);  // block rows per pass of the workgroup
     extern __shared__ unsigned char dd_smem[];
-    T *y = reinterpret_cast<T *>(dd_smem);
+    TC *y = reinterpret_cast<TC *>(dd_smem);
 
     const int s = blockIdx.x;
     const int64_t base = (int64_t)s * S;
@@ -41,7 +47,7 @@ __global__ __launch_bounds__(NT) void k_dd_apply(
     const bool lane_ok = rl < RPW;
 
     const double *rs = r + base * BS;
-    for (int i = tid; i < S * BS; i += NT) y[i] = static_cast<T>(rs[i]);
+    for (int i = tid; i < S * BS; i += NT) y[i] = static_cast<TC>(rs[i]);
     __syncthreads();
 
     // lower sweep: y_I = r_I - sum_{J<I} L_IJ y_J
@@ -55,13 +61,13 @@ __global__ __launch_bounds__(NT) void k_dd_apply(
                 if (lane_ok && p < p1) {
                     const int64_t gp = base + p;
                     const int I = Lrow[gp];
-                    T acc = y[I * BS + c];
+                    TC acc = y[I * BS + c];
                     const int32_t b1 = Lbp[gp + 1];
                     for (int32_t b = Lbp[gp]; b < b1; ++b) {
                         const int J = Lcol[b];
-                        const T *blk = Lval + (int64_t)b * BB + c * BS;
+                        const TS *blk = Lval + (int64_t)b * BB + c * BS;
 #pragma unroll
-                        for (int d = 0; d < BS; ++d) acc -= blk[d] * y[J * BS + d];
+                        for (int d = 0; d < BS; ++d) acc -= static_cast<TC>(blk[d]) * y[J * BS + d];
                     }
                     y[I * BS + c] = acc;
                 }
@@ -81,16 +87,16 @@ __global__ __launch_bounds__(NT) void k_dd_apply(
                 if (lane_ok && p < p1) {
                     const int64_t gp = base + p;
                     const int I = Urow[gp];
-                    const T *dblk = Dval + gp * BB + c * BS;
-                    T acc = 0;
+                    const TS *dblk = Dval + gp * BB + c * BS;
+                    TC acc = 0;
 #pragma unroll
-                    for (int d = 0; d < BS; ++d) acc += dblk[d] * y[I * BS + d];
+                    for (int d = 0; d < BS; ++d) acc += static_cast<TC>(dblk[d]) * y[I * BS + d];
                     const int32_t b1 = Ubp[gp + 1];
                     for (int32_t b = Ubp[gp]; b < b1; ++b) {
                         const int K = Ucol[b];
-                        const T *blk = Uval + (int64_t)b * BB + c * BS;
+                        const TS *blk = Uval + (int64_t)b * BB + c * BS;
 #pragma unroll
-                        for (int d = 0; d < BS; ++d) acc -= blk[d] * y[K * BS + d];
+                        for (int d = 0; d < BS; ++d) acc -= static_cast<TC>(blk[d]) * y[K * BS + d];
                     }
                     // every lane of this row has read y_I above (same wavefront)
                     __asm__ volatile("" ::: "memory");
@@ -105,80 +111,68 @@ __global__ __launch_bounds__(NT) void k_dd_apply(
     for (int i = tid; i < S * BS; i += NT) zs[i] = static_cast<double>(y[i]);
 }
 
-// Software-pipelined variant for subdomains whose widest level fits one pass
-// of the workgroup (every level is handled by one lane group per row).
-// The factor data of a level does not depend on the solve, so it is fetched
-// ahead: while level l computes from LDS, the blocks of level l+1 are already
+// ------------------------------------------------------------------------
+// Variant 2: levels no wider than one workgroup pass, rows in the CSR
+// layout.  The factor data of a level does not depend on the solve, so it is
+// fetched ahead: while level l computes from LDS, the blocks of level l+1 are
 // in flight into registers and the row metadata of level l+2 behind them.
-// The level barrier only orders LDS traffic; it does not wait for these
-// global loads, so HBM latency overlaps the level chain.  Rows with more
-// than MB blocks take the extra blocks through a direct (unpipelined) loop.
-template <int BS, typename T, int MB>
+// The level barrier only orders LDS traffic, so HBM latency overlaps the
+// level chain.  Rows with more than MB blocks take the extra blocks through a
+// direct (unpipelined) loop.
+template <int BS, typename TS, int MB>
 struct LevelRegs {
     bool ok;
     int I, b0, nb;
     int J[MB];
-    T v[MB][BS];
-    T d[BS];
+    TS v[MB][BS];
+    TS d[BS];
 };
 
-template <int BS, typename T, int MB, bool UPPER>
-__device__ __forceinline__ void load_meta(const uint16_t *__restrict__ prow, const int32_t *__restrict__ bp,
-                                          int64_t gp, bool ok, int &I, int &b0, int &nb) {
-    if (ok) {
-        I = prow[gp];
-        b0 = bp[gp];
-        nb = bp[gp + 1] - b0;
-    } else {
-        I = 0;
-        b0 = 0;
-        nb = 0;
-    }
-}
-
-template <int BS, typename T, int MB, bool UPPER>
-__device__ __forceinline__ void load_vals(LevelRegs<BS, T, MB> &R, const uint16_t *__restrict__ col,
-                                          const T *__restrict__ val, const T *__restrict__ dval, int64_t gp,
-                                          bool ok, int c) {
-    constexpr int BB = BS * BS;
-#pragma unroll
-    for (int k = 0; k < MB; ++k) {
-        if (k < R.nb) {
-            const int64_t b = R.b0 + k;
-            R.J[k] = col[b];
-            const T *blk = val + b * BB + c * BS;
-#pragma unroll
-            for (int d = 0; d < BS; ++d) R.v[k][d] = blk[d];
-        }
-    }
-    if constexpr (UPPER) {
-        if (ok) {
-            const T *dblk = dval + gp * BB + c * BS;
-#pragma unroll
-            for (int d = 0; d < BS; ++d) R.d[d] = dblk[d];
-        }
-    }
-}
-
-// Row metadata of one lane at one level.
 struct LevelMeta {
     int64_t gp;
     bool ok;
     int I, b0, nb;
 };
 
-// Compute one level from the registers R and the LDS vector y.
-template <int BS, typename T, int MB, bool UPPER>
-__device__ __forceinline__ void level_compute(T *__restrict__ y, const LevelRegs<BS, T, MB> &R,
-                                              const uint16_t *__restrict__ col, const T *__restrict__ val, int c) {
+template <int BS, typename TS, int MB, bool UPPER>
+__device__ __forceinline__ void csr_fetch(LevelRegs<BS, TS, MB> &R, const LevelMeta &m,
+                                          const uint16_t *__restrict__ col, const TS *__restrict__ val,
+                                          const TS *__restrict__ dval, int c) {
+    constexpr int BB = BS * BS;
+    R.ok = m.ok;
+    R.I = m.I;
+    R.b0 = m.b0;
+    R.nb = m.nb;
+#pragma unroll
+    for (int k = 0; k < MB; ++k) {
+        if (k < R.nb) {
+            const int64_t b = R.b0 + k;
+            R.J[k] = col[b];
+            const TS *blk = val + b * BB + c * BS;
+#pragma unroll
+            for (int d = 0; d < BS; ++d) R.v[k][d] = blk[d];
+        }
+    }
+    if constexpr (UPPER) {
+        if (m.ok) {
+            const TS *dblk = dval + m.gp * BB + c * BS;
+#pragma unroll
+            for (int d = 0; d < BS; ++d) R.d[d] = dblk[d];
+        }
+    }
+}
+
+template <int BS, typename TS, typename TC, int MB, bool UPPER>
+__device__ __forceinline__ void csr_compute(TC *__restrict__ y, const LevelRegs<BS, TS, MB> &R,
+                                            const uint16_t *__restrict__ col, const TS *__restrict__ val, int c) {
     constexpr int BB = BS * BS;
     if (!R.ok) return;
     const int I = R.I;
-    T acc;
+    TC acc;
     if constexpr (UPPER) {
         acc = 0;
 #pragma unroll
-        for (int d = 0; d < BS; ++d) acc += R.d[d] * y[I * BS + d];
+        for (int d = 0; d < BS; ++d) acc += static_cast<TC>(R.d[d]) * y[I * BS + d];
     } else {
         acc = y[I * BS + c];
     }
@@ -187,27 +181,27 @@ __device__ __forceinline__ void level_compute(T *__restrict__ y, const LevelRegs
         if (k < R.nb) {
             const int J = R.J[k];
 #pragma unroll
-            for (int d = 0; d < BS; ++d) acc -= R.v[k][d] * y[J * BS + d];
+            for (int d = 0; d < BS; ++d) acc -= static_cast<TC>(R.v[k][d]) * y[J * BS + d];
         }
     }
     for (int k = MB; k < R.nb; ++k) {  // rows longer than the register window
         const int64_t b = R.b0 + k;
         const int J = col[b];
-        const T *blk = val + b * BB + c * BS;
+        const TS *blk = val + b * BB + c * BS;
 #pragma unroll
-        for (int d = 0; d < BS; ++d) acc -= blk[d] * y[J * BS + d];
+        for (int d = 0; d < BS; ++d) acc -= static_cast<TC>(blk[d]) * y[J * BS + d];
     }
     // all lanes of this row read y_I above (same wavefront)
     __asm__ volatile("" ::: "memory");
     y[I * BS + c] = acc;
 }
 
-template <int BS, typename T, int NT, int MB, bool UPPER>
-__device__ __forceinline__ void sweep_pipelined(T *__restrict__ y, int64_t base, int s,
-                                                const int32_t *__restrict__ off, const int32_t *__restrict__ lp,
-                                                const uint16_t *__restrict__ prow, const int32_t *__restrict__ bp,
-                                                const uint16_t *__restrict__ col, const T *__restrict__ val,
-                                                const T *__restrict__ dval, int slot, bool lane_ok, int c) {
+template <int BS, typename TS, typename TC, int MB, bool UPPER>
+__device__ __forceinline__ void sweep_csr(TC *__restrict__ y, int64_t base, int s, const int32_t *__restrict__ off,
+                                          const int32_t *__restrict__ lp, const uint16_t *__restrict__ prow,
+                                          const int32_t *__restrict__ bp, const uint16_t *__restrict__ col,
+                                          const TS *__restrict__ val, const TS *__restrict__ dval, int slot,
+                                          bool lane_ok, int c) {
     const int32_t o = off[s];
     const int nl = off[s + 1] - o - 1;
     if (nl <= 0) return;
@@ -217,52 +211,51 @@ __device__ __forceinline__ void sweep_pipelined(T *__restrict__ y, int64_t base,
         const int32_t p = p0 + slot;
         m.ok = lane_ok && p < p1;
         m.gp = base + p;
-        load_meta<BS, T, MB, UPPER>(prow, bp, m.gp, m.ok, m.I, m.b0, m.nb);
+        if (m.ok) {
+            m.I = prow[m.gp];
+            m.b0 = bp[m.gp];
+            m.nb = bp[m.gp + 1] - m.b0;
+        } else {
+            m.I = 0;
+            m.b0 = 0;
+            m.nb = 0;
+        }
         return m;
     };
-    auto fetch = [&](LevelRegs<BS, T, MB> &R, const LevelMeta &m) {
-        R.ok = m.ok;
-        R.I = m.I;
-        R.b0 = m.b0;
-        R.nb = m.nb;
-        load_vals<BS, T, MB, UPPER>(R, col, val, dval, m.gp, m.ok, c);
-    };
-    // Two register sets, A and B, alternate between "being computed" and
-    // "being filled"; the loop is unrolled by two so that neither is copied
-    // (a copy of a register with a load in flight would wait for the load).
-    LevelRegs<BS, T, MB> A, B;
+    // Two register sets alternate between "being computed" and "being
+    // filled"; the loop is unrolled by two so that neither is copied (a copy
+    // of a register with a load in flight would wait for the load).
+    LevelRegs<BS, TS, MB> A, B;
     LevelMeta mA = meta(0);
-    fetch(A, mA);
+    csr_fetch<BS, TS, MB, UPPER>(A, mA, col, val, dval, c);
     LevelMeta mB;
     mB.ok = false;
     if (nl > 1) mB = meta(1);
     for (int l = 0; l < nl; l += 2) {
-        // level l from A; fill B with level l+1; metadata of level l+2
-        if (l + 1 < nl) fetch(B, mB);
+        if (l + 1 < nl) csr_fetch<BS, TS, MB, UPPER>(B, mB, col, val, dval, c);
         if (l + 2 < nl) mA = meta(l + 2);
-        level_compute<BS, T, MB, UPPER>(y, A, col, val, c);
+        csr_compute<BS, TS, TC, MB, UPPER>(y, A, col, val, c);
         __syncthreads();
         if (l + 1 >= nl) break;
-        // level l+1 from B; fill A with level l+2; metadata of level l+3
-        if (l + 2 < nl) fetch(A, mA);
+        if (l + 2 < nl) csr_fetch<BS, TS, MB, UPPER>(A, mA, col, val, dval, c);
         if (l + 3 < nl) mB = meta(l + 3);
-        level_compute<BS, T, MB, UPPER>(y, B, col, val, c);
+        csr_compute<BS, TS, TC, MB, UPPER>(y, B, col, val, c);
         __syncthreads();
     }
 }
 
-template <int BS, typename T, int NT, int MB>
+template <int BS, typename TS, typename TC, int NT, int MB>
 __global__ __launch_bounds__(NT) void k_dd_apply_pipe(
     const double *__restrict__ r, double *__restrict__ z, int S,
     const int32_t *__restrict__ Loff, const int32_t *__restrict__ Llp, const uint16_t *__restrict__ Lrow,
-    const int32_t *__restrict__ Lbp, const uint16_t *__restrict__ Lcol, const T *__restrict__ Lval,
+    const int32_t *__restrict__ Lbp, const uint16_t *__restrict__ Lcol, const TS *__restrict__ Lval,
     const int32_t *__restrict__ Uoff, const int32_t *__restrict__ Ulp, const uint16_t *__restrict__ Urow,
-    const int32_t *__restrict__ Ubp, const uint16_t *__restrict__ Ucol, const T *__restrict__ Uval,
-    const T *__restrict__ Dval, const int32_t *__restrict__ state) {
+    const int32_t *__restrict__ Ubp, const uint16_t *__restrict__ Ucol, const TS *__restrict__ Uval,
+    const TS *__restrict__ Dval, const int32_t *__restrict__ state) {
     if (state != nullptr && *state != 0) return;
     constexpr int RPW = kWave / BS;
     extern __shared__ unsigned char dd_smem[];
-    T *y = reinterpret_cast<T *>(dd_smem);
+    TC *y = reinterpret_cast<TC *>(dd_smem);
     const int s = blockIdx.x;
     const int64_t base = (int64_t)s * S;
     const int tid = threadIdx.x;
@@ -272,55 +265,218 @@ __global__ __launch_bounds__(NT) void k_dd_apply_pipe(
     const int slot = wave * RPW + rl;
 
     const double *rs = r + base * BS;
-    for (int i = tid; i < S * BS; i += NT) y[i] = static_cast<T>(rs[i]);
+    for (int i = tid; i < S * BS; i += NT) y[i] = static_cast<TC>(rs[i]);
     __syncthreads();
-    sweep_pipelined<BS, T, NT, MB, false>(y, base, s, Loff, Llp, Lrow, Lbp, Lcol, Lval, nullptr, slot, lane_ok, c);
-    sweep_pipelined<BS, T, NT, MB, true>(y, base, s, Uoff, Ulp, Urow, Ubp, Ucol, Uval, Dval, slot, lane_ok, c);
+    sweep_csr<BS, TS, TC, MB, false>(y, base, s, Loff, Llp, Lrow, Lbp, Lcol, Lval, nullptr, slot, lane_ok, c);
+    sweep_csr<BS, TS, TC, MB, true>(y, base, s, Uoff, Ulp, Urow, Ubp, Ucol, Uval, Dval, slot, lane_ok, c);
     double *zs = z + base * BS;
     for (int i = tid; i < S * BS; i += NT) zs[i] = static_cast<double>(y[i]);
 }
 
-int apply_lds_bytes(const dd_ctx *h, int precision) {
-    return h->S * h->bs * (precision == DD_FP32 ? 4 : 8);
+// ------------------------------------------------------------------------
+// Variant 3: slot layout.  Position p's blocks sit in fixed slots
+// p*MB..p*MB+MB-1 (zero blocks pad short rows), and its row and columns sit
+// in one 64-bit descriptor.  No load depends on another load, so the loads of
+// level l+PD are issued while level l computes: PD+1 register sets rotate.
+// The main loop is unrolled by PD+1 (each set keeps its registers) and has no
+// early exit, and every lane issues the same loads in the same order (idle
+// lanes re-read the level's first position; fetches past the last level
+// re-read the last level), so the compiler can count outstanding loads
+// exactly and each level waits only for its own set, not for the whole queue.
+template <int BS, typename TS, int MB>
+struct SlotRegs {
+    bool ok;
+    uint64_t desc;
+    TS v[MB][BS];
+    TS d[BS];
+};
+
+template <int BS, typename TS, int MB, bool UPPER>
+__device__ __forceinline__ void slot_fetch(SlotRegs<BS, TS, MB> &R, int64_t base, int32_t p0, int32_t p1, int slot,
+                                           bool lane_ok, int c, const uint64_t *__restrict__ desc,
+                                           const TS *__restrict__ sval, const TS *__restrict__ dval) {
+    constexpr int BB = BS * BS;
+    const int32_t p = p0 + slot;
+    R.ok = lane_ok && p < p1;
+    const int64_t gp = base + (R.ok ? p : p0);
+    R.desc = desc[gp];
+#pragma unroll
+    for (int k = 0; k < MB; ++k) {
+        const TS *blk = sval + (gp * MB + k) * BB + c * BS;
+#pragma unroll
+        for (int d = 0; d < BS; ++d) R.v[k][d] = blk[d];
+    }
+    if constexpr (UPPER) {
+        const TS *dblk = dval + gp * BB + c * BS;
+#pragma unroll
+        for (int d = 0; d < BS; ++d) R.d[d] = dblk[d];
+    }
 }
 
+template <int BS, typename TS, typename TC, int MB, bool UPPER>
+__device__ __forceinline__ void slot_compute(TC *__restrict__ y, const SlotRegs<BS, TS, MB> &R, int c) {
+    if (!R.ok) return;
+    const int I = (int)(R.desc & 0xffffu);
+    TC acc;
+    if constexpr (UPPER) {
+        acc = 0;
+#pragma unroll
+        for (int d = 0; d < BS; ++d) acc += static_cast<TC>(R.d[d]) * y[I * BS + d];
+    } else {
+        acc = y[I * BS + c];
+    }
+#pragma unroll
+    for (int k = 0; k < MB; ++k) {
+        const int J = (int)((R.desc >> (16 * (k + 1))) & 0xffffu);
+        if (J != 0xffff) {
+#pragma unroll
+            for (int d = 0; d < BS; ++d) acc -= static_cast<TC>(R.v[k][d]) * y[J * BS + d];
+        }
+    }
+    // all lanes of this row read y_I above (same wavefront)
+    __asm__ volatile("" ::: "memory");
+    y[I * BS + c] = acc;
+}
+
+template <int BS, typename TS, typename TC, int MB, int PD, bool UPPER>
+__device__ __forceinline__ void sweep_slots(TC *__restrict__ y, int64_t base, int s, const int32_t *__restrict__ off,
+                                            const int32_t *__restrict__ lp, const uint64_t *__restrict__ desc,
+                                            const TS *__restrict__ sval, const TS *__restrict__ dval, int slot,
+                                            bool lane_ok, int c) {
+    const int32_t o = off[s];
+    const int nl = off[s + 1] - o - 1;
+    SlotRegs<BS, TS, MB> R[PD + 1];
+    auto fetch = [&](SlotRegs<BS, TS, MB> &Rk, int l) {
+        const int lc = l < nl ? l : nl - 1;
+        slot_fetch<BS, TS, MB, UPPER>(Rk, base, lp[o + lc], lp[o + lc + 1], slot, lane_ok, c, desc, sval, dval);
+    };
+#pragma unroll
+    for (int u = 0; u < PD; ++u) fetch(R[u], u);
+    const int nfull = nl - nl % (PD + 1);
+    for (int l0 = 0; l0 < nfull; l0 += PD + 1) {
+#pragma unroll
+        for (int u = 0; u <= PD; ++u) {
+            fetch(R[(u + PD) % (PD + 1)], l0 + u + PD);
+            slot_compute<BS, TS, TC, MB, UPPER>(y, R[u], c);
+            __syncthreads();
+        }
+    }
+    // remaining levels (fewer than PD+1) were fetched by the loop above
+    const int rem = nl - nfull;
+#pragma unroll
+    for (int u = 0; u < PD; ++u) {
+        if (u < rem) {
+            slot_compute<BS, TS, TC, MB, UPPER>(y, R[u], c);
+            __syncthreads();
+        }
+    }
+}
+
+template <int BS, typename TS, typename TC, int NT, int MB, int PD>
+__global__ __launch_bounds__(NT) void k_dd_apply_slots(
+    const double *__restrict__ r, double *__restrict__ z, int S, const int32_t *__restrict__ Loff,
+    const int32_t *__restrict__ Llp, const uint64_t *__restrict__ Ldesc, const TS *__restrict__ Lval,
+    const int32_t *__restrict__ Uoff, const int32_t *__restrict__ Ulp, const uint64_t *__restrict__ Udesc,
+    const TS *__restrict__ Uval, const TS *__restrict__ Dval, const int32_t *__restrict__ state) {
+    if (state != nullptr && *state != 0) return;
+    constexpr int RPW = kWave / BS;
+    extern __shared__ unsigned char dd_smem[];
+    TC *y = reinterpret_cast<TC *>(dd_smem);
+    const int s = blockIdx.x;
+    const int64_t base = (int64_t)s * S;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wave = tid / kWave;
+    const int c = lane % BS, rl = lane / BS;
+    const bool lane_ok = rl < RPW;
+    const int slot = wave * RPW + rl;
+
+    const double *rs = r + base * BS;
+    for (int i = tid; i < S * BS; i += NT) y[i] = static_cast<TC>(rs[i]);
+    __syncthreads();
+    sweep_slots<BS, TS, TC, MB, PD, false>(y, base, s, Loff, Llp, Ldesc, Lval, nullptr, slot, lane_ok, c);
+    sweep_slots<BS, TS, TC, MB, PD, true>(y, base, s, Uoff, Ulp, Udesc, Uval, Dval, slot, lane_ok, c);
+    double *zs = z + base * BS;
+    for (int i = tid; i < S * BS; i += NT) zs[i] = static_cast<double>(y[i]);
+}
+
+// ------------------------------------------------------------------------
+// Host side: variant choice and launch.
 template <typename K>
-static hipError_t allow_full_lds(K kern) {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               163840);
+static hipError_t allow_full_lds(K kern, bool &done) {
+    if (done) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+    if (e == hipSuccess) done = true;
+    return e;
 }
 
-template <int BS, typename T, int NT>
+static bool compute_fp64(int precision) { return precision != DD_FP32; }
+
+int apply_lds_bytes(const dd_ctx *h, int precision) {
+    return h->S * h->bs * (compute_fp64(precision) ? 8 : 4);
+}
+
+template <typename TS>
+static void factor_ptrs(const dd_ctx *h, bool slots, const TS **lv, const TS **uv, const TS **dv) {
+    const Sweep &L = h->sw[0], &U = h->sw[1];
+    if constexpr (sizeof(TS) == 8) {
+        *lv = slots ? L.sval64 : L.val64;
+        *uv = slots ? U.sval64 : U.val64;
+        *dv = U.d64;
+    } else {
+        *lv = slots ? L.sval32 : L.val32;
+        *uv = slots ? U.sval32 : U.val32;
+        *dv = U.d32;
+    }
+}
+
+template <int BS, typename TS, typename TC, int NT, int MB>
+static hipError_t launch_slots(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st) {
+    const TS *lv, *uv, *dv;
+    factor_ptrs<TS>(h, true, &lv, &uv, &dv);
+    constexpr int PD = 2;
+    auto kern = k_dd_apply_slots<BS, TS, TC, NT, MB, PD>;
+    static bool done = false;
+    hipError_t e = allow_full_lds(kern, done);
+    if (e != hipSuccess) return e;
+    const int lds = h->S * BS * (int)sizeof(TC);
+    kern<<<h->nsub, NT, lds, st>>>(r, z, h->S, h->lev[0].off, h->lev[0].ptr, h->sw[0].desc, lv, h->lev[1].off,
+                                   h->lev[1].ptr, h->sw[1].desc, uv, dv, state);
+    return hipGetLastError();
+}
+
+template <int BS, typename TS, typename TC, int NT>
 static hipError_t launch_typed(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st) {
     const Sweep &L = h->sw[0], &U = h->sw[1];
-    const T *lv, *uv, *dv;
-    if constexpr (sizeof(T) == 8) {
-        lv = L.val64; uv = U.val64; dv = U.d64;
-    } else {
-        lv = L.val32; uv = U.val32; dv = U.d32;
-    }
-    const int lds = h->S * BS * (int)sizeof(T);
+    const int lds = h->S * BS * (int)sizeof(TC);
     constexpr int RPP = (kWave / BS) * (NT / kWave);
-    if (h->max_level_width <= RPP && h->use_pipeline) {
-        constexpr int MB = BS == 3 ? 3 : 3;
-        auto kern = k_dd_apply_pipe<BS, T, NT, MB>;
-        static bool attr_done = false;
-        if (!attr_done) {
-            hipError_t e = allow_full_lds(kern);
-            if (e != hipSuccess) return e;
-            attr_done = true;
+    const bool one_pass = h->max_level_width <= RPP;
+    int variant = h->variant;
+    if (variant == 0) variant = h->slots ? 3 : 2;
+    if (variant == 3 && (!one_pass || !h->slots)) variant = 1;
+    if (variant == 2 && !one_pass) variant = 1;
+    if (variant == 3) {
+        switch (h->slots) {
+            case 1: return launch_slots<BS, TS, TC, NT, 1>(h, r, z, state, st);
+            case 2: return launch_slots<BS, TS, TC, NT, 2>(h, r, z, state, st);
+            default: return launch_slots<BS, TS, TC, NT, 3>(h, r, z, state, st);
         }
+    }
+    const TS *lv, *uv, *dv;
+    factor_ptrs<TS>(h, false, &lv, &uv, &dv);
+    if (variant == 2) {
+        auto kern = k_dd_apply_pipe<BS, TS, TC, NT, 3>;
+        static bool done = false;
+        hipError_t e = allow_full_lds(kern, done);
+        if (e != hipSuccess) return e;
         kern<<<h->nsub, NT, lds, st>>>(r, z, h->S, h->lev[0].off, h->lev[0].ptr, L.prow, L.bptr, L.bcol, lv,
                                        h->lev[1].off, h->lev[1].ptr, U.prow, U.bptr, U.bcol, uv, dv, state);
         return hipGetLastError();
     }
-    auto kern = k_dd_apply<BS, T, NT>;
-    static bool attr_done = false;
-    if (!attr_done) {
-        hipError_t e = allow_full_lds(kern);
-        if (e != hipSuccess) return e;
-        attr_done = true;
-    }
+    auto kern = k_dd_apply<BS, TS, TC, NT>;
+    static bool done = false;
+    hipError_t e = allow_full_lds(kern, done);
+    if (e != hipSuccess) return e;
     kern<<<h->nsub, NT, lds, st>>>(r, z, h->S, h->lev[0].off, h->lev[0].ptr, L.prow, L.bptr, L.bcol, lv,
                                    h->lev[1].off, h->lev[1].ptr, U.prow, U.bptr, U.bcol, uv, dv, state);
     return hipGetLastError();
@@ -337,23 +493,28 @@ static int pick_threads(const dd_ctx *h) {
     return nt;
 }
 
-template <int BS, typename T>
+template <int BS, typename TS, typename TC>
 static hipError_t launch_nt(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st) {
     switch (pick_threads(h)) {
-        case 64: return launch_typed<BS, T, 64>(h, r, z, state, st);
-        case 128: return launch_typed<BS, T, 128>(h, r, z, state, st);
-        case 256: return launch_typed<BS, T, 256>(h, r, z, state, st);
-        case 512: return launch_typed<BS, T, 512>(h, r, z, state, st);
-        default: return launch_typed<BS, T, 1024>(h, r, z, state, st);
+        case 64: return launch_typed<BS, TS, TC, 64>(h, r, z, state, st);
+        case 128: return launch_typed<BS, TS, TC, 128>(h, r, z, state, st);
+        case 256: return launch_typed<BS, TS, TC, 256>(h, r, z, state, st);
+        case 512: return launch_typed<BS, TS, TC, 512>(h, r, z, state, st);
+        default: return launch_typed<BS, TS, TC, 1024>(h, r, z, state, st);
+    }
+}
+
+template <int BS>
+static hipError_t launch_bs(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st) {
+    switch (h->precision) {
+        case DD_FP32: return launch_nt<BS, float, float>(h, r, z, state, st);
+        case DD_MIXED: return launch_nt<BS, float, double>(h, r, z, state, st);
+        default: return launch_nt<BS, double, double>(h, r, z, state, st);
     }
 }
 
 hipError_t launch_apply(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st) {
-    if (h->bs == 3)
-        return h->precision == DD_FP32 ? launch_nt<3, float>(h, r, z, state, st)
-                                       : launch_nt<3, double>(h, r, z, state, st);
-    return h->precision == DD_FP32 ? launch_nt<1, float>(h, r, z, state, st)
-                                   : launch_nt<1, double>(h, r, z, state, st);
+    return h->bs == 3 ? launch_bs<3>(h, r, z, state, st) : launch_bs<1>(h, r, z, state, st);
 }
 
 }  // namespace ddilu

@@ -14,6 +14,7 @@ namespace ddilu {
 
 constexpr int kMaxRowBlocks = 64;   // blocks per row accepted by the reorder
 constexpr int kWave = 64;           // CDNA wavefront width
+constexpr int kMaxSlots = 3;        // largest per-row block count of the slot layout
 
 // Streaming layout of one triangular sweep.  Positions are the rows of each
 // subdomain in sweep order (level by level, ascending local row inside a
@@ -29,6 +30,15 @@ struct Sweep {
     double *d64 = nullptr;      // upper only: inv_D per position [n*bb]
     float *d32 = nullptr;
     int64_t nblk = 0;
+    int32_t max_row = 0;        // most blocks of any row in this sweep
+    // Slot layout (when every row has at most kMaxSlots blocks): position p
+    // owns MB consecutive block slots p*MB .. p*MB+MB-1 (MB = the handle's
+    // slot count); unused slots hold zero blocks.  The address of a block is
+    // then a function of the position alone, so a sweep can issue its loads
+    // without first reading row offsets.
+    uint64_t *desc = nullptr;   // [n] local row | column of slot k << 16(k+1); 0xFFFF empty
+    double *sval64 = nullptr;   // [n*MB*bb]
+    float *sval32 = nullptr;
 };
 
 // Level sets of one factor, per subdomain.
@@ -77,7 +87,8 @@ struct dd_ctx {
     int32_t precision = DD_FP64;
     int32_t max_level_width = 0;  // widest level of any subdomain, L or U
     int32_t profile = 0;          // time every apply inside bicgstab_solve
-    int32_t use_pipeline = 1;     // software-pipelined apply when levels fit one pass
+    int32_t slots = 0;            // MB of the slot layout (0: CSR layout only)
+    int32_t variant = 0;          // apply kernel: 0 auto, 1 simple, 2 pipelined CSR, 3 slots
     double *hist = nullptr;       // optional residual history (device, caller-owned)
     int32_t hist_len = 0;
     std::vector<hipEvent_t> events;
@@ -137,6 +148,8 @@ hipError_t launch_bilu0(dd_ctx *h, hipStream_t st);
 hipError_t launch_pack_count(dd_ctx *h, int which, int32_t *cnt, hipStream_t st);
 hipError_t launch_pack_fill(dd_ctx *h, int which, hipStream_t st);
 hipError_t launch_cast32(dd_ctx *h, hipStream_t st);
+hipError_t launch_pack_slots(dd_ctx *h, int which, hipStream_t st);
+hipError_t launch_max_count(int64_t n, const int32_t *cnt, int32_t *out, hipStream_t st);
 hipError_t launch_export_factors(dd_ctx *h, double *f, hipStream_t st);
 
 hipError_t launch_apply(dd_ctx *h, const double *r, double *z, const int32_t *state,

@@ -552,6 +552,75 @@ hipError_t launch_pack_fill(dd_ctx *h, int which, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Slot layout of one sweep: position p owns MB block slots; its blocks fill
+// the first nb slots in ascending column order, zero blocks the rest.  The
+// position's 64-bit descriptor holds its local row in bits 0-15 and the
+// local column of slot k in bits 16(k+1)..16(k+1)+15, 0xFFFF for an empty
+// slot.
+template <int BS>
+__global__ void k_pack_slots(int64_t n, int S, int which, int MB, const int32_t *tptr, const int32_t *tcol,
+                             const double *lu, const double *invd, const int32_t *rows, uint64_t *desc,
+                             double *sval) {
+    constexpr int BB = BS * BS;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int64_t base = (p / S) * (int64_t)S;
+    const int32_t lr = rows[p];
+    const int64_t gi = base + lr;
+    const double *inv = invd + gi * BB;
+    uint64_t dsc = (uint64_t)(uint16_t)lr;
+    int k = 0;
+    for (int32_t q = tptr[gi]; q < tptr[gi + 1] && k < MB; ++q) {
+        const int32_t c = tcol[q];
+        if (which == 0 ? (c < gi) : (c > gi)) {
+            const int64_t slot = p * MB + k;
+            dsc |= (uint64_t)(uint16_t)(c - base) << (16 * (k + 1));
+            if (which == 0) {
+#pragma unroll
+                for (int e = 0; e < BB; ++e) sval[slot * BB + e] = lu[(int64_t)q * BB + e];
+            } else {
+                double t[BB];
+                blk_mul<BS>(inv, lu + (int64_t)q * BB, t);
+#pragma unroll
+                for (int e = 0; e < BB; ++e) sval[slot * BB + e] = t[e];
+            }
+            ++k;
+        }
+    }
+    for (int e = k; e < 3; ++e) dsc |= (uint64_t)0xffffu << (16 * (e + 1));
+    for (; k < MB; ++k) {
+        const int64_t slot = p * MB + k;
+#pragma unroll
+        for (int e = 0; e < BB; ++e) sval[slot * BB + e] = 0.0;
+    }
+    desc[p] = dsc;
+}
+
+// Largest per-row block count of a sweep (integer max, order-free).
+__global__ void k_max_count(int64_t n, const int32_t *cnt, int32_t *out) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) atomicMax(out, cnt[p]);
+}
+
+hipError_t launch_max_count(int64_t n, const int32_t *cnt, int32_t *out, hipStream_t st) {
+    const int T = 256;
+    k_max_count<<<(unsigned)((n + T - 1) / T), T, 0, st>>>(n, cnt, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_slots(dd_ctx *h, int which, hipStream_t st) {
+    const int T = 256;
+    Sweep &w = h->sw[which];
+    const unsigned g = (unsigned)((h->n + T - 1) / T);
+    if (h->bs == 3)
+        k_pack_slots<3><<<g, T, 0, st>>>(h->n, h->S, which, h->slots, h->tptr, h->tcol, h->lu, h->invd,
+                                         h->lev[which].rows, w.desc, w.sval64);
+    else
+        k_pack_slots<1><<<g, T, 0, st>>>(h->n, h->S, which, h->slots, h->tptr, h->tcol, h->lu, h->invd,
+                                         h->lev[which].rows, w.desc, w.sval64);
+    return hipGetLastError();
+}
+
 // FP64 -> FP32 copies, round to nearest even.
 __global__ void k_cast32(int64_t m, const double *in, float *out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -568,6 +637,12 @@ hipError_t launch_cast32(dd_ctx *h, hipStream_t st) {
     }
     const int64_t m = h->n * bb;
     k_cast32<<<(unsigned)((m + T - 1) / T), T, 0, st>>>(m, h->sw[1].d64, h->sw[1].d32);
+    if (h->slots) {
+        for (int w = 0; w < 2; ++w) {
+            const int64_t ms = h->n * h->slots * bb;
+            k_cast32<<<(unsigned)((ms + T - 1) / T), T, 0, st>>>(ms, h->sw[w].sval64, h->sw[w].sval32);
+        }
+    }
     return hipGetLastError();
 }
 

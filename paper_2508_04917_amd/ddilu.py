@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libddilu.so")
 
 DD_OK, DD_EINVAL, DD_ENOTDIV, DD_ELDS, DD_EZEROPIVOT = 0, -1, -2, -3, -4
 DD_EBREAKDOWN, DD_ENOCONV, DD_EHIP, DD_ENOMEM, DD_ESTATE = -5, -6, -7, -8, -9
-DD_FP64, DD_FP32 = 0, 1
+DD_FP64, DD_FP32, DD_MIXED = 0, 1, 2
 
 STATUS_NAMES = {0: "DD_OK", -1: "DD_EINVAL", -2: "DD_ENOTDIV", -3: "DD_ELDS", -4: "DD_EZEROPIVOT",
                 -5: "DD_EBREAKDOWN", -6: "DD_ENOCONV", -7: "DD_EHIP", -8: "DD_ENOMEM", -9: "DD_ESTATE"}
@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "DD_OK", -1: "DD_EINVAL", -2: "DD_ENOTDIV", -3: "DD_ELDS", -4
 # every symbol include/ddilu.h declares
 EXPORTS = ("dd_auto_subdims", "dd_device_caps", "dd_partition", "dd_get_info", "dd_get_partition",
            "dd_get_reordered", "ilu0_factor", "dd_set_precision", "dd_get_levels", "dd_get_factors",
-           "dd_trsv_apply", "dd_spmv", "bicgstab_solve", "dd_set_profiling",
+           "dd_trsv_apply", "dd_spmv", "bicgstab_solve", "dd_set_apply_variant", "dd_set_profiling",
            "dd_set_residual_history", "dd_last_error", "dd_destroy")
 
 
@@ -78,6 +78,7 @@ def lib():
             "dd_trsv_apply": (C.c_int, [vp, vp, vp, vp]),
             "dd_spmv": (C.c_int, [vp, vp, vp, vp]),
             "bicgstab_solve": (C.c_int, [vp, vp, vp, C.c_double, i32, vp, C.POINTER(SolveInfo)]),
+            "dd_set_apply_variant": (C.c_int, [vp, i32]),
             "dd_set_profiling": (C.c_int, [vp, i32]),
             "dd_set_residual_history": (C.c_int, [vp, vp, i32]),
             "dd_last_error": (C.c_char_p, [vp]),
@@ -253,6 +254,10 @@ def bicgstab_solve(h: Handle, b, x=None, rtol=1e-8, maxit=10000, stream=None):
     if rc not in (DD_OK, DD_EBREAKDOWN, DD_ENOCONV):
         raise DDError(rc, dd_last_error(h))
     return x, {k: getattr(si, k) for k, _ in SolveInfo._fields_}
+
+
+def dd_set_apply_variant(h: Handle, variant: int):
+    _check(lib().dd_set_apply_variant(h.ptr, variant), h)
 
 
 def dd_set_profiling(h: Handle, on: bool):

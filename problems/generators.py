@@ -139,10 +139,12 @@ def lognormal_problem(nx: int, ny: int, nz: int, seed: int, sigma: float = 2.0,
     white noise of the field, H (nnzb-n,3,3) in CSR order of the off-diagonal
     blocks, then b ~ N(0,1) (3n).
 
-    Face value k_f = 2 k_a k_b / (k_a + k_b) times the axis multiplier aniso[axis];
-    A_IJ = -k_f I + noise * k_f * H_IJ (noise relative to k_f);
-    A_II = (sum of k_f over its faces + sum over boundary faces of 2 k_I aniso[axis]) I
-    (Dirichlet boundary at the half cell).
+    Face value k_f = 2 k_a k_b / (k_a + k_b) times the axis multiplier aniso[axis].
+    Coupling block B_IJ = k_f (I - noise * H_IJ) (noise relative to k_f, drawn
+    independently for (I,J) and (J,I), so A is nonsymmetric); A_IJ = -B_IJ.
+    Diagonal block A_II = sum_J B_IJ + (sum over boundary faces of 2 k_I
+    aniso[axis]) I: every interior block row sums to zero (flux conservation),
+    and the Dirichlet boundary at the half cell makes the operator nonsingular.
     """
     ptr, col, kind = stencil_pattern(nx, ny, nz)
     n = nx * ny * nz
@@ -160,6 +162,8 @@ def lognormal_problem(nx: int, ny: int, nz: int, seed: int, sigma: float = 2.0,
     kb = kcell[col[off]]
     mult = np.asarray(aniso, dtype=np.float64)[KIND_AXIS[kind[off]]]
     kf = mult * 2.0 * ka * kb / (ka + kb)
+    eye = np.eye(3)
+    B = kf[:, None, None] * (eye - noise * H)
 
     # boundary faces: each missing neighbour of a cell contributes 2 k_I aniso[axis]
     g = np.arange(n, dtype=np.int64)
@@ -170,12 +174,14 @@ def lognormal_problem(nx: int, ny: int, nz: int, seed: int, sigma: float = 2.0,
     nb_missing = ((i == 0).astype(np.float64) + (i == nx - 1)) * ax[0] \
         + ((j == 0).astype(np.float64) + (j == ny - 1)) * ax[1] \
         + ((k == 0).astype(np.float64) + (k == nz - 1)) * ax[2]
-    dsum = np.bincount(rows[off], weights=kf, minlength=n) + 2.0 * kcell * nb_missing
+    diag = np.zeros((n, 3, 3))
+    for e in range(9):
+        diag.reshape(n, 9)[:, e] = np.bincount(rows[off], weights=B.reshape(-1, 9)[:, e], minlength=n)
+    diag += (2.0 * kcell * nb_missing)[:, None, None] * eye
 
     val = np.empty((nnzb, 3, 3), dtype=np.float64)
-    eye = np.eye(3)
-    val[off] = kf[:, None, None] * (-eye + noise * H)
-    val[~off] = dsum[:, None, None] * eye
+    val[off] = -B
+    val[~off] = diag
     meta = {"sigma": sigma, "corr_len": corr_len, "aniso": tuple(aniso), "noise": noise}
     return Problem(name, nx, ny, nz, 3, ptr, col, val, b, seed, meta)
 
