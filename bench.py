@@ -56,6 +56,45 @@ def measured_traffic(workload, sub):
     return rec.get("bytes_per_apply")
 
 
+def kernels_only(args, p, sub, ptr_d, col_d, val_d, dd, torch):
+    """A plain device copy of known size (the reference for scaling hardware
+    byte counters), then bursts of applies in each precision, each burst
+    timed with events on the stream the library launches on."""
+    copy_elems = 1 << 28  # 2 GiB of FP64 read + 2 GiB written
+    src = torch.ones(copy_elems, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    out = {"copy_bytes_read": copy_elems * 8, "copy_bytes_written": copy_elems * 8}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for _ in range(2):
+        dst.copy_(src)
+    ev[0].record()
+    for _ in range(3):
+        dst.copy_(src)
+    ev[1].record()
+    torch.cuda.synchronize()
+    out["copy_us"] = 1e3 * ev[0].elapsed_time(ev[1]) / 3
+    out["copy_GBs"] = 2 * copy_elems * 8 / (out["copy_us"] * 1e-6) / 1e9
+    del src, dst
+    h = dd.dd_partition(p.nx, p.ny, p.nz, p.bs, ptr_d, col_d, val_d, sub=sub)
+    dd.ilu0_factor(h, dd.DD_FP64)
+    r = torch.randn(p.n * p.bs, dtype=torch.float64, device="cuda:0")
+    z = torch.empty_like(r)
+    for name, prec in (("fp64", dd.DD_FP64), ("mixed", dd.DD_MIXED), ("fp32", dd.DD_FP32)):
+        dd.dd_set_precision(h, prec)
+        dd.dd_trsv_apply(h, r, z)
+        ev[0].record()
+        for _ in range(args.applies):
+            dd.dd_trsv_apply(h, r, z)
+        ev[1].record()
+        torch.cuda.synchronize()
+        us = 1e3 * ev[0].elapsed_time(ev[1]) / args.applies
+        nbytes = dd.dd_get_info(h)["apply_bytes"]
+        out[name] = {"us_per_apply": round(us, 2), "bytes_per_apply": nbytes, "GB/s": round(nbytes / us / 1e3, 1)}
+        log(f"{name}: {us:.1f} us per apply, {nbytes / us / 1e3:.1f} GB/s")
+    h.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +106,10 @@ def main():
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--cpu-applies", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="full", choices=["full", "kernels"],
+                    help="kernels: only a copy kernel of known size and bursts of applies "
+                         "(the short program the rocprofv3 counter runs profile)")
+    ap.add_argument("--applies", type=int, default=10)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -92,6 +135,10 @@ def main():
     b_d = torch.as_tensor(p.b, device=dev)
     n_cu, lds = dd.dd_device_caps()
     log(f"device: {n_cu} CUs, {lds} B LDS per workgroup; n={p.n} nnzb={p.nnzb}")
+
+    if args.mode == "kernels":
+        kernels_only(args, p, sub, ptr_d, col_d, val_d, dd, torch)
+        return
 
     def step():
         rec = {}

@@ -61,6 +61,15 @@ def lib():
             "o_spmv": (None, [i64, C.c_int, vp, vp, vp, vp, vp]),
             "o_bicgstab": (C.c_int, [i64, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp,
                                      C.c_double, i32, vp, vp, vp]),
+            "o_lic_nparam": (i64, []),
+            "o_cut_faces": (i64, [i64, i64, vp, vp, vp, vp, vp]),
+            "o_lic_features": (None, [i64, vp, vp, vp, vp, vp, vp, vp]),
+            "o_mlp_forward": (None, [i64, vp, vp, vp, vp, vp]),
+            "o_mlp_backward": (None, [i64, vp, vp, vp, vp, vp, vp]),
+            "o_lic_correct": (None, [i64, i64, vp, vp, vp, vp, vp]),
+            "o_lic_dC": (None, [i64, i64, vp, vp, C.c_int, vp, vp, vp]),
+            "o_adam": (None, [i64, vp, vp, vp, vp, C.c_int, C.c_double, C.c_double, C.c_double,
+                              C.c_double]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -362,3 +371,123 @@ def setup(problem, sub):
     f = ildu0(n, bs, tptr, tcol, lu)
     return OracleSetup(n, bs, tuple(sub), S, nsub, pid, n2o, o2n, aptr, acol, aval,
                        tptr, tcol, tval, lu, f)
+
+
+# ------------------------------------------ learned interface correction
+# An addition to the paper's method (the paper has no learned component):
+# a per-face MLP 27 -> 64 -> 64 -> 9 maps scale-normalised local blocks
+# [A_II, A_IJ, A_JJ] of each cut face (I, J) to a 3x3 C_f, and the
+# preconditioner becomes z = M_DD^{-1} (r + C r).  It is trained by
+# regression onto the global ILU0 apply (the same reordered matrix without
+# the drop) on probe vectors.
+LIC_NPARAM = 6537
+
+
+def cut_faces(n, S, ptr, col):
+    """Directed cut pairs (I, J) = the dropped blocks, CSR order: (fI, fJ, fq)."""
+    ptr, col = _i32(ptr), _i32(col)
+    m = lib().o_cut_faces(n, S, _p(ptr), _p(col), None, None, None)
+    fI, fJ, fq = (np.empty(m, dtype=np.int32) for _ in range(3))
+    lib().o_cut_faces(n, S, _p(ptr), _p(col), _p(fI), _p(fJ), _p(fq))
+    return fI, fJ, fq
+
+
+def lic_features(ptr, col, val, faces):
+    fI, fJ, fq = faces
+    X = np.empty((fI.shape[0], 27))
+    lib().o_lic_features(fI.shape[0], _p(_i32(ptr)), _p(_i32(col)), _p(_f64(val)), _p(fI), _p(fJ),
+                         _p(fq), _p(X))
+    return X
+
+
+def mlp_forward(P, X):
+    P, X = _f64(P), _f64(X)
+    nf = X.shape[0]
+    H1, H2, OUT = np.empty((nf, 64)), np.empty((nf, 64)), np.empty((nf, 9))
+    lib().o_mlp_forward(nf, _p(P), _p(X), _p(H1), _p(H2), _p(OUT))
+    return H1, H2, OUT
+
+
+def mlp_backward(P, X, H1, H2, dOUT):
+    dP = np.zeros(LIC_NPARAM)
+    lib().o_mlp_backward(X.shape[0], _p(_f64(P)), _p(_f64(X)), _p(_f64(H1)), _p(_f64(H2)),
+                         _p(_f64(dOUT)), _p(dP))
+    return dP
+
+
+def lic_correct(n, faces, C, r):
+    fI, fJ, _ = faces
+    r = _f64(r)
+    rt = np.empty_like(r)
+    lib().o_lic_correct(n, fI.shape[0], _p(fI), _p(fJ), _p(_f64(C)), _p(r), _p(rt))
+    return rt
+
+
+def lic_dC(n, faces, A, R):
+    fI, fJ, _ = faces
+    A, R = _f64(A), _f64(R)
+    dC = np.empty((fI.shape[0], 3, 3))
+    lib().o_lic_dC(n, fI.shape[0], _p(fI), _p(fJ), A.shape[0], _p(A), _p(R), _p(dC))
+    return dC
+
+
+def adam(P, G, M, V, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In place on P, M, V (float64 arrays)."""
+    lib().o_adam(P.shape[0], _p(P), _p(_f64(G)), _p(M), _p(V), t, lr, b1, b2, eps)
+
+
+class LicOracle:
+    """Learned-correction pieces on one problem's oracle setup."""
+
+    def __init__(self, st: "OracleSetup"):
+        if st.bs != 3:
+            raise ValueError("the learned correction is defined for 3x3 blocks")
+        self.st = st
+        self.faces = cut_faces(st.n, st.S, st.aptr, st.acol)
+        self.X = lic_features(st.aptr, st.acol, st.aval, self.faces)
+        self._glob = None
+
+    @property
+    def nf(self):
+        return self.faces[0].shape[0]
+
+    def coeffs(self, P):
+        return mlp_forward(P, self.X)[2].reshape(-1, 3, 3)
+
+    def apply(self, C, r):
+        """z = M_DD^{-1} (r + C r)."""
+        return self.st.apply(lic_correct(self.st.n, self.faces, C, r))
+
+    def global_factors(self):
+        """ILU0 + ILDU0 of the full reordered matrix (no drop), same ordering."""
+        if self._glob is None:
+            st = self.st
+            lu = bilu0(st.n, 3, st.aptr, st.acol, st.aval)
+            self._glob = ildu0(st.n, 3, st.aptr, st.acol, lu)
+        return self._glob
+
+    def apply_global(self, r):
+        return apply(self.st.n, 3, self.st.aptr, self.st.acol, self.global_factors(), r)
+
+    def loss_and_grad(self, P, R, Zstar, den, want_grad=True):
+        """Loss = mean over probes q of ||z_q - z*_q||^2 / den_q with
+        z_q = M_DD^{-1}(r_q + C r_q), den_q = ||z_DD,q - z*_q||^2; and its
+        gradient with respect to the MLP parameters:
+        g_q = 2 (z_q - z*_q) / (Q den_q), a_q = M_DD^{-T} g_q,
+        dL/dC_f = sum_q a_q[I] r_q[J]^T, then backpropagation."""
+        st = self.st
+        H1, H2, OUT = mlp_forward(P, self.X)
+        C = OUT.reshape(-1, 3, 3)
+        Q = R.shape[0]
+        loss = 0.0
+        A = np.empty_like(R)
+        for q in range(Q):
+            z = self.apply(C, R[q])
+            e = z - Zstar[q]
+            loss += (e @ e) / den[q] / Q
+            if want_grad:
+                A[q] = apply_transpose(st.n, 3, st.tptr, st.tcol, st.f, 2.0 * e / (Q * den[q]))
+        if not want_grad:
+            return loss, None
+        dC = lic_dC(st.n, self.faces, A, R)
+        return loss, mlp_backward(P, self.X, H1, H2, dC.reshape(-1, 9))

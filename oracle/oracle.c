@@ -549,3 +549,158 @@ done:
     free(r); free(r0); free(p); free(ph); free(v); free(s); free(sh); free(t);
     return status;
 }
+
+/* ================================================================== */
+/* Learned interface correction (an addition to the paper's method;   */
+/* the paper has no learned component).                               */
+/*                                                                    */
+/* Faces are the directed cut pairs (I, J): the blocks A_IJ of the     */
+/* full reordered matrix whose row and column lie in different         */
+/* subdomains, i.e. exactly the blocks the drop of Section 3.2         */
+/* removes, listed in CSR order.  Each face gets a 3x3 coefficient     */
+/* C_f from a small MLP, and the preconditioner becomes                */
+/* z = M_DD^{-1} (r + C r) with (C r)_I = sum_{f=(I,J)} C_f r_J: still */
+/* a fixed linear operator once C is set.                              */
+/* ================================================================== */
+
+#define LIC_IN 27
+#define LIC_H 64
+#define LIC_OUT 9
+/* parameter layout: W1[64][27] b1[64] W2[64][64] b2[64] W3[9][64] b3[9] */
+#define LIC_W1 0
+#define LIC_B1 (LIC_W1 + LIC_H * LIC_IN)
+#define LIC_W2 (LIC_B1 + LIC_H)
+#define LIC_B2 (LIC_W2 + LIC_H * LIC_H)
+#define LIC_W3 (LIC_B2 + LIC_H)
+#define LIC_B3 (LIC_W3 + LIC_OUT * LIC_H)
+#define LIC_NPARAM (LIC_B3 + LIC_OUT)
+
+int64_t o_lic_nparam(void) { return LIC_NPARAM; }
+
+/* Cut faces in CSR order of the full reordered matrix.  With fI == NULL it
+ * only counts.  fq[f] is the block's position in (ptr, col, val). */
+int64_t o_cut_faces(int64_t n, int64_t S, const int32_t *ptr, const int32_t *col,
+                    int32_t *fI, int32_t *fJ, int32_t *fq) {
+    int64_t m = 0;
+    for (int64_t I = 0; I < n; ++I)
+        for (int64_t q = ptr[I]; q < ptr[I + 1]; ++q)
+            if (col[q] / S != I / S) {
+                if (fI) { fI[m] = (int32_t)I; fJ[m] = col[q]; fq[m] = (int32_t)q; }
+                ++m;
+            }
+    return m;
+}
+
+/* Features x_f = [A_II, A_IJ, A_JJ] / sigma_f (three 3x3 blocks, row-major),
+ * sigma_f = sqrt(|tr A_II| |tr A_JJ|) / 3. */
+void o_lic_features(int64_t nf, const int32_t *ptr, const int32_t *col, const double *val,
+                    const int32_t *fI, const int32_t *fJ, const int32_t *fq, double *X) {
+    for (int64_t f = 0; f < nf; ++f) {
+        int64_t dI = find_col(ptr, col, fI[f], fI[f]);
+        int64_t dJ = find_col(ptr, col, fJ[f], fJ[f]);
+        const double *Aii = val + dI * 9, *Aij = val + (int64_t)fq[f] * 9, *Ajj = val + dJ * 9;
+        double ti = Aii[0] + Aii[4] + Aii[8], tj = Ajj[0] + Ajj[4] + Ajj[8];
+        double sigma = sqrt(fabs(ti) * fabs(tj)) / 3.0;
+        double *x = X + f * LIC_IN;
+        for (int e = 0; e < 9; ++e) {
+            x[e] = Aii[e] / sigma;
+            x[9 + e] = Aij[e] / sigma;
+            x[18 + e] = Ajj[e] / sigma;
+        }
+    }
+}
+
+/* h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), out = W3 h2 + b3 (per face). */
+void o_mlp_forward(int64_t nf, const double *P, const double *X, double *H1, double *H2, double *OUT) {
+    for (int64_t f = 0; f < nf; ++f) {
+        const double *x = X + f * LIC_IN;
+        double *h1 = H1 + f * LIC_H, *h2 = H2 + f * LIC_H, *o = OUT + f * LIC_OUT;
+        for (int i = 0; i < LIC_H; ++i) {
+            double s = P[LIC_B1 + i];
+            for (int k = 0; k < LIC_IN; ++k) s += P[LIC_W1 + i * LIC_IN + k] * x[k];
+            h1[i] = s > 0.0 ? s : 0.0;
+        }
+        for (int i = 0; i < LIC_H; ++i) {
+            double s = P[LIC_B2 + i];
+            for (int k = 0; k < LIC_H; ++k) s += P[LIC_W2 + i * LIC_H + k] * h1[k];
+            h2[i] = s > 0.0 ? s : 0.0;
+        }
+        for (int i = 0; i < LIC_OUT; ++i) {
+            double s = P[LIC_B3 + i];
+            for (int k = 0; k < LIC_H; ++k) s += P[LIC_W3 + i * LIC_H + k] * h2[k];
+            o[i] = s;
+        }
+    }
+}
+
+/* Backpropagation of dOUT (per face) through the MLP, summed over faces
+ * into dP (which the caller zeroes).  ReLU'(0) is taken as 0. */
+void o_mlp_backward(int64_t nf, const double *P, const double *X, const double *H1, const double *H2,
+                    const double *dOUT, double *dP) {
+    double g2[LIC_H], g1[LIC_H];
+    for (int64_t f = 0; f < nf; ++f) {
+        const double *x = X + f * LIC_IN, *h1 = H1 + f * LIC_H, *h2 = H2 + f * LIC_H;
+        const double *d = dOUT + f * LIC_OUT;
+        for (int i = 0; i < LIC_OUT; ++i) {
+            dP[LIC_B3 + i] += d[i];
+            for (int k = 0; k < LIC_H; ++k) dP[LIC_W3 + i * LIC_H + k] += d[i] * h2[k];
+        }
+        for (int k = 0; k < LIC_H; ++k) {
+            double s = 0.0;
+            for (int i = 0; i < LIC_OUT; ++i) s += P[LIC_W3 + i * LIC_H + k] * d[i];
+            g2[k] = h2[k] > 0.0 ? s : 0.0;
+        }
+        for (int i = 0; i < LIC_H; ++i) {
+            dP[LIC_B2 + i] += g2[i];
+            for (int k = 0; k < LIC_H; ++k) dP[LIC_W2 + i * LIC_H + k] += g2[i] * h1[k];
+        }
+        for (int k = 0; k < LIC_H; ++k) {
+            double s = 0.0;
+            for (int i = 0; i < LIC_H; ++i) s += P[LIC_W2 + i * LIC_H + k] * g2[i];
+            g1[k] = h1[k] > 0.0 ? s : 0.0;
+        }
+        for (int i = 0; i < LIC_H; ++i) {
+            dP[LIC_B1 + i] += g1[i];
+            for (int k = 0; k < LIC_IN; ++k) dP[LIC_W1 + i * LIC_IN + k] += g1[i] * x[k];
+        }
+    }
+}
+
+/* r~ = r + C r:  r~_I = r_I + sum over faces f = (I, J) of C_f r_J
+ * (faces visited in their CSR order). */
+void o_lic_correct(int64_t n, int64_t nf, const int32_t *fI, const int32_t *fJ, const double *C,
+                   const double *r, double *rt) {
+    memcpy(rt, r, sizeof(double) * (size_t)(n * 3));
+    for (int64_t f = 0; f < nf; ++f)
+        for (int a = 0; a < 3; ++a) {
+            double s = 0.0;
+            for (int b = 0; b < 3; ++b) s += C[f * 9 + a * 3 + b] * r[(int64_t)fJ[f] * 3 + b];
+            rt[(int64_t)fI[f] * 3 + a] += s;
+        }
+}
+
+/* dC_f = sum over probes q of a_q[I] r_q[J]^T, with A and R holding nq
+ * vectors of length 3n each (probe-major). */
+void o_lic_dC(int64_t n, int64_t nf, const int32_t *fI, const int32_t *fJ, int nq, const double *A,
+              const double *R, double *dC) {
+    for (int64_t f = 0; f < nf; ++f)
+        for (int e = 0; e < 9; ++e) dC[f * 9 + e] = 0.0;
+    for (int q = 0; q < nq; ++q)
+        for (int64_t f = 0; f < nf; ++f)
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    dC[f * 9 + a * 3 + b] += A[(int64_t)q * 3 * n + (int64_t)fI[f] * 3 + a] *
+                                             R[(int64_t)q * 3 * n + (int64_t)fJ[f] * 3 + b];
+}
+
+/* One Adam step (Kingma & Ba): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps). */
+void o_adam(int64_t np, double *P, const double *G, double *M, double *V, int t, double lr, double b1,
+            double b2, double eps) {
+    double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
+    for (int64_t i = 0; i < np; ++i) {
+        M[i] = b1 * M[i] + (1.0 - b1) * G[i];
+        V[i] = b2 * V[i] + (1.0 - b2) * G[i] * G[i];
+        P[i] -= lr * (M[i] / c1) / (sqrt(V[i] / c2) + eps);
+    }
+}

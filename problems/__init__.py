@@ -15,6 +15,7 @@ from .generators import (  # noqa: F401
     lognormal_problem,
     training_problem,
     probe_vectors,
+    lic_init_params,
     WORKLOADS,
     make_workload,
 )

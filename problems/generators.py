@@ -199,6 +199,18 @@ def probe_vectors(seed: int, n_probes: int, size: int) -> np.ndarray:
     return out
 
 
+def lic_init_params(seed: int = 0) -> np.ndarray:
+    """Initial parameters of the 27 -> 64 -> 64 -> 9 interface MLP (6,537 values,
+    layout W1[64][27] b1[64] W2[64][64] b2[64] W3[9][64] b3[9]): He-normal
+    W1 and W2 from default_rng(seed), zero biases, and W3 = b3 = 0 so that the
+    untrained correction is exactly zero."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.standard_normal((64, 27)) * np.sqrt(2.0 / 27)
+    W2 = rng.standard_normal((64, 64)) * np.sqrt(2.0 / 64)
+    return np.concatenate([W1.ravel(), np.zeros(64), W2.ravel(), np.zeros(64), np.zeros(9 * 64),
+                           np.zeros(9)])
+
+
 # Named workloads: (generator, kwargs, default subdomain dims or None = automatic rule)
 WORKLOADS = {
     # scalar 7-point Laplacian, 16^3, eight 8^3 subdomains
