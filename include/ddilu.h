@@ -225,6 +225,96 @@ int dd_set_profiling(dd_handle h, int32_t on);
  * recording. */
 int dd_set_residual_history(dd_handle h, double *hist, int32_t len);
 
+/* ---------------------------------------------------------------------
+ * Global (undecomposed) ILU0 of the full reordered matrix: what the
+ * decomposition approximates (Section 4, the rocSPARSE ILU0 the paper
+ * compares with, here as our own level-scheduled kernels: one launch per
+ * level over the whole matrix, vector in global memory).
+ * --------------------------------------------------------------------- */
+
+/* Level sets, block ILU0 and ILDU0 form of the full reordered matrix (no
+ * drop).  Synchronises; DD_EZEROPIVOT on a singular pivot block. */
+int dd_global_factor(dd_handle h, void *hip_stream);
+
+/* z = M_global^{-1} r for nrhs right-hand sides stored one after another
+ * (device double[nrhs*n*bs] each, reordered order, r != z). */
+int dd_global_apply(dd_handle h, const double *r, double *z, int32_t nrhs,
+                    void *hip_stream);
+
+/* Preconditioner of bicgstab_solve: 0 = the domain-decomposed ILU0 apply
+ * (default), 1 = the global ILU0 apply (needs dd_global_factor). */
+int dd_set_preconditioner(dd_handle h, int32_t kind);
+
+/* ---------------------------------------------------------------------
+ * Learned interface correction (an addition to the paper's method; the
+ * paper has no learned component).  Faces are the directed cut pairs
+ * (I, J): the blocks A_IJ the drop removes, in CSR order of the reordered
+ * matrix.  Per face a 27 -> 64 -> 64 -> 9 ReLU MLP (FP32; parameters
+ * W1[64][27] b1[64] W2[64][64] b2[64] W3[9][64] b3[9], 6,537 floats)
+ * maps x_f = [A_II, A_IJ, A_JJ] / sigma_f (blocks row-major,
+ * sigma_f = sqrt(|tr A_II| |tr A_JJ|) / 3) to C_f (3x3, row-major), and
+ * dd_trsv_apply / bicgstab_solve use z = M_DD^{-1} (r + C r) with
+ * (C r)_I = sum over faces (I, J) of C_f r_J: a fixed linear operator.
+ * Requires 3x3 blocks, rows of at most 3 blocks per triangle and a
+ * structurally symmetric pattern (DD_EINVAL otherwise).
+ * --------------------------------------------------------------------- */
+
+/* Faces, features and the transposed factor streams of the adjoint apply
+ * (after ilu0_factor).  The correction stays off until lic_set_params or
+ * lic_set_coeffs. */
+int lic_setup(dd_handle h, void *hip_stream);
+
+/* nf: host, number of faces.  fI, fJ (device int32[nf], reordered rows and
+ * columns), X (device float[nf*27], features); each may be NULL. */
+int lic_get_faces(dd_handle h, int32_t *nf, int32_t *fI, int32_t *fJ, float *X,
+                  void *hip_stream);
+
+/* Evaluate the MLP (device float params[6537]) on every face and switch the
+ * correction on; params = NULL switches it off (plain DD-ILU0). */
+int lic_set_params(dd_handle h, const float *params, void *hip_stream);
+
+/* Set the coefficients directly (device float[nf*9]); NULL switches the
+ * correction off. */
+int lic_set_coeffs(dd_handle h, const float *C, void *hip_stream);
+
+/* Copy the current coefficients (device float[nf*9]). */
+int lic_get_coeffs(dd_handle h, float *C, void *hip_stream);
+
+/* a = M_DD^{-T} g (transposed factors, FP64; device double[n*3],
+ * reordered order, g != a).  Needs lic_setup. */
+int dd_apply_adjoint(dd_handle h, const double *g, double *a, void *hip_stream);
+
+/* Regression targets for nq probe vectors R (device double[nq*n*3]):
+ * Zs = M_global^{-1} r_q and den_q = ||M_DD^{-1} r_q - Zs_q||^2 (device
+ * double[nq*n*3] and double[nq]).  Needs dd_global_factor and lic_setup. */
+int lic_targets(dd_handle h, int32_t nq, const double *R, double *Zs, double *den,
+                void *hip_stream);
+
+/* Loss and gradient of one problem:
+ * loss += mean_q ||z_q - Zs_q||^2 / den_q with z_q = M_DD^{-1}(r_q + C r_q),
+ * C from params; grad (device float[6537]) = (accumulate ? grad : 0) +
+ * d loss / d params, through g_q = 2 (z_q - Zs_q) / (nq den_q),
+ * a_q = M_DD^{-T} g_q, dC_f = sum_q a_q[I] r_q[J]^T and backpropagation.
+ * loss: device double[1]. */
+int lic_loss_grad(dd_handle h, const float *params, int32_t nq, const double *R,
+                  const double *Zs, const double *den, double *loss, float *grad,
+                  int32_t accumulate, void *hip_stream);
+
+/* One Adam step (Kingma & Ba) on nparam device floats, step number t >= 1. */
+int lic_adam(float *params, const float *grad, float *m, float *v, int32_t nparam,
+             int32_t t, float lr, float b1, float b2, float eps, void *hip_stream);
+
+/* Training loop: for every epoch, one lic_loss_grad + Adam step (lr,
+ * beta = 0.9/0.999, eps = 1e-8) per problem, problems visited in the order
+ * order[epoch*nprob + k] (host int32).  hs, R, Zs, den: host arrays of nprob
+ * handles / device pointers (each problem's nq probes, targets and
+ * denominators).  params, m, v: device float[6537], updated in place.
+ * loss_hist: host double[epochs] (mean loss per epoch), may be NULL. */
+int lic_train(dd_handle *hs, int32_t nprob, const double *const *R,
+              const double *const *Zs, const double *const *den, int32_t nq,
+              float *params, float *m, float *v, int32_t epochs,
+              const int32_t *order, float lr, double *loss_hist, void *hip_stream);
+
 /* Message of the last failed call on h (or of the last failure before a
  * handle existed when h is NULL).  Owned by the library. */
 const char *dd_last_error(dd_handle h);

@@ -491,6 +491,144 @@ extern "C" int dd_set_residual_history(dd_handle h, double *hist, int32_t len) {
     return DD_OK;
 }
 
+// ------------------------------------------------------------- global ILU0
+extern "C" int dd_global_factor(dd_handle h, void *hip_stream) {
+    if (!h) return set_global_error(DD_EINVAL, "dd_global_factor: null handle");
+    return global_factor(h, as_stream(hip_stream));
+}
+
+extern "C" int dd_global_apply(dd_handle h, const double *r, double *z, int32_t nrhs, void *hip_stream) {
+    if (!h) return set_global_error(DD_EINVAL, "dd_global_apply: null handle");
+    if (!h->gfactored) return h->fail(DD_ESTATE, "dd_global_apply before dd_global_factor");
+    if (!r || !z || r == z || nrhs < 1) return h->fail(DD_EINVAL, "dd_global_apply: bad arguments");
+    HCHK(launch_global_apply(h, r, z, nrhs, as_stream(hip_stream)));
+    return DD_OK;
+}
+
+extern "C" int dd_set_preconditioner(dd_handle h, int32_t kind) {
+    if (!h) return set_global_error(DD_EINVAL, "dd_set_preconditioner: null handle");
+    if (kind != 0 && kind != 1) return h->fail(DD_EINVAL, "dd_set_preconditioner: kind must be 0 or 1");
+    if (kind == 1 && !h->gfactored) return h->fail(DD_ESTATE, "global preconditioner before dd_global_factor");
+    h->pc_kind = kind;
+    return DD_OK;
+}
+
+// ------------------------------------------------------- learned correction
+extern "C" int lic_setup(dd_handle h, void *hip_stream) {
+    if (!h) return set_global_error(DD_EINVAL, "lic_setup: null handle");
+    return ddilu::lic_setup(h, as_stream(hip_stream));
+}
+
+extern "C" int lic_get_faces(dd_handle h, int32_t *nf, int32_t *fI, int32_t *fJ, float *X, void *hip_stream) {
+    if (!h) return set_global_error(DD_EINVAL, "lic_get_faces: null handle");
+    if (!h->lic.ready) return h->fail(DD_ESTATE, "lic_get_faces before lic_setup");
+    hipStream_t st = as_stream(hip_stream);
+    const int64_t m = h->lic.nf;
+    if (nf) *nf = (int32_t)m;
+    if (fI && m) HCHK(hipMemcpyAsync(fI, h->lic.fI, m * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    if (fJ && m) HCHK(hipMemcpyAsync(fJ, h->lic.fJ, m * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    if (X && m) HCHK(hipMemcpyAsync(X, h->lic.X, m * 27 * sizeof(float), hipMemcpyDeviceToDevice, st));
+    return DD_OK;
+}
+
+extern "C" int lic_set_params(dd_handle h, const float *params, void *hip_stream) {
+    if (!h) return set_global_error(DD_EINVAL, "lic_set_params: null handle");
+    if (!params) {
+        h->lic.active = 0;
+        return DD_OK;
+    }
+    if (!h->lic.ready) return h->fail(DD_ESTATE, "lic_set_params before lic_setup");
+    RCHK(ddilu::lic_coeffs_from_params(h, params, false, as_stream(hip_stream)));
+    h->lic.active = 1;
+    return DD_OK;
+}
+
+extern "C" int lic_set_coeffs(dd_handle h, const float *C, void *hip_stream) {
+    if (!h) return set_global_error(DD_EINVAL, "lic_set_coeffs: null handle");
+    if (!C) {
+        h->lic.active = 0;
+        return DD_OK;
+    }
+    if (!h->lic.ready) return h->fail(DD_ESTATE, "lic_set_coeffs before lic_setup");
+    if (h->lic.nf)
+        HCHK(hipMemcpyAsync(h->lic.C, C, (size_t)h->lic.nf * 9 * sizeof(float), hipMemcpyDeviceToDevice,
+                            as_stream(hip_stream)));
+    h->lic.active = 1;
+    return DD_OK;
+}
+
+extern "C" int lic_get_coeffs(dd_handle h, float *C, void *hip_stream) {
+    if (!h) return set_global_error(DD_EINVAL, "lic_get_coeffs: null handle");
+    if (!h->lic.ready || !C) return h->fail(DD_ESTATE, "lic_get_coeffs before lic_setup");
+    if (h->lic.nf)
+        HCHK(hipMemcpyAsync(C, h->lic.C, (size_t)h->lic.nf * 9 * sizeof(float), hipMemcpyDeviceToDevice,
+                            as_stream(hip_stream)));
+    return DD_OK;
+}
+
+extern "C" int dd_apply_adjoint(dd_handle h, const double *g, double *a, void *hip_stream) {
+    if (!h) return set_global_error(DD_EINVAL, "dd_apply_adjoint: null handle");
+    if (!h->lic.ready) return h->fail(DD_ESTATE, "dd_apply_adjoint before lic_setup");
+    if (!g || !a || g == a) return h->fail(DD_EINVAL, "dd_apply_adjoint: bad arguments");
+    HCHK(launch_apply_adjoint(h, g, a, as_stream(hip_stream)));
+    return DD_OK;
+}
+
+extern "C" int lic_targets(dd_handle h, int32_t nq, const double *R, double *Zs, double *den, void *hip_stream) {
+    if (!h) return set_global_error(DD_EINVAL, "lic_targets: null handle");
+    if (!h->gfactored || !h->lic.ready) return h->fail(DD_ESTATE, "lic_targets needs dd_global_factor and lic_setup");
+    if (nq < 1 || !R || !Zs || !den) return h->fail(DD_EINVAL, "lic_targets: bad arguments");
+    return ddilu::lic_targets_run(h, nq, R, Zs, den, as_stream(hip_stream));
+}
+
+extern "C" int lic_loss_grad(dd_handle h, const float *params, int32_t nq, const double *R, const double *Zs,
+                             const double *den, double *loss, float *grad, int32_t accumulate, void *hip_stream) {
+    if (!h) return set_global_error(DD_EINVAL, "lic_loss_grad: null handle");
+    if (!h->lic.ready) return h->fail(DD_ESTATE, "lic_loss_grad before lic_setup");
+    if (nq < 1 || !params || !R || !Zs || !den || !loss || !grad) return h->fail(DD_EINVAL, "lic_loss_grad: bad arguments");
+    return ddilu::lic_loss_grad_run(h, params, nq, R, Zs, den, loss, grad, accumulate, as_stream(hip_stream));
+}
+
+extern "C" int lic_adam(float *params, const float *grad, float *m, float *v, int32_t nparam, int32_t t, float lr,
+                        float b1, float b2, float eps, void *hip_stream) {
+    if (!params || !grad || !m || !v || nparam < 1 || t < 1) return set_global_error(DD_EINVAL, "lic_adam: bad arguments");
+    hipError_t e = launch_adam(nparam, params, grad, m, v, t, lr, b1, b2, eps, as_stream(hip_stream));
+    if (e != hipSuccess) return set_global_error(DD_EHIP, "lic_adam: %s", hipGetErrorString(e));
+    return DD_OK;
+}
+
+extern "C" int lic_train(dd_handle *hs, int32_t nprob, const double *const *R, const double *const *Zs,
+                         const double *const *den, int32_t nq, float *params, float *m, float *v, int32_t epochs,
+                         const int32_t *order, float lr, double *loss_hist, void *hip_stream) {
+    if (!hs || nprob < 1 || !R || !Zs || !den || nq < 1 || !params || !m || !v || epochs < 0 || !order)
+        return set_global_error(DD_EINVAL, "lic_train: bad arguments");
+    hipStream_t st = as_stream(hip_stream);
+    float *grad = nullptr;
+    double *lacc = nullptr;
+    hipError_t e = hipMalloc(&grad, 6537 * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&lacc, sizeof(double));
+    if (e != hipSuccess) return set_global_error(DD_ENOMEM, "lic_train: %s", hipGetErrorString(e));
+    int rc = DD_OK, t = 0;
+    for (int ep = 0; ep < epochs && rc == DD_OK; ++ep) {
+        e = hipMemsetAsync(lacc, 0, sizeof(double), st);
+        for (int k = 0; k < nprob && rc == DD_OK && e == hipSuccess; ++k) {
+            const int p = order[(int64_t)ep * nprob + k];
+            if (p < 0 || p >= nprob) { rc = set_global_error(DD_EINVAL, "lic_train: bad order entry"); break; }
+            rc = ddilu::lic_loss_grad_run(hs[p], params, nq, R[p], Zs[p], den[p], lacc, grad, 0, st);
+            if (rc) { g_err = hs[p]->err; break; }
+            e = launch_adam(6537, params, grad, m, v, ++t, lr, 0.9f, 0.999f, 1e-8f, st);
+        }
+        double l = 0.0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&l, lacc, sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess && rc == DD_OK) rc = set_global_error(DD_EHIP, "lic_train: %s", hipGetErrorString(e));
+        if (loss_hist) loss_hist[ep] = l / nprob;
+    }
+    (void)hipFree(grad);
+    (void)hipFree(lacc);
+    return rc;
+}
+
 extern "C" const char *dd_last_error(dd_handle h) { return h ? h->err.c_str() : g_err.c_str(); }
 
 extern "C" void dd_destroy(dd_handle h) { delete h; }

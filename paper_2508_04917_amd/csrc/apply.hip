@@ -20,18 +20,55 @@
 // DD_MIXED, float for DD_FP32).  Input r and output z are always FP64.
 #include "internal.h"
 
+// Prefetch depth (levels loaded ahead) of the slot-layout kernel, per factor
+// storage type: deeper for FP32 blocks, which take half the registers.
+#ifndef DDILU_PD64
+#define DDILU_PD64 2
+#endif
+#ifndef DDILU_PD32
+#define DDILU_PD32 3
+#endif
+
 namespace ddilu {
+
+// Learned interface correction inside the apply: once the subdomain's r is
+// in LDS, every row with cut faces adds sum_f C_f r_J (J in a neighbouring
+// subdomain, read from r in global memory; faces in CSR order).  One lane per
+// (row, component), so the update order is fixed.
+struct LicArgs {
+    const int32_t *bsub, *brow, *fptr, *fJ;
+    const float *C;
+};
+
+template <int BS, typename TC>
+__device__ __forceinline__ void lic_correct_lds(TC *__restrict__ y, const double *__restrict__ r, int64_t base, int s,
+                                                const LicArgs &la, int tid, int nt) {
+    const int32_t b0 = la.bsub[s], b1 = la.bsub[s + 1];
+    for (int item = tid; item < (b1 - b0) * BS; item += nt) {
+        const int k = item / BS, c = item % BS;
+        const int64_t gi = la.brow[b0 + k];
+        double acc = 0.0;
+        for (int32_t f = la.fptr[gi]; f < la.fptr[gi + 1]; ++f) {
+            const int64_t J = la.fJ[f];
+            const float *Cf = la.C + (int64_t)f * BS * BS + c * BS;
+#pragma unroll
+            for (int d = 0; d < BS; ++d) acc += (double)Cf[d] * r[J * BS + d];
+        }
+        y[(gi - base) * BS + c] += static_cast<TC>(acc);
+    }
+    __syncthreads();
+}
 
 // ------------------------------------------------------------------------
 // Variant 1: plain level loop (levels of any width, rows of any length).
-template <int BS, typename TS, typename TC, int NT>
+template <int BS, typename TS, typename TC, int NT, bool LIC>
 __global__ __launch_bounds__(NT) void k_dd_apply(
     const double *__restrict__ r, double *__restrict__ z, int S,
     const int32_t *__restrict__ Loff, const int32_t *__restrict__ Llp, const uint16_t *__restrict__ Lrow,
     const int32_t *__restrict__ Lbp, const uint16_t *__restrict__ Lcol, const TS *__restrict__ Lval,
     const int32_t *__restrict__ Uoff, const int32_t *__restrict__ Ulp, const uint16_t *__restrict__ Urow,
     const int32_t *__restrict__ Ubp, const uint16_t *__restrict__ Ucol, const TS *__restrict__ Uval,
-    const TS *__restrict__ Dval, const int32_t *__restrict__ state) {
+    const TS *__restrict__ Dval, const int32_t *__restrict__ state, LicArgs la) {
     if (state != nullptr && *state != 0) return;  // enclosing solve already finished
     constexpr int BB = BS * BS;
     constexpr int RPW = kWave / BS;          // block rows per wavefront
@@ -49,6 +86,7 @@ __global__ __launch_bounds__(NT) void k_dd_apply(
     const double *rs = r + base * BS;
     for (int i = tid; i < S * BS; i += NT) y[i] = static_cast<TC>(rs[i]);
     __syncthreads();
+    if constexpr (LIC) lic_correct_lds<BS, TC>(y, r, base, s, la, tid, NT);
 
     // lower sweep: y_I = r_I - sum_{J<I} L_IJ y_J
     {
@@ -372,12 +410,12 @@ __device__ __forceinline__ void sweep_slots(TC *__restrict__ y, int64_t base, in
     }
 }
 
-template <int BS, typename TS, typename TC, int NT, int MB, int PD>
+template <int BS, typename TS, typename TC, int NT, int MB, int PD, bool LIC>
 __global__ __launch_bounds__(NT) void k_dd_apply_slots(
     const double *__restrict__ r, double *__restrict__ z, int S, const int32_t *__restrict__ Loff,
     const int32_t *__restrict__ Llp, const uint64_t *__restrict__ Ldesc, const TS *__restrict__ Lval,
     const int32_t *__restrict__ Uoff, const int32_t *__restrict__ Ulp, const uint64_t *__restrict__ Udesc,
-    const TS *__restrict__ Uval, const TS *__restrict__ Dval, const int32_t *__restrict__ state) {
+    const TS *__restrict__ Uval, const TS *__restrict__ Dval, const int32_t *__restrict__ state, LicArgs la) {
     if (state != nullptr && *state != 0) return;
     constexpr int RPW = kWave / BS;
     extern __shared__ unsigned char dd_smem[];
@@ -393,6 +431,7 @@ __global__ __launch_bounds__(NT) void k_dd_apply_slots(
     const double *rs = r + base * BS;
     for (int i = tid; i < S * BS; i += NT) y[i] = static_cast<TC>(rs[i]);
     __syncthreads();
+    if constexpr (LIC) lic_correct_lds<BS, TC>(y, r, base, s, la, tid, NT);
     sweep_slots<BS, TS, TC, MB, PD, false>(y, base, s, Loff, Llp, Ldesc, Lval, nullptr, slot, lane_ok, c);
     sweep_slots<BS, TS, TC, MB, PD, true>(y, base, s, Uoff, Ulp, Udesc, Uval, Dval, slot, lane_ok, c);
     double *zs = z + base * BS;
@@ -430,19 +469,32 @@ static void factor_ptrs(const dd_ctx *h, bool slots, const TS **lv, const TS **u
     }
 }
 
-template <int BS, typename TS, typename TC, int NT, int MB>
-static hipError_t launch_slots(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st) {
-    const TS *lv, *uv, *dv;
-    factor_ptrs<TS>(h, true, &lv, &uv, &dv);
-    constexpr int PD = 2;
-    auto kern = k_dd_apply_slots<BS, TS, TC, NT, MB, PD>;
+static LicArgs lic_args(const dd_ctx *h) {
+    return LicArgs{h->lic.bsub, h->lic.brow, h->lic.fptr, h->lic.fJ, h->lic.C};
+}
+
+template <int BS, typename TS, typename TC, int NT, int MB, bool LIC>
+static hipError_t launch_slots(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st,
+                               const TS *lv, const TS *uv, const TS *dv) {
+    constexpr int PD = sizeof(TS) == 8 ? DDILU_PD64 : DDILU_PD32;
+    auto kern = k_dd_apply_slots<BS, TS, TC, NT, MB, PD, LIC>;
     static bool done = false;
     hipError_t e = allow_full_lds(kern, done);
     if (e != hipSuccess) return e;
     const int lds = h->S * BS * (int)sizeof(TC);
     kern<<<h->nsub, NT, lds, st>>>(r, z, h->S, h->lev[0].off, h->lev[0].ptr, h->sw[0].desc, lv, h->lev[1].off,
-                                   h->lev[1].ptr, h->sw[1].desc, uv, dv, state);
+                                   h->lev[1].ptr, h->sw[1].desc, uv, dv, state, lic_args(h));
     return hipGetLastError();
+}
+
+template <int BS, typename TS, typename TC, int NT, bool LIC>
+static hipError_t launch_slots_mb(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st,
+                                  const TS *lv, const TS *uv, const TS *dv) {
+    switch (h->slots) {
+        case 1: return launch_slots<BS, TS, TC, NT, 1, LIC>(h, r, z, state, st, lv, uv, dv);
+        case 2: return launch_slots<BS, TS, TC, NT, 2, LIC>(h, r, z, state, st, lv, uv, dv);
+        default: return launch_slots<BS, TS, TC, NT, 3, LIC>(h, r, z, state, st, lv, uv, dv);
+    }
 }
 
 template <int BS, typename TS, typename TC, int NT>
@@ -451,16 +503,17 @@ static hipError_t launch_typed(dd_ctx *h, const double *r, double *z, const int3
     const int lds = h->S * BS * (int)sizeof(TC);
     constexpr int RPP = (kWave / BS) * (NT / kWave);
     const bool one_pass = h->max_level_width <= RPP;
+    const bool lic = BS == 3 && h->lic.active;
     int variant = h->variant;
     if (variant == 0) variant = h->slots ? 3 : 2;
     if (variant == 3 && (!one_pass || !h->slots)) variant = 1;
-    if (variant == 2 && !one_pass) variant = 1;
+    if (variant == 2 && (!one_pass || lic)) variant = 1;
     if (variant == 3) {
-        switch (h->slots) {
-            case 1: return launch_slots<BS, TS, TC, NT, 1>(h, r, z, state, st);
-            case 2: return launch_slots<BS, TS, TC, NT, 2>(h, r, z, state, st);
-            default: return launch_slots<BS, TS, TC, NT, 3>(h, r, z, state, st);
-        }
+        const TS *lv, *uv, *dv;
+        factor_ptrs<TS>(h, true, &lv, &uv, &dv);
+        if constexpr (BS == 3)
+            if (lic) return launch_slots_mb<BS, TS, TC, NT, true>(h, r, z, state, st, lv, uv, dv);
+        return launch_slots_mb<BS, TS, TC, NT, false>(h, r, z, state, st, lv, uv, dv);
     }
     const TS *lv, *uv, *dv;
     factor_ptrs<TS>(h, false, &lv, &uv, &dv);
@@ -473,13 +526,22 @@ static hipError_t launch_typed(dd_ctx *h, const double *r, double *z, const int3
                                        h->lev[1].off, h->lev[1].ptr, U.prow, U.bptr, U.bcol, uv, dv, state);
         return hipGetLastError();
     }
-    auto kern = k_dd_apply<BS, TS, TC, NT>;
+    auto launch_simple = [&](auto kern, bool &done) -> hipError_t {
+        hipError_t e = allow_full_lds(kern, done);
+        if (e != hipSuccess) return e;
+        kern<<<h->nsub, NT, lds, st>>>(r, z, h->S, h->lev[0].off, h->lev[0].ptr, L.prow, L.bptr, L.bcol, lv,
+                                       h->lev[1].off, h->lev[1].ptr, U.prow, U.bptr, U.bcol, uv, dv, state,
+                                       lic_args(h));
+        return hipGetLastError();
+    };
+    if constexpr (BS == 3) {
+        if (lic) {
+            static bool done_l = false;
+            return launch_simple(k_dd_apply<BS, TS, TC, NT, true>, done_l);
+        }
+    }
     static bool done = false;
-    hipError_t e = allow_full_lds(kern, done);
-    if (e != hipSuccess) return e;
-    kern<<<h->nsub, NT, lds, st>>>(r, z, h->S, h->lev[0].off, h->lev[0].ptr, L.prow, L.bptr, L.bcol, lv,
-                                   h->lev[1].off, h->lev[1].ptr, U.prow, U.bptr, U.bcol, uv, dv, state);
-    return hipGetLastError();
+    return launch_simple(k_dd_apply<BS, TS, TC, NT, false>, done);
 }
 
 // Workgroup size: enough wavefronts to cover the widest level in one pass,
@@ -515,6 +577,32 @@ static hipError_t launch_bs(dd_ctx *h, const double *r, double *z, const int32_t
 
 hipError_t launch_apply(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st) {
     return h->bs == 3 ? launch_bs<3>(h, r, z, state, st) : launch_bs<1>(h, r, z, state, st);
+}
+
+// a = M_DD^{-T} g: the slot kernel run on the transposed factor streams (FP64,
+// no correction); needs 3x3 blocks, the slot layout and one-pass levels.
+template <int NT>
+static hipError_t launch_adjoint_nt(dd_ctx *h, const double *g, double *a, hipStream_t st) {
+    constexpr int RPP = (kWave / 3) * (NT / kWave);
+    if (h->max_level_width > RPP) return hipErrorInvalidValue;
+    const double *lv = h->lic.adj_val[0], *uv = h->lic.adj_val[1], *dv = h->lic.adj_d;
+    return launch_slots_mb<3, double, double, NT, false>(h, g, a, nullptr, st, lv, uv, dv);
+}
+
+hipError_t launch_apply_adjoint(dd_ctx *h, const double *g, double *a, hipStream_t st) {
+    if (h->bs != 3 || !h->slots || !h->lic.ready) return hipErrorInvalidValue;
+    switch (pick_threads(h)) {
+        case 64: return launch_adjoint_nt<64>(h, g, a, st);
+        case 128: return launch_adjoint_nt<128>(h, g, a, st);
+        case 256: return launch_adjoint_nt<256>(h, g, a, st);
+        case 512: return launch_adjoint_nt<512>(h, g, a, st);
+        default: return launch_adjoint_nt<1024>(h, g, a, st);
+    }
+}
+
+hipError_t launch_precond(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st) {
+    if (h->pc_kind == 1) return launch_global_apply(h, r, z, 1, st);
+    return launch_apply(h, r, z, state, st);
 }
 
 }  // namespace ddilu

@@ -52,6 +52,26 @@ struct Levels {
     int32_t max_levels = 0;
 };
 
+// Learned interface correction state (faces, features, coefficients, and
+// the training workspace).
+struct Lic {
+    int32_t ready = 0, active = 0;
+    int32_t nf = 0, nb = 0;       // faces; rows with at least one face
+    int32_t *fptr = nullptr;      // [n+1] faces of each row (CSR order)
+    int32_t *fI = nullptr, *fJ = nullptr, *fq = nullptr;  // [nf] row, column, block position in A
+    int32_t *diag = nullptr;      // [n] diagonal block position of each row of A
+    int32_t *brow = nullptr;      // [nb] rows with faces, ascending
+    int32_t *bsub = nullptr;      // [nsub+1] first entry of brow of each subdomain
+    float *X = nullptr;           // [nf*27] features
+    float *C = nullptr;           // [nf*9] coefficients
+    float *H1 = nullptr, *H2 = nullptr, *G1 = nullptr, *G2 = nullptr, *dC = nullptr;
+    double *wpart = nullptr, *rpart = nullptr;
+    double *Z = nullptr, *G = nullptr, *A = nullptr;
+    int32_t work_q = 0;
+    double *adj_val[2] = {nullptr, nullptr};  // transposed slot streams (U^T lower, L^T upper)
+    double *adj_d = nullptr;                  // inv_D^T per upper position
+};
+
 // Device scalars of one BiCGSTAB run (all FP64 except the control words).
 struct KrylovScalars {
     double rho, alpha, omega, beta;
@@ -90,6 +110,14 @@ struct dd_ctx {
     int32_t slots = 0;            // MB of the slot layout (0: CSR layout only)
     int32_t variant = 0;          // apply kernel: 0 auto, 1 simple, 2 pipelined CSR, 3 slots
     double *hist = nullptr;       // optional residual history (device, caller-owned)
+    ddilu::Lic lic;
+    int32_t pc_kind = 0;          // preconditioner of bicgstab_solve: 0 DD-ILU0, 1 global ILU0
+    // global (undecomposed) ILU0 of the full reordered matrix
+    int32_t *glev[2] = {nullptr, nullptr};
+    int32_t gnlev[2] = {0, 0};
+    int32_t *gdiag = nullptr;
+    double *glu = nullptr, *ginvd = nullptr, *gf = nullptr;
+    int32_t gfactored = 0;
     int32_t hist_len = 0;
     std::vector<hipEvent_t> events;
     // scratch
@@ -98,7 +126,8 @@ struct dd_ctx {
     int64_t scan_tmp_len = 0;
     // Krylov workspace (allocated on first solve)
     double *kv = nullptr;       // 9 vectors of n*bs
-    double *partials = nullptr; // [kMaxPartials * 3]
+    double *partials = nullptr; // [8 * spmv_part_stride] per-workgroup partial sums
+    int32_t spmv_part_stride = 0;
     ddilu::KrylovScalars *ks = nullptr;
     ddilu::KrylovScalars *ks_host = nullptr;  // pinned
     std::vector<void *> allocs;
@@ -162,4 +191,21 @@ hipError_t launch_permute(int64_t n, int bs, const int32_t *map, const double *i
                           hipStream_t st);
 int bicgstab_run(dd_ctx *h, const double *b, double *x, double rtol, int32_t maxit,
                  hipStream_t st, dd_solve_info *info);
+
+// global ILU0
+int global_factor(dd_ctx *h, hipStream_t st);
+hipError_t launch_global_apply(dd_ctx *h, const double *r, double *z, int nrhs, hipStream_t st);
+hipError_t launch_diag_positions(dd_ctx *h, int32_t *diag, hipStream_t st);
+
+// learned correction
+int lic_setup(dd_ctx *h, hipStream_t st);
+int lic_coeffs_from_params(dd_ctx *h, const float *params, bool keep_hidden, hipStream_t st);
+int lic_loss_grad_run(dd_ctx *h, const float *params, int Q, const double *R, const double *Zs, const double *den,
+                      double *loss, float *grad, int accumulate, hipStream_t st);
+int lic_targets_run(dd_ctx *h, int Q, const double *R, double *Zs, double *den, hipStream_t st);
+hipError_t launch_adam(int np, float *P, const float *G, float *M, float *V, int t, float lr, float b1, float b2,
+                       float eps, hipStream_t st);
+hipError_t launch_apply_adjoint(dd_ctx *h, const double *g, double *a, hipStream_t st);
+// the preconditioner bicgstab_solve uses (DD apply, or the global ILU0 apply)
+hipError_t launch_precond(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st);
 }  // namespace ddilu

@@ -29,9 +29,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Sums NV values over the workgroup in a fixed order and writes them to
-// out[k*kMaxGrid + blockIdx.x].
+// out[k*stride + blockIdx.x].
 template <int NV>
-__device__ __forceinline__ void block_partials(double (&v)[NV], double *out) {
+__device__ __forceinline__ void block_partials(double (&v)[NV], double *out, int stride) {
     __shared__ double sh[NV][16];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
@@ -45,25 +45,48 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double *out) {
         for (int k = 0; k < NV; ++k) {
             double t = 0.0;
             for (int i = 0; i < nw; ++i) t += sh[k][i];
-            out[k * kMaxGrid + blockIdx.x] = t;
+            out[k * stride + blockIdx.x] = t;
         }
     }
 }
 
 // --------------------------------------------------------------- SpMV
 // BS lanes of one wavefront per block row, lane c computes component c.
+// The first kUnroll blocks of a row are loaded with predicated, unrolled
+// loads (all issued before any is used), longer rows finish in a loop.
+constexpr int kUnroll = 8;
+
 template <int BS>
 __device__ __forceinline__ double bsr_row(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
                                           const double *__restrict__ val, const double *__restrict__ x,
                                           int64_t row, int c) {
     constexpr int BB = BS * BS;
+    const int32_t b0 = ptr[row], b1 = ptr[row + 1];
+    const int nb = b1 - b0;
+    int64_t J[kUnroll];
+    double v[kUnroll][BS];
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) {
+        if (k < nb) {
+            J[k] = col[b0 + k];
+            const double *blk = val + (int64_t)(b0 + k) * BB + c * BS;
+#pragma unroll
+            for (int d = 0; d < BS; ++d) v[k][d] = blk[d];
+        }
+    }
     double acc = 0.0;
-    const int32_t b1 = ptr[row + 1];
-    for (int32_t b = ptr[row]; b < b1; ++b) {
-        const int64_t J = col[b];
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) {
+        if (k < nb) {
+#pragma unroll
+            for (int d = 0; d < BS; ++d) acc += v[k][d] * x[J[k] * BS + d];
+        }
+    }
+    for (int32_t b = b0 + kUnroll; b < b1; ++b) {
+        const int64_t Jb = col[b];
         const double *blk = val + (int64_t)b * BB + c * BS;
 #pragma unroll
-        for (int d = 0; d < BS; ++d) acc += blk[d] * x[J * BS + d];
+        for (int d = 0; d < BS; ++d) acc += blk[d] * x[Jb * BS + d];
     }
     return acc;
 }
@@ -90,10 +113,10 @@ hipError_t launch_spmv(dd_ctx *h, const double *x, double *y, hipStream_t st) {
     return hipGetLastError();
 }
 
-// y = A x, grid-stride over wavefront row groups; partials of w.y (and y.y
-// when NV == 2, or w2.y ... see mode).  mode 0: v = A p^, dot r0.v.
-// mode 1: t = A s^, dots t.s and t.t.  mode 2: t = A x, r = b - t (init),
-// dots r.r and b.b.  mode 3: t = A x, dot (b-t).(b-t) (true residual).
+// y = A x, one wavefront per 64/BS block rows, one workgroup partial sum per
+// dot product.  mode 0: v = A p^, dot r0.v.  mode 1: t = A s^, dots t.s and
+// t.t.  mode 2: t = A x, r = b - t (init), dots r.r and b.b.  mode 3:
+// t = A x, dot (b-t).(b-t) (true residual).
 template <int BS, int MODE>
 __global__ __launch_bounds__(kRedT) void k_spmv_dots(int64_t n, const int32_t *__restrict__ ptr,
                                                     const int32_t *__restrict__ col,
@@ -101,42 +124,40 @@ __global__ __launch_bounds__(kRedT) void k_spmv_dots(int64_t n, const int32_t *_
                                                     double *__restrict__ y, const double *__restrict__ w,
                                                     double *__restrict__ r_out, double *__restrict__ r0_out,
                                                     double *__restrict__ p_out, double *__restrict__ part,
-                                                    const int32_t *__restrict__ state) {
+                                                    int part_stride, const int32_t *__restrict__ state) {
     if (state != nullptr && *state != ST_RUN) return;
     constexpr int RPW = kWave / BS;
     constexpr int NV = MODE == 0 ? 1 : (MODE == 3 ? 1 : 2);
     const int lane = threadIdx.x & 63;
     const int c = lane % BS;
-    const int64_t nwaves_total = ((int64_t)gridDim.x * blockDim.x) >> 6;
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    for (int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; gw * RPW < n; gw += nwaves_total) {
-        const int64_t row = gw * RPW + lane / BS;
-        if (lane / BS < RPW && row < n) {
-            const int64_t e = row * BS + c;
-            const double t = bsr_row<BS>(ptr, col, val, x, row, c);
-            if constexpr (MODE == 0) {
-                y[e] = t;
-                acc[0] += w[e] * t;
-            } else if constexpr (MODE == 1) {
-                y[e] = t;
-                acc[0] += t * w[e];
-                acc[1] += t * t;
-            } else if constexpr (MODE == 2) {
-                const double rr = w[e] - t;
-                r_out[e] = rr;
-                r0_out[e] = rr;
-                p_out[e] = rr;
-                acc[0] += rr * rr;
-                acc[1] += w[e] * w[e];
-            } else {
-                const double rr = w[e] - t;
-                acc[0] += rr * rr;
-            }
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t row = gw * RPW + lane / BS;
+    if (lane / BS < RPW && row < n) {
+        const int64_t e = row * BS + c;
+        const double t = bsr_row<BS>(ptr, col, val, x, row, c);
+        if constexpr (MODE == 0) {
+            y[e] = t;
+            acc[0] += w[e] * t;
+        } else if constexpr (MODE == 1) {
+            y[e] = t;
+            acc[0] += t * w[e];
+            acc[1] += t * t;
+        } else if constexpr (MODE == 2) {
+            const double rr = w[e] - t;
+            r_out[e] = rr;
+            r0_out[e] = rr;
+            p_out[e] = rr;
+            acc[0] += rr * rr;
+            acc[1] += w[e] * w[e];
+        } else {
+            const double rr = w[e] - t;
+            acc[0] += rr * rr;
         }
     }
-    block_partials<NV>(acc, part);
+    block_partials<NV>(acc, part, part_stride);
 }
 
 // s = r - alpha v; partial s.s
@@ -151,7 +172,7 @@ __global__ __launch_bounds__(kRedT) void k_axpy_s(int64_t m, const double *__res
         s[i] = t;
         acc[0] += t * t;
     }
-    block_partials<1>(acc, part);
+    block_partials<1>(acc, part, kMaxGrid);
 }
 
 // x += alpha p^ when the half step converged
@@ -179,7 +200,7 @@ __global__ __launch_bounds__(kRedT) void k_update(int64_t m, double *__restrict_
         acc[0] += rn * rn;
         acc[1] += r0[i] * rn;
     }
-    block_partials<2>(acc, part);
+    block_partials<2>(acc, part, kMaxGrid);
 }
 
 // p = r + beta (p - omega v)
@@ -192,10 +213,10 @@ __global__ __launch_bounds__(kRedT) void k_pupdate(int64_t m, double *__restrict
 }
 
 // Fixed-order sum of nblk partials of slot k.
-__device__ double reduce_slot(const double *part, int k, int nblk) {
+__device__ double reduce_slot(const double *part, int k, int nblk, int stride) {
     __shared__ double sh[kRedT];
     double t = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += kRedT) t += part[k * kMaxGrid + i];
+    for (int i = threadIdx.x; i < nblk; i += kRedT) t += part[(int64_t)k * stride + i];
     sh[threadIdx.x] = t;
     __syncthreads();
     for (int w = kRedT / 2; w > 0; w >>= 1) {
@@ -210,12 +231,13 @@ __device__ double reduce_slot(const double *part, int k, int nblk) {
 enum : int { SC_INIT = 0, SC_ALPHA = 1, SC_S = 2, SC_OMEGA = 3, SC_BETA = 4, SC_TRUE = 5 };
 
 // Scalar steps of Algorithm 1 (one workgroup).
-__global__ __launch_bounds__(kRedT) void k_scalars(int stage, int it, const double *part, int nblk,
+__global__ __launch_bounds__(kRedT) void k_scalars(int stage, int it, const double *part, int nblk, int stride,
                                                   KrylovScalars *ks, double *hist, int hist_len) {
     const int32_t st0 = ks->state;
     if (stage != SC_INIT && stage != SC_TRUE && st0 != ST_RUN) return;
-    const double a = reduce_slot(part, 0, nblk);
-    const double b = (stage == SC_INIT || stage == SC_OMEGA || stage == SC_BETA) ? reduce_slot(part, 1, nblk) : 0.0;
+    const double a = reduce_slot(part, 0, nblk, stride);
+    const double b = (stage == SC_INIT || stage == SC_OMEGA || stage == SC_BETA) ? reduce_slot(part, 1, nblk, stride)
+                                                                                   : 0.0;
     if (threadIdx.x != 0) return;
     switch (stage) {
         case SC_INIT: {  // a = r.r (= r0.r), b = b.b
@@ -321,8 +343,9 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
     const int32_t *state = &ks->state;
 
     const int rpb = (kWave / BS) * (kRedT / kWave);
-    const int gsp = (int)std::min<int64_t>((n + rpb - 1) / rpb, kMaxGrid);
+    const int gsp = (int)((n + rpb - 1) / rpb);  // one partial per SpMV workgroup
     const int gvec = (int)std::min<int64_t>((m + kRedT - 1) / kRedT, kMaxGrid);
+    const int sps = h->spmv_part_stride;
 
     hipEvent_t e0, e1;
     KCHK(hipEventCreate(&e0));
@@ -338,8 +361,8 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
     KCHK(launch_permute(n, BS, h->new2old, b, bp, st));
     KCHK(launch_permute(n, BS, h->new2old, x, xp, st));
     // r = b - A x0, r0 = p = r; rho = r0.r
-    k_spmv_dots<BS, 2><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, xp, t, bp, r, r0, p, part, nullptr);
-    k_scalars<<<1, kRedT, 0, st>>>(SC_INIT, 0, part, gsp, ks, h->hist, h->hist_len);
+    k_spmv_dots<BS, 2><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, xp, t, bp, r, r0, p, part, sps, nullptr);
+    k_scalars<<<1, kRedT, 0, st>>>(SC_INIT, 0, part, gsp, sps, ks, h->hist, h->hist_len);
     KCHK(hipGetLastError());
 
     const int chunk = 8;
@@ -378,22 +401,22 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
         for (int k = 0; k < todo; ++k) {
             ++it;
             if (h->profile) KCHK(hipEventRecord(h->events[4 * k], st));
-            KCHK(launch_apply(h, p, ph, state, st));                       // p^ = M^{-1} p
+            KCHK(launch_precond(h, p, ph, state, st));                       // p^ = M^{-1} p
             if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 1], st));
             k_spmv_dots<BS, 0><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, ph, v, r0, nullptr,
-                                                      nullptr, nullptr, part, state);  // v = A p^, r0.v
-            k_scalars<<<1, kRedT, 0, st>>>(SC_ALPHA, it, part, gsp, ks, h->hist, h->hist_len);
+                                                      nullptr, nullptr, part, sps, state);  // v = A p^, r0.v
+            k_scalars<<<1, kRedT, 0, st>>>(SC_ALPHA, it, part, gsp, sps, ks, h->hist, h->hist_len);
             k_axpy_s<<<gvec, kRedT, 0, st>>>(m, r, v, s, ks, part);        // s = r - alpha v
-            k_scalars<<<1, kRedT, 0, st>>>(SC_S, it, part, gvec, ks, h->hist, h->hist_len);
+            k_scalars<<<1, kRedT, 0, st>>>(SC_S, it, part, gvec, kMaxGrid, ks, h->hist, h->hist_len);
             k_half<<<gvec, kRedT, 0, st>>>(m, xp, ph, ks);
             if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 2], st));
-            KCHK(launch_apply(h, s, shat, state, st));                     // s^ = M^{-1} s
+            KCHK(launch_precond(h, s, shat, state, st));                     // s^ = M^{-1} s
             if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 3], st));
             k_spmv_dots<BS, 1><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, shat, t, s, nullptr,
-                                                      nullptr, nullptr, part, state);  // t = A s^, t.s, t.t
-            k_scalars<<<1, kRedT, 0, st>>>(SC_OMEGA, it, part, gsp, ks, h->hist, h->hist_len);
+                                                      nullptr, nullptr, part, sps, state);  // t = A s^, t.s, t.t
+            k_scalars<<<1, kRedT, 0, st>>>(SC_OMEGA, it, part, gsp, sps, ks, h->hist, h->hist_len);
             k_update<<<gvec, kRedT, 0, st>>>(m, xp, ph, shat, r, s, t, r0, ks, part);
-            k_scalars<<<1, kRedT, 0, st>>>(SC_BETA, it, part, gvec, ks, h->hist, h->hist_len);
+            k_scalars<<<1, kRedT, 0, st>>>(SC_BETA, it, part, gvec, kMaxGrid, ks, h->hist, h->hist_len);
             k_pupdate<<<gvec, kRedT, 0, st>>>(m, p, r, v, ks);
             k_half_to_conv<<<1, 1, 0, st>>>(ks);
             KCHK(hipGetLastError());
@@ -402,8 +425,8 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
     KCHK(hipEventRecord(e1, st));
     // true residual ||b - A x|| / ||b||
     k_spmv_dots<BS, 3><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, xp, t, bp, nullptr, nullptr, nullptr,
-                                              part, nullptr);
-    k_scalars<<<1, kRedT, 0, st>>>(SC_TRUE, 0, part, gsp, ks, h->hist, h->hist_len);
+                                              part, sps, nullptr);
+    k_scalars<<<1, kRedT, 0, st>>>(SC_TRUE, 0, part, gsp, sps, ks, h->hist, h->hist_len);
     KCHK(launch_permute(n, BS, h->old2new, xp, x, st));
     KCHK(hipMemcpyAsync(h->ks_host, ks, sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
     KCHK(hipStreamSynchronize(st));
@@ -438,7 +461,9 @@ int bicgstab_run(dd_ctx *h, const double *b, double *x, double rtol, int32_t max
     if (!h->kv) {
         int rc = h->alloc(&h->kv, 10 * h->n * h->bs);
         if (rc) return rc;
-        rc = h->alloc(&h->partials, (int64_t)kStride * kMaxGrid);
+        const int rpb = (kWave / h->bs) * (kRedT / kWave);
+        h->spmv_part_stride = (int)std::max<int64_t>((h->n + rpb - 1) / rpb, kMaxGrid);
+        rc = h->alloc(&h->partials, (int64_t)kStride * h->spmv_part_stride);
         if (rc) return rc;
         rc = h->alloc(&h->ks, 1);
         if (rc) return rc;

@@ -28,7 +28,12 @@ STATUS_NAMES = {0: "DD_OK", -1: "DD_EINVAL", -2: "DD_ENOTDIV", -3: "DD_ELDS", -4
 EXPORTS = ("dd_auto_subdims", "dd_device_caps", "dd_partition", "dd_get_info", "dd_get_partition",
            "dd_get_reordered", "ilu0_factor", "dd_set_precision", "dd_get_levels", "dd_get_factors",
            "dd_trsv_apply", "dd_spmv", "bicgstab_solve", "dd_set_apply_variant", "dd_set_profiling",
-           "dd_set_residual_history", "dd_last_error", "dd_destroy")
+           "dd_set_residual_history", "dd_global_factor", "dd_global_apply", "dd_set_preconditioner",
+           "lic_setup", "lic_get_faces", "lic_set_params", "lic_set_coeffs", "lic_get_coeffs",
+           "dd_apply_adjoint", "lic_targets", "lic_loss_grad", "lic_adam", "lic_train",
+           "dd_last_error", "dd_destroy")
+
+LIC_NPARAM = 6537
 
 
 class PartitionDesc(C.Structure):
@@ -81,6 +86,19 @@ def lib():
             "dd_set_apply_variant": (C.c_int, [vp, i32]),
             "dd_set_profiling": (C.c_int, [vp, i32]),
             "dd_set_residual_history": (C.c_int, [vp, vp, i32]),
+            "dd_global_factor": (C.c_int, [vp, vp]),
+            "dd_global_apply": (C.c_int, [vp, vp, vp, i32, vp]),
+            "dd_set_preconditioner": (C.c_int, [vp, i32]),
+            "lic_setup": (C.c_int, [vp, vp]),
+            "lic_get_faces": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+            "lic_set_params": (C.c_int, [vp, vp, vp]),
+            "lic_set_coeffs": (C.c_int, [vp, vp, vp]),
+            "lic_get_coeffs": (C.c_int, [vp, vp, vp]),
+            "dd_apply_adjoint": (C.c_int, [vp, vp, vp, vp]),
+            "lic_targets": (C.c_int, [vp, i32, vp, vp, vp, vp]),
+            "lic_loss_grad": (C.c_int, [vp, vp, i32, vp, vp, vp, vp, vp, i32, vp]),
+            "lic_adam": (C.c_int, [vp, vp, vp, vp, i32, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp]),
+            "lic_train": (C.c_int, [vp, i32, vp, vp, vp, i32, vp, vp, vp, i32, vp, C.c_float, vp, vp]),
             "dd_last_error": (C.c_char_p, [vp]),
             "dd_destroy": (None, [vp]),
         }
@@ -275,3 +293,105 @@ def dd_set_residual_history(h: Handle, hist):
 
 def dd_destroy(h: Handle):
     h.close()
+
+
+# ------------------------------------------------------------- global ILU0
+def dd_global_factor(h: Handle, stream=None):
+    _check(lib().dd_global_factor(h.ptr, _stream(stream)), h)
+
+
+def dd_global_apply(h: Handle, r, z=None, nrhs=1, stream=None):
+    if z is None:
+        z = torch.empty_like(r)
+    _dev_check(r, torch.float64, z.numel(), "r")
+    _check(lib().dd_global_apply(h.ptr, _ptr(r), _ptr(z), nrhs, _stream(stream)), h)
+    return z
+
+
+def dd_set_preconditioner(h: Handle, kind: int):
+    """0: the domain-decomposed ILU0 apply; 1: the global ILU0 apply."""
+    _check(lib().dd_set_preconditioner(h.ptr, kind), h)
+
+
+# ------------------------------------------------------ learned correction
+def lic_setup(h: Handle, stream=None):
+    _check(lib().lic_setup(h.ptr, _stream(stream)), h)
+
+
+def lic_get_faces(h: Handle, stream=None):
+    nf = C.c_int32(0)
+    _check(lib().lic_get_faces(h.ptr, C.byref(nf), None, None, None, _stream(stream)), h)
+    m = nf.value
+    fI, fJ = _i32(m), _i32(m)
+    X = torch.empty(m * 27, dtype=torch.float32, device="cuda")
+    _check(lib().lic_get_faces(h.ptr, C.byref(nf), _ptr(fI), _ptr(fJ), _ptr(X), _stream(stream)), h)
+    return fI, fJ, X.view(m, 27)
+
+
+def lic_set_params(h: Handle, params, stream=None):
+    """params: CUDA float32 tensor of 6537 values, or None for the plain apply."""
+    if params is not None:
+        _dev_check(params, torch.float32, LIC_NPARAM, "params")
+    _check(lib().lic_set_params(h.ptr, _ptr(params), _stream(stream)), h)
+
+
+def lic_set_coeffs(h: Handle, coeffs, stream=None):
+    if coeffs is not None and not (coeffs.is_cuda and coeffs.dtype == torch.float32 and coeffs.is_contiguous()):
+        raise ValueError("coeffs: contiguous CUDA float32 tensor [nf, 3, 3]")
+    _check(lib().lic_set_coeffs(h.ptr, _ptr(coeffs), _stream(stream)), h)
+
+
+def lic_get_coeffs(h: Handle, nf: int, stream=None):
+    out = torch.empty(nf * 9, dtype=torch.float32, device="cuda")
+    _check(lib().lic_get_coeffs(h.ptr, _ptr(out), _stream(stream)), h)
+    return out.view(nf, 3, 3)
+
+
+def dd_apply_adjoint(h: Handle, g, a=None, stream=None):
+    if a is None:
+        a = torch.empty_like(g)
+    _dev_check(g, torch.float64, a.numel(), "g")
+    _check(lib().dd_apply_adjoint(h.ptr, _ptr(g), _ptr(a), _stream(stream)), h)
+    return a
+
+
+def lic_targets(h: Handle, R, stream=None):
+    """R: CUDA float64 [nq, 3n] probes.  Returns (Zs, den): global ILU0 applies
+    and den_q = ||M_DD^{-1} r_q - Zs_q||^2."""
+    nq = R.shape[0]
+    Zs = torch.empty_like(R)
+    den = torch.empty(nq, dtype=torch.float64, device="cuda")
+    _check(lib().lic_targets(h.ptr, nq, _ptr(R), _ptr(Zs), _ptr(den), _stream(stream)), h)
+    return Zs, den
+
+
+def lic_loss_grad(h: Handle, params, R, Zs, den, loss=None, grad=None, accumulate=False, stream=None):
+    if loss is None:
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    if grad is None:
+        grad = torch.zeros(LIC_NPARAM, dtype=torch.float32, device="cuda")
+    _check(lib().lic_loss_grad(h.ptr, _ptr(params), R.shape[0], _ptr(R), _ptr(Zs), _ptr(den), _ptr(loss),
+                               _ptr(grad), 1 if accumulate else 0, _stream(stream)), h)
+    return loss, grad
+
+
+def lic_adam(params, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+    _check(lib().lic_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(), t, lr, b1, b2, eps,
+                          _stream(stream)))
+
+
+def lic_train(handles, Rs, Zss, dens, params, m, v, epochs, order, lr=1e-3, stream=None):
+    """One Adam step per problem, problems visited in order[epoch] (host
+    int array epochs x nprob).  Returns the mean loss of every epoch."""
+    import numpy as np
+    nprob = len(handles)
+    hs = (C.c_void_p * nprob)(*[h.ptr.value for h in handles])
+    R = (C.c_void_p * nprob)(*[t.data_ptr() for t in Rs])
+    Z = (C.c_void_p * nprob)(*[t.data_ptr() for t in Zss])
+    D = (C.c_void_p * nprob)(*[t.data_ptr() for t in dens])
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    hist = np.zeros(epochs)
+    _check(lib().lic_train(hs, nprob, R, Z, D, Rs[0].shape[0], _ptr(params), _ptr(m), _ptr(v), epochs,
+                           order.ctypes.data_as(C.c_void_p), lr, hist.ctypes.data_as(C.c_void_p),
+                           _stream(stream)))
+    return hist

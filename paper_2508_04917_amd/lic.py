@@ -1,0 +1,168 @@
+"""Learned interface correction: training-set construction, training and
+evaluation drivers around the library's C ABI (lic_* entry points).
+
+Every numerical step runs in the library's kernels (problem setup, global
+ILU0 targets, corrected and adjoint applies, MLP forward/backward, Adam);
+this module only generates the seeded inputs, moves them to the device and
+sequences the calls.
+
+Training set: 48^3 log-normal problems (sigma ~ U[1,3]), seeds 1000..,
+explicit 16^3 subdomains, 16 N(0,1) probes each; regression target: the
+global ILU0 apply of the probes.
+
+usage:
+    python -m paper_2508_04917_amd.lic train [--problems 256] [--epochs E] [--out FILE]
+    python -m paper_2508_04917_amd.lic eval  [--params FILE] [--n 128] [--seeds 2000 2001 ...]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import ddilu as dd
+from .solver import DDSolver
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_PARAMS = os.path.join(HERE, "lic_params.npz")
+
+
+def _log(msg):
+    print(f"[lic] {msg}", file=sys.stderr, flush=True)
+
+
+def _cuda(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda").to(dtype)
+
+
+def prepare_problem(p, sub, nq, probe_seed):
+    """Set up one training problem: DD factors, faces, global ILU0, probes and
+    their regression targets (all on the device)."""
+    from problems import probe_vectors
+    s = DDSolver.from_problem(p, sub=sub)
+    dd.lic_setup(s.h)
+    dd.dd_global_factor(s.h)
+    R = _cuda(probe_vectors(probe_seed, nq, p.n * 3), torch.float64)
+    Zs, den = dd.lic_targets(s.h, R)
+    return s, R, Zs, den
+
+
+def train(nprob=256, epochs=10, nq=16, n=48, sub=(16, 16, 16), lr=1e-3, init_seed=0, order_seed=1,
+          first_seed=1000):
+    from problems import lic_init_params, training_order, training_problem
+    probs = []
+    t0 = time.time()
+    for k in range(nprob):
+        seed = first_seed + k
+        p = training_problem(seed, n)
+        probs.append(prepare_problem(p, sub, nq, seed))
+        if (k + 1) % 16 == 0 or k + 1 == nprob:
+            _log(f"prepared {k + 1}/{nprob} problems ({time.time() - t0:.1f}s)")
+    params = _cuda(lic_init_params(init_seed), torch.float32)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    order = training_order(order_seed, epochs, nprob)
+    hist = []
+    t1 = time.time()
+    for ep in range(epochs):
+        h = dd.lic_train([q[0].h for q in probs], [q[1] for q in probs], [q[2] for q in probs],
+                         [q[3] for q in probs], params, m, v, 1, order[ep:ep + 1], lr=lr)
+        hist.append(float(h[0]))
+        _log(f"epoch {ep + 1}/{epochs}: mean loss {hist[-1]:.4f} ({time.time() - t1:.1f}s)")
+    for q in probs:
+        q[0].close()
+    meta = {"nprob": nprob, "epochs": epochs, "nq": nq, "grid": n, "subdomain": list(sub), "lr": lr,
+            "init_seed": init_seed, "order_seed": order_seed, "first_seed": first_seed,
+            "loss_history": hist, "train_seconds": time.time() - t1}
+    return params.cpu().numpy(), meta
+
+
+def save_params(path, params, meta):
+    np.savez(path, params=params.astype(np.float32), meta=json.dumps(meta))
+
+
+def load_params(path=DEFAULT_PARAMS):
+    with np.load(path, allow_pickle=False) as f:
+        return f["params"].astype(np.float32), json.loads(str(f["meta"]))
+
+
+def heldout_loss(params, p, sub, nq=8, probe_seed=99):
+    """Mean loss of the correction on probes of an unseen problem."""
+    s, R, Zs, den = prepare_problem(p, sub, nq, probe_seed)
+    loss, _ = dd.lic_loss_grad(s.h, _cuda(params, torch.float32), R, Zs, den)
+    out = float(loss.item())
+    s.close()
+    return out
+
+
+def evaluate(params, p, sub=(0, 0, 0), rtol=1e-8, maxit=5000, with_global=True):
+    """BiCGSTAB iterations and solve times: plain DD-ILU0 (FP64 and mixed),
+    learned correction (FP64 and mixed), and global ILU0 (FP64)."""
+    s = DDSolver.from_problem(p, sub=sub)
+    dd.lic_setup(s.h)
+    b = _cuda(p.b, torch.float64)
+    out = {"subdomain": [s.info["sx"], s.info["sy"], s.info["sz"]]}
+    P = _cuda(params, torch.float32)
+    for name, prec, learned in (("plain_fp64", dd.DD_FP64, False), ("plain_mixed", dd.DD_MIXED, False),
+                                ("learned_fp64", dd.DD_FP64, True), ("learned_mixed", dd.DD_MIXED, True)):
+        s.set_precision(prec)
+        dd.lic_set_params(s.h, P if learned else None)
+        x, info = s.solve(b, rtol=rtol, maxit=maxit)
+        if learned and info["status"] != 0:  # fallback: plain DD-ILU0
+            dd.lic_set_params(s.h, None)
+            x, info = s.solve(b, rtol=rtol, maxit=maxit)
+            info["fallback"] = True
+        out[name] = {k: info[k] for k in ("iters", "status", "solve_seconds", "rel_res_true")}
+        out[name]["fallback"] = bool(info.get("fallback", False))
+    dd.lic_set_params(s.h, None)
+    s.set_precision(dd.DD_FP64)
+    if with_global:
+        dd.dd_global_factor(s.h)
+        dd.dd_set_preconditioner(s.h, 1)
+        x, info = s.solve(b, rtol=rtol, maxit=maxit)
+        dd.dd_set_preconditioner(s.h, 0)
+        out["global_fp64"] = {k: info[k] for k in ("iters", "status", "solve_seconds", "rel_res_true")}
+    s.close()
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sp = ap.add_subparsers(dest="cmd", required=True)
+    t = sp.add_parser("train")
+    t.add_argument("--problems", type=int, default=256)
+    t.add_argument("--epochs", type=int, default=10)
+    t.add_argument("--probes", type=int, default=16)
+    t.add_argument("--grid", type=int, default=48)
+    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--out", default=DEFAULT_PARAMS)
+    e = sp.add_parser("eval")
+    e.add_argument("--params", default=DEFAULT_PARAMS)
+    e.add_argument("--n", type=int, default=128)
+    e.add_argument("--seeds", type=int, nargs="+", default=[2000, 2001, 2002, 2003])
+    e.add_argument("--sigma", type=float, default=2.0)
+    e.add_argument("--no-global", action="store_true")
+    args = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    if args.cmd == "train":
+        params, meta = train(nprob=args.problems, epochs=args.epochs, nq=args.probes, n=args.grid, lr=args.lr)
+        save_params(args.out, params, meta)
+        print(json.dumps(meta))
+    else:
+        from problems import lognormal_problem
+        params, meta = load_params(args.params)
+        for seed in args.seeds:
+            p = lognormal_problem(args.n, args.n, args.n, seed=seed, sigma=args.sigma)
+            res = evaluate(params, p, with_global=not args.no_global)
+            res["seed"] = seed
+            print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

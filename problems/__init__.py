@@ -16,6 +16,7 @@ from .generators import (  # noqa: F401
     training_problem,
     probe_vectors,
     lic_init_params,
+    training_order,
     WORKLOADS,
     make_workload,
 )

@@ -211,6 +211,13 @@ def lic_init_params(seed: int = 0) -> np.ndarray:
                            np.zeros(9)])
 
 
+def training_order(seed: int, epochs: int, nprob: int) -> np.ndarray:
+    """Order in which the training problems are visited: a fresh permutation of
+    range(nprob) per epoch from default_rng(seed), shape (epochs, nprob)."""
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.permutation(nprob) for _ in range(epochs)]).astype(np.int32)
+
+
 # Named workloads: (generator, kwargs, default subdomain dims or None = automatic rule)
 WORKLOADS = {
     # scalar 7-point Laplacian, 16^3, eight 8^3 subdomains
