@@ -21,7 +21,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB lets the mutation tests load a deliberately broken copy of the
+# oracle (built from a mutated oracle.c) in a child process.
+_LIB = os.environ.get("ORACLE_LIB", os.path.join(_HERE, "liboracle.so"))
 
 O_OK, O_EINVAL, O_ENOTDIV, O_EZEROPIVOT, O_EBREAKDOWN, O_ENOCONV = 0, -1, -2, -4, -5, -6
 
