@@ -4,7 +4,10 @@ One step = one pass of the whole path over the workload's matrix, already
 resident in HBM: partition + reorder, drop + level sets + block ILU0/ILDU0,
 BiCGSTAB to rel. residual 1e-8 with the FP64 preconditioner, FP32 factor
 copies, BiCGSTAB to 1e-8 with FP32-stored factors and FP64 trisolve
-arithmetic (DD_MIXED), and BiCGSTAB to 1e-8 with FP32 trisolves (DD_FP32).
+arithmetic (DD_MIXED), BiCGSTAB to 1e-8 with FP32 trisolves (DD_FP32), and,
+when trained parameters are present (paper_2508_04917_amd/lic_params.npz),
+the learned interface correction: faces + features + MLP inference, then
+BiCGSTAB to 1e-8 with the corrected mixed-precision preconditioner.
 
 Printed (one JSON line): the trisolve bandwidth of the FP64 apply -- its
 algorithmic bytes divided by its average duration, timed by HIP event pairs
@@ -134,6 +137,11 @@ def main():
     val_d = torch.as_tensor(p.val.reshape(-1), device=dev)
     b_d = torch.as_tensor(p.b, device=dev)
     n_cu, lds = dd.dd_device_caps()
+    lic_params = None
+    lic_path = os.path.join(ROOT, "paper_2508_04917_amd", "lic_params.npz")
+    if os.path.exists(lic_path) and p.bs == 3:
+        from paper_2508_04917_amd.lic import load_params
+        lic_params = torch.as_tensor(load_params(lic_path)[0], device=dev)
     log(f"device: {n_cu} CUs, {lds} B LDS per workgroup; n={p.n} nnzb={p.nnzb}")
 
     if args.mode == "kernels":
@@ -164,6 +172,24 @@ def main():
         nx64 = torch.linalg.norm(x64)
         rec["x_rel_diff_mixed"] = float(torch.linalg.norm(xm - x64) / nx64)
         rec["x_rel_diff_fp32"] = float(torch.linalg.norm(x32 - x64) / nx64)
+        rec["learned"] = None
+        if lic_params is not None:
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            dd.lic_setup(h)
+            dd.lic_set_params(h, lic_params)
+            torch.cuda.synchronize()
+            rec["lic_setup_s"] = time.perf_counter() - t2
+            dd.dd_set_precision(h, dd.DD_MIXED)
+            xl, il = dd.bicgstab_solve(h, b_d, rtol=args.rtol, maxit=args.maxit)
+            if il["status"] != 0:  # fallback: plain DD-ILU0
+                log(f"learned solve status {il['status']}: falling back to the plain preconditioner")
+                dd.lic_set_params(h, None)
+                xl, il2 = dd.bicgstab_solve(h, b_d, rtol=args.rtol, maxit=args.maxit)
+                il2["fallback_from"] = il
+                il = il2
+            rec["learned"] = il
+            rec["x_rel_diff_learned"] = float(torch.linalg.norm(xl - x64) / nx64)
         h.close()
         for k in ("fp64", "mixed", "fp32"):
             if rec[k]["status"] != 0:
@@ -238,6 +264,13 @@ def main():
                      "rel_res_true": recs[0]["fp32"]["rel_res_true"],
                      "x_rel_diff_vs_fp64": recs[0]["x_rel_diff_fp32"]},
             "setup_s": round(med([r["setup_s"] for r in recs]), 4),
+            "learned_mixed": None if recs[0]["learned"] is None else {
+                "iters": recs[0]["learned"]["iters"], "status": recs[0]["learned"]["status"],
+                "solve_s": round(med([r["learned"]["solve_seconds"] for r in recs]), 4),
+                "lic_setup_s": round(med([r["lic_setup_s"] for r in recs]), 4),
+                "rel_res_true": recs[0]["learned"]["rel_res_true"],
+                "x_rel_diff_vs_fp64": recs[0]["x_rel_diff_learned"],
+                "fallback": "fallback_from" in recs[0]["learned"]},
         },
         "roofline": {"bound": "hbm", "achieved": round(gbs64, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs64 / HBM_PEAK_GBS, 4),

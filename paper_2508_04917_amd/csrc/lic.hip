@@ -311,10 +311,15 @@ __global__ void k_pack_adjoint(int64_t n, int S, int which, int MB, const int32_
     for (int32_t q = tptr[gi]; q < tptr[gi + 1] && k < MB; ++q) {
         const int32_t c = tcol[q];
         if (which == 0 ? (c < gi) : (c > gi)) {
-            int32_t qt = -1;  // position of (c, gi) in row c
+            int32_t qt = -1;  // position of (c, gi) in row c (exists: symmetric pattern)
             for (int32_t r = tptr[c]; r < tptr[c + 1]; ++r)
                 if (tcol[r] == gi) qt = r;
             double blk[9];
+            if (qt < 0) {
+                for (int e = 0; e < 9; ++e) sval[(p * MB + k) * 9 + e] = 0.0;
+                ++k;
+                continue;
+            }
             if (which == 0) {  // Uhat_{c,gi} = inv_D_c U_{c,gi}
                 const double *a = invd + (int64_t)c * 9, *b = lu + (int64_t)qt * 9;
                 for (int i = 0; i < 3; ++i)
@@ -451,7 +456,7 @@ int lic_loss_grad_run(dd_ctx *h, const float *params, int Q, const double *R, co
     int rc = lic_coeffs_from_params(h, params, true, st);
     if (rc) return rc;
     if (L.work_q < Q) {
-        for (void *q : {(void *)L.Z, (void *)L.G, (void *)L.A})
+        for (void *q : {(void *)L.Z, (void *)L.G, (void *)L.A, (void *)L.rpart})
             if (q) {
                 h->allocs.erase(std::find(h->allocs.begin(), h->allocs.end(), q));
                 (void)hipFree(q);
@@ -459,6 +464,7 @@ int lic_loss_grad_run(dd_ctx *h, const float *params, int Q, const double *R, co
         rc = h->alloc(&L.Z, Q * m);
         if (!rc) rc = h->alloc(&L.G, Q * m);
         if (!rc) rc = h->alloc(&L.A, Q * m);
+        if (!rc) rc = h->alloc(&L.rpart, (int64_t)Q * 2048);
         if (rc) return rc;
         L.work_q = Q;
     }
@@ -468,7 +474,6 @@ int lic_loss_grad_run(dd_ctx *h, const float *params, int Q, const double *R, co
         if (!rc) rc = h->alloc(&L.G2, (int64_t)std::max(L.nf, 1) * kHid);
         const int nchunk = (int)((std::max(L.nf, 1) + kFaceChunk - 1) / kFaceChunk);
         if (!rc) rc = h->alloc(&L.wpart, (int64_t)nchunk * kNParam);
-        if (!rc) rc = h->alloc(&L.rpart, (int64_t)Q * 2048);
         if (rc) return rc;
     }
     const int32_t saved_prec = h->precision, saved_active = L.active;
