@@ -309,11 +309,14 @@ int lic_adam(float *params, const float *grad, float *m, float *v, int32_t npara
  * order[epoch*nprob + k] (host int32).  hs, R, Zs, den: host arrays of nprob
  * handles / device pointers (each problem's nq probes, targets and
  * denominators).  params, m, v: device float[6537], updated in place.
+ * step0: Adam steps already taken with this m, v (0 for a fresh start), so
+ * that a run split over several calls keeps its bias correction.
  * loss_hist: host double[epochs] (mean loss per epoch), may be NULL. */
 int lic_train(dd_handle *hs, int32_t nprob, const double *const *R,
               const double *const *Zs, const double *const *den, int32_t nq,
               float *params, float *m, float *v, int32_t epochs,
-              const int32_t *order, float lr, double *loss_hist, void *hip_stream);
+              const int32_t *order, float lr, int32_t step0, double *loss_hist,
+              void *hip_stream);
 
 /* Message of the last failed call on h (or of the last failure before a
  * handle existed when h is NULL).  Owned by the library. */

@@ -599,8 +599,9 @@ extern "C" int lic_adam(float *params, const float *grad, float *m, float *v, in
 
 extern "C" int lic_train(dd_handle *hs, int32_t nprob, const double *const *R, const double *const *Zs,
                          const double *const *den, int32_t nq, float *params, float *m, float *v, int32_t epochs,
-                         const int32_t *order, float lr, double *loss_hist, void *hip_stream) {
-    if (!hs || nprob < 1 || !R || !Zs || !den || nq < 1 || !params || !m || !v || epochs < 0 || !order)
+                         const int32_t *order, float lr, int32_t step0, double *loss_hist, void *hip_stream) {
+    if (!hs || nprob < 1 || !R || !Zs || !den || nq < 1 || !params || !m || !v || epochs < 0 || !order ||
+        step0 < 0)
         return set_global_error(DD_EINVAL, "lic_train: bad arguments");
     hipStream_t st = as_stream(hip_stream);
     float *grad = nullptr;
@@ -608,7 +609,7 @@ extern "C" int lic_train(dd_handle *hs, int32_t nprob, const double *const *R, c
     hipError_t e = hipMalloc(&grad, 6537 * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&lacc, sizeof(double));
     if (e != hipSuccess) return set_global_error(DD_ENOMEM, "lic_train: %s", hipGetErrorString(e));
-    int rc = DD_OK, t = 0;
+    int rc = DD_OK, t = step0;
     for (int ep = 0; ep < epochs && rc == DD_OK; ++ep) {
         e = hipMemsetAsync(lacc, 0, sizeof(double), st);
         for (int k = 0; k < nprob && rc == DD_OK && e == hipSuccess; ++k) {

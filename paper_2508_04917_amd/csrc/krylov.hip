@@ -52,9 +52,13 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double *out, int
 
 // --------------------------------------------------------------- SpMV
 // BS lanes of one wavefront per block row, lane c computes component c.
-// The first kUnroll blocks of a row are loaded with predicated, unrolled
-// loads (all issued before any is used), longer rows finish in a loop.
-constexpr int kUnroll = 8;
+// The first kUnroll blocks of a row (a 7-point stencil row has at most 7)
+// are fetched branch-free: column indices and block rows for all of them are
+// issued together, positions past the row end re-read the row's last block
+// (a valid address, same cache line) and are discarded by a select, so a row
+// costs two memory round trips (A and col, then x) rather than one per block.
+// Longer rows finish in a loop.
+constexpr int kUnroll = 7;
 
 template <int BS>
 __device__ __forceinline__ double bsr_row(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
@@ -63,24 +67,36 @@ __device__ __forceinline__ double bsr_row(const int32_t *__restrict__ ptr, const
     constexpr int BB = BS * BS;
     const int32_t b0 = ptr[row], b1 = ptr[row + 1];
     const int nb = b1 - b0;
-    int64_t J[kUnroll];
+    int32_t idx[kUnroll];
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) idx[k] = max(min(b0 + k, b1 - 1), 0);  // nnzb >= 1
+    int32_t J[kUnroll];
     double v[kUnroll][BS];
 #pragma unroll
-    for (int k = 0; k < kUnroll; ++k) {
-        if (k < nb) {
-            J[k] = col[b0 + k];
-            const double *blk = val + (int64_t)(b0 + k) * BB + c * BS;
+    for (int k = 0; k < kUnroll; ++k) J[k] = col[idx[k]];
 #pragma unroll
-            for (int d = 0; d < BS; ++d) v[k][d] = blk[d];
-        }
+    for (int k = 0; k < kUnroll; ++k) {
+        const double *blk = val + (int64_t)idx[k] * BB + c * BS;
+#pragma unroll
+        for (int d = 0; d < BS; ++d) v[k][d] = blk[d];
     }
+    // keep the scheduler from sinking these loads next to their uses
+    __builtin_amdgcn_sched_barrier(0);
+    double xv[kUnroll][BS];
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) {
+        const double *xb = x + (int64_t)J[k] * BS;
+#pragma unroll
+        for (int d = 0; d < BS; ++d) xv[k][d] = xb[d];
+    }
+    __builtin_amdgcn_sched_barrier(0);
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < kUnroll; ++k) {
-        if (k < nb) {
+        double t = 0.0;
 #pragma unroll
-            for (int d = 0; d < BS; ++d) acc += v[k][d] * x[J[k] * BS + d];
-        }
+        for (int d = 0; d < BS; ++d) t += v[k][d] * xv[k][d];
+        acc += k < nb ? t : 0.0;
     }
     for (int32_t b = b0 + kUnroll; b < b1; ++b) {
         const int64_t Jb = col[b];

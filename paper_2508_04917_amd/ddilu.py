@@ -98,7 +98,7 @@ def lib():
             "lic_targets": (C.c_int, [vp, i32, vp, vp, vp, vp]),
             "lic_loss_grad": (C.c_int, [vp, vp, i32, vp, vp, vp, vp, vp, i32, vp]),
             "lic_adam": (C.c_int, [vp, vp, vp, vp, i32, i32, C.c_float, C.c_float, C.c_float, C.c_float, vp]),
-            "lic_train": (C.c_int, [vp, i32, vp, vp, vp, i32, vp, vp, vp, i32, vp, C.c_float, vp, vp]),
+            "lic_train": (C.c_int, [vp, i32, vp, vp, vp, i32, vp, vp, vp, i32, vp, C.c_float, i32, vp, vp]),
             "dd_last_error": (C.c_char_p, [vp]),
             "dd_destroy": (None, [vp]),
         }
@@ -380,9 +380,10 @@ def lic_adam(params, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=
                           _stream(stream)))
 
 
-def lic_train(handles, Rs, Zss, dens, params, m, v, epochs, order, lr=1e-3, stream=None):
+def lic_train(handles, Rs, Zss, dens, params, m, v, epochs, order, lr=1e-3, step0=0, stream=None):
     """One Adam step per problem, problems visited in order[epoch] (host
-    int array epochs x nprob).  Returns the mean loss of every epoch."""
+    int array epochs x nprob); step0 = Adam steps already taken with m, v.
+    Returns the mean loss of every epoch."""
     import numpy as np
     nprob = len(handles)
     hs = (C.c_void_p * nprob)(*[h.ptr.value for h in handles])
@@ -392,6 +393,6 @@ def lic_train(handles, Rs, Zss, dens, params, m, v, epochs, order, lr=1e-3, stre
     order = np.ascontiguousarray(order, dtype=np.int32)
     hist = np.zeros(epochs)
     _check(lib().lic_train(hs, nprob, R, Z, D, Rs[0].shape[0], _ptr(params), _ptr(m), _ptr(v), epochs,
-                           order.ctypes.data_as(C.c_void_p), lr, hist.ctypes.data_as(C.c_void_p),
+                           order.ctypes.data_as(C.c_void_p), lr, step0, hist.ctypes.data_as(C.c_void_p),
                            _stream(stream)))
     return hist

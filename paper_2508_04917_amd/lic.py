@@ -54,7 +54,7 @@ def prepare_problem(p, sub, nq, probe_seed):
 
 
 def train(nprob=256, epochs=10, nq=16, n=48, sub=(16, 16, 16), lr=1e-3, init_seed=0, order_seed=1,
-          first_seed=1000):
+          first_seed=1000, nval=4, first_val_seed=1900, out=None):
     from problems import lic_init_params, training_order, training_problem
     probs = []
     t0 = time.time()
@@ -64,22 +64,35 @@ def train(nprob=256, epochs=10, nq=16, n=48, sub=(16, 16, 16), lr=1e-3, init_see
         probs.append(prepare_problem(p, sub, nq, seed))
         if (k + 1) % 16 == 0 or k + 1 == nprob:
             _log(f"prepared {k + 1}/{nprob} problems ({time.time() - t0:.1f}s)")
+    vals = [prepare_problem(training_problem(first_val_seed + k, n), sub, nq, first_val_seed + k)
+            for k in range(nval)]
+
+    def val_loss(params):
+        if not vals:
+            return float("nan")
+        return float(np.mean([dd.lic_loss_grad(q[0].h, params, q[1], q[2], q[3])[0].item() for q in vals]))
+
     params = _cuda(lic_init_params(init_seed), torch.float32)
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
     order = training_order(order_seed, epochs, nprob)
-    hist = []
+    hist, vhist, meta = [], [], {}
     t1 = time.time()
     for ep in range(epochs):
         h = dd.lic_train([q[0].h for q in probs], [q[1] for q in probs], [q[2] for q in probs],
-                         [q[3] for q in probs], params, m, v, 1, order[ep:ep + 1], lr=lr)
+                         [q[3] for q in probs], params, m, v, 1, order[ep:ep + 1], lr=lr, step0=ep * nprob)
         hist.append(float(h[0]))
-        _log(f"epoch {ep + 1}/{epochs}: mean loss {hist[-1]:.4f} ({time.time() - t1:.1f}s)")
-    for q in probs:
+        vhist.append(val_loss(params))
+        _log(f"epoch {ep + 1}/{epochs}: mean loss {hist[-1]:.4f}, held-out {vhist[-1]:.4f} "
+             f"({time.time() - t1:.1f}s)")
+        meta = {"nprob": nprob, "epochs": ep + 1, "nq": nq, "grid": n, "subdomain": list(sub), "lr": lr,
+                "init_seed": init_seed, "order_seed": order_seed, "first_seed": first_seed,
+                "loss_history": hist, "val_seeds": [first_val_seed, first_val_seed + nval - 1],
+                "val_loss_history": vhist, "train_seconds": time.time() - t1}
+        if out:  # checkpoint after every epoch
+            save_params(out, params.cpu().numpy(), meta)
+    for q in probs + vals:
         q[0].close()
-    meta = {"nprob": nprob, "epochs": epochs, "nq": nq, "grid": n, "subdomain": list(sub), "lr": lr,
-            "init_seed": init_seed, "order_seed": order_seed, "first_seed": first_seed,
-            "loss_history": hist, "train_seconds": time.time() - t1}
     return params.cpu().numpy(), meta
 
 
@@ -141,6 +154,7 @@ def main(argv=None):
     t.add_argument("--probes", type=int, default=16)
     t.add_argument("--grid", type=int, default=48)
     t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--val", type=int, default=4)
     t.add_argument("--out", default=DEFAULT_PARAMS)
     e = sp.add_parser("eval")
     e.add_argument("--params", default=DEFAULT_PARAMS)
@@ -151,8 +165,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
     if args.cmd == "train":
-        params, meta = train(nprob=args.problems, epochs=args.epochs, nq=args.probes, n=args.grid, lr=args.lr)
-        save_params(args.out, params, meta)
+        params, meta = train(nprob=args.problems, epochs=args.epochs, nq=args.probes, n=args.grid, lr=args.lr,
+                             nval=args.val, out=args.out)
         print(json.dumps(meta))
     else:
         from problems import lognormal_problem
