@@ -130,6 +130,24 @@ def test_least_squares_bound(small):
     coef, *_ = np.linalg.lstsq(D, rhs, rcond=None)
     ls_loss = ((D @ coef - rhs) ** 2).sum() / Q
     assert ls_loss < 0.9
+    # the same loss through the correction + apply path, and a zero gradient
+    # (adjoint apply + dC) at the minimiser
+    C_ls = coef.reshape(nf, 3, 3)
+
+    def loss_and_dC(C):
+        A = np.empty_like(R)
+        loss = 0.0
+        for q in range(Q):
+            e = L.apply(C, R[q]) - Zs[q]
+            loss += (e @ e) / den[q] / Q
+            A[q] = O.apply_transpose(n, 3, st.tptr, st.tcol, st.f, 2.0 * e / (Q * den[q]))
+        return loss, O.lic_dC(n, L.faces, A, R)
+
+    loss_ls2, g_ls = loss_and_dC(C_ls)
+    loss_zero, g_zero = loss_and_dC(np.zeros_like(C_ls))
+    assert abs(loss_ls2 - ls_loss) <= 1e-10 * ls_loss
+    assert abs(loss_zero - 1.0) < 1e-12
+    assert np.linalg.norm(g_ls) <= 1e-7 * np.linalg.norm(g_zero)
     P = lic_init_params(0)
     loss0, _ = L.loss_and_grad(P, R, Zs, den, want_grad=False)
     assert abs(loss0 - 1.0) < 1e-12

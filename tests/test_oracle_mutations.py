@@ -45,7 +45,20 @@ MUTATIONS = [
     ("mlp_backward_wrong_mask",
      "g2[k] = h2[k] > 0.0 ? s : 0.0;", "g2[k] = s;",
      ["test_mlp_forward_backward_against_torch", "test_loss_gradient_central_differences"]),
+    ("lic_dC_transposed",
+     "dC[f * 9 + a * 3 + b] += A[(int64_t)q * 3 * n + (int64_t)fI[f] * 3 + a] *\n"
+     "                                             R[(int64_t)q * 3 * n + (int64_t)fJ[f] * 3 + b];",
+     "dC[f * 9 + a * 3 + b] += A[(int64_t)q * 3 * n + (int64_t)fI[f] * 3 + b] *\n"
+     "                                             R[(int64_t)q * 3 * n + (int64_t)fJ[f] * 3 + a];",
+     ["test_loss_gradient_central_differences", "test_least_squares_bound"]),
+    ("adjoint_block_not_transposed",
+     "for (int d = 0; d < bs; ++d) s += f[p * bb + d * bs + c] * a[K * bs + d];",
+     "for (int d = 0; d < bs; ++d) s += f[p * bb + c * bs + d] * a[K * bs + d];",
+     ["test_apply_transpose_adjoint", "test_least_squares_bound"]),
 ]
+
+LIC_PINS = ("test_mlp_forward_backward_against_torch", "test_loss_gradient_central_differences",
+            "test_least_squares_bound")
 
 
 @pytest.mark.parametrize("name,old,new,pins", MUTATIONS, ids=[m[0] for m in MUTATIONS])
@@ -59,8 +72,7 @@ def test_mutation_is_caught(name, old, new, pins, tmp_path):
     env = dict(os.environ, ORACLE_LIB=str(lib))
     tests = []
     for pin in pins:
-        mod = "tests/test_oracle_lic.py" if pin in ("test_mlp_forward_backward_against_torch",
-                                                    "test_loss_gradient_central_differences") else "tests/test_oracle.py"
+        mod = "tests/test_oracle_lic.py" if pin in LIC_PINS else "tests/test_oracle.py"
         tests.append(f"{mod}::{pin}")
     for t in tests:
         r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", t],
