@@ -21,12 +21,13 @@
 #include "internal.h"
 
 // Prefetch depth (levels loaded ahead) of the slot-layout kernel, per factor
-// storage type: deeper for FP32 blocks, which take half the registers.
+// storage type.  Depths 1 to 3 measure the same at 160^3 (the per-level time
+// is not set by load latency), so the default takes the fewest registers.
 #ifndef DDILU_PD64
-#define DDILU_PD64 2
+#define DDILU_PD64 1
 #endif
 #ifndef DDILU_PD32
-#define DDILU_PD32 3
+#define DDILU_PD32 1
 #endif
 
 namespace ddilu {
@@ -317,10 +318,10 @@ __global__ __launch_bounds__(NT) void k_dd_apply_pipe(
 // in one 64-bit descriptor.  No load depends on another load, so the loads of
 // level l+PD are issued while level l computes: PD+1 register sets rotate.
 // The main loop is unrolled by PD+1 (each set keeps its registers) and has no
-// early exit, and every lane issues the same loads in the same order (idle
-// lanes re-read the level's first position; fetches past the last level
-// re-read the last level), so the compiler can count outstanding loads
-// exactly and each level waits only for its own set, not for the whole queue.
+// early exit, and every lane issues the same loads in the same order (fetches
+// past the last level re-read the last level), so the compiler can count
+// outstanding loads exactly and each level waits only for its own set, not
+// for the whole queue.
 template <int BS, typename TS, int MB>
 struct SlotRegs {
     bool ok;
@@ -329,64 +330,121 @@ struct SlotRegs {
     TS d[BS];
 };
 
-template <int BS, typename TS, int MB, bool UPPER>
-__device__ __forceinline__ void slot_fetch(SlotRegs<BS, TS, MB> &R, int64_t base, int32_t p0, int32_t p1, int slot,
-                                           bool lane_ok, int c, const uint64_t *__restrict__ desc,
-                                           const TS *__restrict__ sval, const TS *__restrict__ dval) {
-    constexpr int BB = BS * BS;
-    const int32_t p = p0 + slot;
-    R.ok = lane_ok && p < p1;
-    const int64_t gp = base + (R.ok ? p : p0);
-    R.desc = desc[gp];
-#pragma unroll
-    for (int k = 0; k < MB; ++k) {
-        const TS *blk = sval + (gp * MB + k) * BB + c * BS;
-#pragma unroll
-        for (int d = 0; d < BS; ++d) R.v[k][d] = blk[d];
-    }
-    if constexpr (UPPER) {
-        const TS *dblk = dval + gp * BB + c * BS;
-#pragma unroll
-        for (int d = 0; d < BS; ++d) R.d[d] = dblk[d];
-    }
-}
-
 template <int BS, typename TS, typename TC, int MB, bool UPPER>
 __device__ __forceinline__ void slot_compute(TC *__restrict__ y, const SlotRegs<BS, TS, MB> &R, int c) {
     if (!R.ok) return;
     const int I = (int)(R.desc & 0xffffu);
+    // gather every LDS operand first (one round of LDS latency), then the
+    // fixed-order arithmetic.  An empty slot holds a zero block: it is
+    // applied to y_I (a valid LDS address) instead of being branched around,
+    // so every loaded value has an unconditional use and the factor loads
+    // stay where they were issued.
+    constexpr int NI = UPPER ? BS : 1;
+    TC yi[NI], yj[MB][BS];
+#pragma unroll
+    for (int d = 0; d < NI; ++d) yi[d] = y[I * BS + (UPPER ? d : c)];
+#pragma unroll
+    for (int k = 0; k < MB; ++k) {
+        const int J = (int)((R.desc >> (16 * (k + 1))) & 0xffffu);
+        const int Jc = J != 0xffff ? J : I;
+#pragma unroll
+        for (int d = 0; d < BS; ++d) yj[k][d] = y[Jc * BS + d];
+    }
+    __builtin_amdgcn_sched_barrier(0);
     TC acc;
     if constexpr (UPPER) {
         acc = 0;
 #pragma unroll
-        for (int d = 0; d < BS; ++d) acc += static_cast<TC>(R.d[d]) * y[I * BS + d];
+        for (int d = 0; d < BS; ++d) acc += static_cast<TC>(R.d[d]) * yi[d];
     } else {
-        acc = y[I * BS + c];
+        acc = yi[0];
     }
 #pragma unroll
-    for (int k = 0; k < MB; ++k) {
-        const int J = (int)((R.desc >> (16 * (k + 1))) & 0xffffu);
-        if (J != 0xffff) {
+    for (int k = 0; k < MB; ++k)
 #pragma unroll
-            for (int d = 0; d < BS; ++d) acc -= static_cast<TC>(R.v[k][d]) * y[J * BS + d];
-        }
-    }
+        for (int d = 0; d < BS; ++d) acc -= static_cast<TC>(R.v[k][d]) * yj[k][d];
     // all lanes of this row read y_I above (same wavefront)
     __asm__ volatile("" ::: "memory");
     y[I * BS + c] = acc;
 }
 
+// Loads go through buffer resources over the workgroup's slice of the
+// descriptor, block and inv_D streams: a lane without a row at a level passes
+// an offset past the slice, for which the hardware returns zeros without a
+// memory access (and no lane can address outside its subdomain's slice).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t slice_rsrc(const void *p, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+constexpr uint32_t kOobOffset = 0x80000000u;  // beyond every slice (slices < 2 GiB)
+
+template <typename TS, int BS>
+__device__ __forceinline__ void buf_load_row(__amdgpu_buffer_rsrc_t rs, uint32_t off, TS *v) {
+    if constexpr (sizeof(TS) == 8 && BS == 3) {
+        struct D2 { double x, y; };
+        const D2 a = __builtin_bit_cast(D2, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+        v[0] = a.x;
+        v[1] = a.y;
+        v[2] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off + 16, 0, 0));
+    } else if constexpr (sizeof(TS) == 4 && BS == 3) {
+        // 64 + 32 bits (the 96-bit builtin is avoided: this compiler lowers
+        // it to a single dword load)
+        struct F2 { float x, y; };
+        const F2 a = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+        v[0] = a.x;
+        v[1] = a.y;
+        v[2] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + 8, 0, 0));
+    } else if constexpr (sizeof(TS) == 8) {
+        v[0] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+    } else {
+        v[0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+    }
+}
+
+struct SlotRsrc {
+    __amdgpu_buffer_rsrc_t desc, val, dval;
+};
+
+template <int BS, typename TS, int MB, bool UPPER>
+__device__ __forceinline__ void slot_fetch(SlotRegs<BS, TS, MB> &R, const SlotRsrc &rs, int32_t p0, int32_t p1,
+                                           int slot, bool lane_ok, int c) {
+    constexpr int BB = BS * BS;
+    const int32_t p = p0 + slot;
+    R.ok = lane_ok && p < p1;
+    const uint32_t pd = R.ok ? (uint32_t)p * 8u : kOobOffset;
+    R.desc = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(rs.desc, pd, 0, 0));
+#pragma unroll
+    for (int k = 0; k < MB; ++k) {
+        const uint32_t off = R.ok ? (uint32_t)(((p * MB + k) * BB + c * BS) * sizeof(TS)) : kOobOffset;
+        buf_load_row<TS, BS>(rs.val, off, R.v[k]);
+    }
+    if constexpr (UPPER) {
+        const uint32_t off = R.ok ? (uint32_t)((p * BB + c * BS) * sizeof(TS)) : kOobOffset;
+        buf_load_row<TS, BS>(rs.dval, off, R.d);
+    }
+}
+
 template <int BS, typename TS, typename TC, int MB, int PD, bool UPPER>
-__device__ __forceinline__ void sweep_slots(TC *__restrict__ y, int64_t base, int s, const int32_t *__restrict__ off,
-                                            const int32_t *__restrict__ lp, const uint64_t *__restrict__ desc,
-                                            const TS *__restrict__ sval, const TS *__restrict__ dval, int slot,
-                                            bool lane_ok, int c) {
+__device__ __forceinline__ void sweep_slots(TC *__restrict__ y, int64_t base, int S, int s,
+                                            const int32_t *__restrict__ off, const int32_t *__restrict__ lp,
+                                            const uint64_t *__restrict__ desc, const TS *__restrict__ sval,
+                                            const TS *__restrict__ dval, int slot, bool lane_ok, int c) {
+    constexpr int BB = BS * BS;
+    SlotRsrc rs;
+    rs.desc = slice_rsrc(desc + base, (int64_t)S * 8);
+    rs.val = slice_rsrc(sval + base * MB * BB, (int64_t)S * MB * BB * sizeof(TS));
+    rs.dval = slice_rsrc(UPPER ? dval + base * BB : sval, UPPER ? (int64_t)S * BB * sizeof(TS) : 0);
     const int32_t o = off[s];
     const int nl = off[s + 1] - o - 1;
     SlotRegs<BS, TS, MB> R[PD + 1];
+    // level bounds are read one fetch ahead, so their scalar loads complete
+    // during a level's update instead of after the barrier that follows it
+    int32_t q0 = lp[o], q1 = lp[o + 1];
     auto fetch = [&](SlotRegs<BS, TS, MB> &Rk, int l) {
-        const int lc = l < nl ? l : nl - 1;
-        slot_fetch<BS, TS, MB, UPPER>(Rk, base, lp[o + lc], lp[o + lc + 1], slot, lane_ok, c, desc, sval, dval);
+        slot_fetch<BS, TS, MB, UPPER>(Rk, rs, q0, q1, slot, lane_ok, c);
+        const int ln = l + 1 < nl ? l + 1 : nl - 1;
+        q0 = lp[o + ln];
+        q1 = lp[o + ln + 1];
     };
 #pragma unroll
     for (int u = 0; u < PD; ++u) fetch(R[u], u);
@@ -399,7 +457,6 @@ __device__ __forceinline__ void sweep_slots(TC *__restrict__ y, int64_t base, in
             __syncthreads();
         }
     }
-    // remaining levels (fewer than PD+1) were fetched by the loop above
     const int rem = nl - nfull;
 #pragma unroll
     for (int u = 0; u < PD; ++u) {
@@ -432,8 +489,8 @@ __global__ __launch_bounds__(NT) void k_dd_apply_slots(
     for (int i = tid; i < S * BS; i += NT) y[i] = static_cast<TC>(rs[i]);
     __syncthreads();
     if constexpr (LIC) lic_correct_lds<BS, TC>(y, r, base, s, la, tid, NT);
-    sweep_slots<BS, TS, TC, MB, PD, false>(y, base, s, Loff, Llp, Ldesc, Lval, nullptr, slot, lane_ok, c);
-    sweep_slots<BS, TS, TC, MB, PD, true>(y, base, s, Uoff, Ulp, Udesc, Uval, Dval, slot, lane_ok, c);
+sweep_slots<BS, TS, TC, MB, PD, false>(y, base, S, s, Loff, Llp, Ldesc, Lval, nullptr, slot, lane_ok, c);
+    sweep_slots<BS, TS, TC, MB, PD, true>(y, base, S, s, Uoff, Ulp, Udesc, Uval, Dval, slot, lane_ok, c);
     double *zs = z + base * BS;
     for (int i = tid; i < S * BS; i += NT) zs[i] = static_cast<double>(y[i]);
 }

@@ -129,10 +129,12 @@ hipError_t launch_spmv(dd_ctx *h, const double *x, double *y, hipStream_t st) {
     return hipGetLastError();
 }
 
-// y = A x, one wavefront per 64/BS block rows, one workgroup partial sum per
-// dot product.  mode 0: v = A p^, dot r0.v.  mode 1: t = A s^, dots t.s and
-// t.t.  mode 2: t = A x, r = b - t (init), dots r.r and b.b.  mode 3:
-// t = A x, dot (b-t).(b-t) (true residual).
+// y = A x, one wavefront per 64/BS block rows, workgroups striding over
+// row groups (a fixed grid of at most kMaxGrid, so the dot products leave at
+// most kMaxGrid partial sums for the one-workgroup scalar step), one partial
+// sum per workgroup and dot product.  mode 0: v = A p^, dot r0.v.  mode 1:
+// t = A s^, dots t.s and t.t.  mode 2: t = A x, r = b - t (init), dots r.r
+// and b.b.  mode 3: t = A x, dot (b-t).(b-t) (true residual).
 template <int BS, int MODE>
 __global__ __launch_bounds__(kRedT) void k_spmv_dots(int64_t n, const int32_t *__restrict__ ptr,
                                                     const int32_t *__restrict__ col,
@@ -149,9 +151,10 @@ __global__ __launch_bounds__(kRedT) void k_spmv_dots(int64_t n, const int32_t *_
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t row = gw * RPW + lane / BS;
-    if (lane / BS < RPW && row < n) {
+    constexpr int RPB = RPW * (kRedT / kWave);
+    const int64_t first = (int64_t)(threadIdx.x >> 6) * RPW + lane / BS;
+    for (int64_t row = (int64_t)blockIdx.x * RPB + first; row < n; row += (int64_t)gridDim.x * RPB) {
+        if (lane / BS >= RPW) break;
         const int64_t e = row * BS + c;
         const double t = bsr_row<BS>(ptr, col, val, x, row, c);
         if constexpr (MODE == 0) {
@@ -359,7 +362,7 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
     const int32_t *state = &ks->state;
 
     const int rpb = (kWave / BS) * (kRedT / kWave);
-    const int gsp = (int)((n + rpb - 1) / rpb);  // one partial per SpMV workgroup
+    const int gsp = (int)std::min<int64_t>((n + rpb - 1) / rpb, kMaxGrid);  // one partial per workgroup
     const int gvec = (int)std::min<int64_t>((m + kRedT - 1) / kRedT, kMaxGrid);
     const int sps = h->spmv_part_stride;
 
@@ -477,8 +480,7 @@ int bicgstab_run(dd_ctx *h, const double *b, double *x, double rtol, int32_t max
     if (!h->kv) {
         int rc = h->alloc(&h->kv, 10 * h->n * h->bs);
         if (rc) return rc;
-        const int rpb = (kWave / h->bs) * (kRedT / kWave);
-        h->spmv_part_stride = (int)std::max<int64_t>((h->n + rpb - 1) / rpb, kMaxGrid);
+        h->spmv_part_stride = kMaxGrid;
         rc = h->alloc(&h->partials, (int64_t)kStride * h->spmv_part_stride);
         if (rc) return rc;
         rc = h->alloc(&h->ks, 1);
