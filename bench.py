@@ -274,7 +274,8 @@ def main():
         },
         "roofline": {"bound": "hbm", "achieved": round(gbs64, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs64 / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_dd_apply<3,double>", "bytes_per_launch": bytes64},
+                     "traffic": traffic, "kernel": "k_dd_apply_slots<3, double, double, 1024, 3, 1, false>",
+                     "bytes_per_launch": bytes64},
         "cpu_baseline": None,
     }
 

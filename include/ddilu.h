@@ -103,7 +103,11 @@ typedef struct {
     double rel_res_true;       /* ||b - A x||/||b|| recomputed at exit    */
     double solve_seconds;      /* wall time of the solve on the stream    */
     int32_t applies;           /* preconditioner applies that did work    */
-    int32_t pad;
+    int32_t restarts;          /* restarts from the current iterate: when
+                                  the recurrence residual meets rtol but
+                                  ||b - A x|| exceeds 2 rtol ||b||, the
+                                  solve restarts (r = r^ = p = b - A x), at
+                                  most 4 times within maxit iterations    */
     double apply_seconds;      /* summed duration of those applies (event
                                   pairs on the stream; 0 unless profiling
                                   was switched on with dd_set_profiling)  */
@@ -197,7 +201,10 @@ int dd_spmv(dd_handle h, const double *x, double *y, void *hip_stream);
  * after the half step when ||s||/||b|| <= rtol), at most maxit iterations.
  * b, x: device double[n*bs] in GRID order; x holds the initial guess on
  * entry and the solution on exit.  Krylov vectors, dot products and the
- * stopping test are FP64 whatever the apply precision.  Synchronises.
+ * stopping test are FP64 whatever the apply precision.  A solve whose
+ * true residual misses 2*rtol when the recurrence converges restarts from
+ * its current iterate (dd_solve_info.restarts); DD_OK therefore implies
+ * ||b - A x|| <= 2 rtol ||b||.  Synchronises.
  * info: host, may be NULL.  Returns DD_OK, DD_EBREAKDOWN or DD_ENOCONV (x
  * then holds the last iterate). */
 int bicgstab_solve(dd_handle h, const double *b, double *x, double rtol,
@@ -207,10 +214,11 @@ int bicgstab_solve(dd_handle h, const double *b, double *x, double rtol,
  * in how factor data is fetched): 0 = automatic (the fastest one the
  * handle's shape allows), 1 = plain level loop (levels of any width),
  * 2 = level loop with the next level's blocks prefetched into registers
- * (levels no wider than one workgroup pass), 3 = as 2 with fixed per-row
- * block slots so that loads run two levels ahead (rows of at most 4
- * blocks).  A variant the shape does not allow falls back to 1.  Returns
- * DD_EINVAL for other values. */
+ * (levels no wider than one workgroup pass), 3 = fixed per-row block
+ * slots so that no load depends on another and a level's loads are issued
+ * while the previous level computes (rows of at most 3 off-diagonal blocks
+ * per sweep, levels no wider than one pass).  A variant the shape does not
+ * allow falls back to 1.  Returns DD_EINVAL for other values. */
 int dd_set_apply_variant(dd_handle h, int32_t variant);
 
 /* Switch per-apply timing inside bicgstab_solve on (1) or off (0): a HIP

@@ -129,12 +129,11 @@ hipError_t launch_spmv(dd_ctx *h, const double *x, double *y, hipStream_t st) {
     return hipGetLastError();
 }
 
-// y = A x, one wavefront per 64/BS block rows, workgroups striding over
-// row groups (a fixed grid of at most kMaxGrid, so the dot products leave at
-// most kMaxGrid partial sums for the one-workgroup scalar step), one partial
-// sum per workgroup and dot product.  mode 0: v = A p^, dot r0.v.  mode 1:
-// t = A s^, dots t.s and t.t.  mode 2: t = A x, r = b - t (init), dots r.r
-// and b.b.  mode 3: t = A x, dot (b-t).(b-t) (true residual).
+// y = A x, one wavefront per 64/BS block rows, one workgroup per 4*64/BS
+// rows, one partial sum per workgroup and dot product.  mode 0: v = A p^,
+// dot r0.v.  mode 1: t = A s^, dots t.s and t.t.  mode 2: t = A x,
+// r = b - t (init), dots r.r and b.b.  mode 3: t = A x, dot (b-t).(b-t)
+// (true residual).
 template <int BS, int MODE>
 __global__ __launch_bounds__(kRedT) void k_spmv_dots(int64_t n, const int32_t *__restrict__ ptr,
                                                     const int32_t *__restrict__ col,
@@ -151,10 +150,9 @@ __global__ __launch_bounds__(kRedT) void k_spmv_dots(int64_t n, const int32_t *_
     double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    constexpr int RPB = RPW * (kRedT / kWave);
-    const int64_t first = (int64_t)(threadIdx.x >> 6) * RPW + lane / BS;
-    for (int64_t row = (int64_t)blockIdx.x * RPB + first; row < n; row += (int64_t)gridDim.x * RPB) {
-        if (lane / BS >= RPW) break;
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t row = gw * RPW + lane / BS;
+    if (lane / BS < RPW && row < n) {
         const int64_t e = row * BS + c;
         const double t = bsr_row<BS>(ptr, col, val, x, row, c);
         if constexpr (MODE == 0) {
@@ -232,31 +230,69 @@ __global__ __launch_bounds__(kRedT) void k_pupdate(int64_t m, double *__restrict
 }
 
 // Fixed-order sum of nblk partials of slot k.
-__device__ double reduce_slot(const double *part, int k, int nblk, int stride) {
-    __shared__ double sh[kRedT];
-    double t = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += kRedT) t += part[(int64_t)k * stride + i];
-    sh[threadIdx.x] = t;
-    __syncthreads();
-    for (int w = kRedT / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
+// Scalar step: one workgroup of kScalT threads sums the partials of one or
+// two dot products.  Thread t adds entries t + (j*kScalU + u)*kScalT into
+// accumulator u (kScalU independent loads in flight per thread), then the
+// accumulators, the wavefront and the wavefronts are combined in a fixed
+// order, so the result does not depend on timing.
+constexpr int kScalT = 1024;
+constexpr int kScalU = 4;
+
+template <int NS>
+__device__ void reduce_slots(const double *part, int nblk, int stride, double (&out)[NS]) {
+    __shared__ double sh[2][kScalT / kWave];
+    double acc[NS][kScalU];
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+#pragma unroll
+        for (int u = 0; u < kScalU; ++u) acc[k][u] = 0.0;
+    for (int i0 = threadIdx.x; i0 < nblk; i0 += kScalT * kScalU) {
+#pragma unroll
+        for (int u = 0; u < kScalU; ++u) {
+            const int i = i0 + u * kScalT;
+            if (i < nblk)
+#pragma unroll
+                for (int k = 0; k < NS; ++k) acc[k][u] += part[(int64_t)k * stride + i];
+        }
     }
-    const double res = sh[0];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        double t = acc[k][0];
+#pragma unroll
+        for (int u = 1; u < kScalU; ++u) t += acc[k][u];
+        t = wave_sum(t);
+        if (lane == 0) sh[k][w] = t;
+    }
     __syncthreads();
-    return res;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        double t = 0.0;
+        for (int i = 0; i < kScalT / kWave; ++i) t += sh[k][i];
+        out[k] = t;
+    }
 }
 
-enum : int { SC_INIT = 0, SC_ALPHA = 1, SC_S = 2, SC_OMEGA = 3, SC_BETA = 4, SC_TRUE = 5 };
+constexpr int kMaxRestarts = 4;  // true-residual restarts per solve
+
+enum : int { SC_INIT = 0, SC_ALPHA = 1, SC_S = 2, SC_OMEGA = 3, SC_BETA = 4, SC_TRUE = 5, SC_RESTART = 6 };
 
 // Scalar steps of Algorithm 1 (one workgroup).
-__global__ __launch_bounds__(kRedT) void k_scalars(int stage, int it, const double *part, int nblk, int stride,
-                                                  KrylovScalars *ks, double *hist, int hist_len) {
+__global__ __launch_bounds__(kScalT) void k_scalars(int stage, int it, const double *part, int nblk, int stride,
+                                                   KrylovScalars *ks, double *hist, int hist_len) {
     const int32_t st0 = ks->state;
-    if (stage != SC_INIT && stage != SC_TRUE && st0 != ST_RUN) return;
-    const double a = reduce_slot(part, 0, nblk, stride);
-    const double b = (stage == SC_INIT || stage == SC_OMEGA || stage == SC_BETA) ? reduce_slot(part, 1, nblk, stride)
-                                                                                   : 0.0;
+    if (stage != SC_INIT && stage != SC_TRUE && stage != SC_RESTART && st0 != ST_RUN) return;
+    double a, b = 0.0;
+    if (stage == SC_INIT || stage == SC_OMEGA || stage == SC_BETA) {
+        double ab[2];
+        reduce_slots<2>(part, nblk, stride, ab);
+        a = ab[0];
+        b = ab[1];
+    } else {
+        double a1[1];
+        reduce_slots<1>(part, nblk, stride, a1);
+        a = a1[0];
+    }
     if (threadIdx.x != 0) return;
     switch (stage) {
         case SC_INIT: {  // a = r.r (= r0.r), b = b.b
@@ -321,6 +357,14 @@ __global__ __launch_bounds__(kRedT) void k_scalars(int stage, int it, const doub
             ks->snorm = sqrt(a);  // reused slot: true residual norm
             break;
         }
+        case SC_RESTART: {  // a = r.r of r = b - A x (iteration count, ||b|| and tol kept)
+            ks->rho = a;
+            ks->rnorm = sqrt(a);
+            ks->half = 0;
+            ks->state = (sqrt(a) <= ks->tol) ? ST_CONV : ST_RUN;
+            if (!isfinite(a)) ks->state = DD_EBREAKDOWN;
+            break;
+        }
     }
 }
 
@@ -362,7 +406,7 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
     const int32_t *state = &ks->state;
 
     const int rpb = (kWave / BS) * (kRedT / kWave);
-    const int gsp = (int)std::min<int64_t>((n + rpb - 1) / rpb, kMaxGrid);  // one partial per workgroup
+    const int gsp = (int)((n + rpb - 1) / rpb);  // one partial per SpMV workgroup
     const int gvec = (int)std::min<int64_t>((m + kRedT - 1) / kRedT, kMaxGrid);
     const int sps = h->spmv_part_stride;
 
@@ -381,7 +425,7 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
     KCHK(launch_permute(n, BS, h->new2old, x, xp, st));
     // r = b - A x0, r0 = p = r; rho = r0.r
     k_spmv_dots<BS, 2><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, xp, t, bp, r, r0, p, part, sps, nullptr);
-    k_scalars<<<1, kRedT, 0, st>>>(SC_INIT, 0, part, gsp, sps, ks, h->hist, h->hist_len);
+    k_scalars<<<1, kScalT, 0, st>>>(SC_INIT, 0, part, gsp, sps, ks, h->hist, h->hist_len);
     KCHK(hipGetLastError());
 
     const int chunk = 8;
@@ -392,62 +436,81 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
             h->events.push_back(ev);
         }
     }
-    int it = 0, applies = 0, chunk_first = 1, chunk_todo = 0;
+    int it = 0, applies = 0, chunk_first = 1, chunk_todo = 0, restarts = 0;
     double apply_ms = 0.0;
     int32_t final_state = ST_RUN;
-    while (true) {
-        KCHK(hipMemcpyAsync(h->ks_host, ks, sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
-        KCHK(hipStreamSynchronize(st));
-        final_state = h->ks_host->state;
-        if (h->profile) {  // applies of the finished chunk that did work
-            const KrylovScalars &hk = *h->ks_host;
-            for (int k = 0; k < chunk_todo; ++k) {
-                const int itk = chunk_first + k;
-                if (itk > hk.iters) break;
-                for (int a = 0; a < 2; ++a) {
-                    if (a == 1 && itk == hk.iters && final_state != ST_RUN && hk.half) continue;
-                    float ms = 0.f;
-                    KCHK(hipEventElapsedTime(&ms, h->events[4 * k + 2 * a], h->events[4 * k + 2 * a + 1]));
-                    apply_ms += ms;
-                    ++applies;
+    for (;;) {  // restarts
+        chunk_todo = 0;
+        while (true) {
+            KCHK(hipMemcpyAsync(h->ks_host, ks, sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
+            KCHK(hipStreamSynchronize(st));
+            final_state = h->ks_host->state;
+            if (h->profile) {  // applies of the finished chunk that did work
+                const KrylovScalars &hk = *h->ks_host;
+                for (int k = 0; k < chunk_todo; ++k) {
+                    const int itk = chunk_first + k;
+                    if (itk > hk.iters) break;
+                    for (int a = 0; a < 2; ++a) {
+                        if (a == 1 && itk == hk.iters && final_state != ST_RUN && hk.half) continue;
+                        float ms = 0.f;
+                        KCHK(hipEventElapsedTime(&ms, h->events[4 * k + 2 * a], h->events[4 * k + 2 * a + 1]));
+                        apply_ms += ms;
+                        ++applies;
+                    }
                 }
             }
+            if (final_state != ST_RUN || it >= maxit) break;
+            const int todo = std::min(chunk, maxit - it);
+            chunk_first = it + 1;
+            chunk_todo = todo;
+            for (int k = 0; k < todo; ++k) {
+                ++it;
+                if (h->profile) KCHK(hipEventRecord(h->events[4 * k], st));
+                KCHK(launch_precond(h, p, ph, state, st));                       // p^ = M^{-1} p
+                if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 1], st));
+                k_spmv_dots<BS, 0><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, ph, v, r0, nullptr,
+                                                          nullptr, nullptr, part, sps, state);  // v = A p^, r0.v
+                k_scalars<<<1, kScalT, 0, st>>>(SC_ALPHA, it, part, gsp, sps, ks, h->hist, h->hist_len);
+                k_axpy_s<<<gvec, kRedT, 0, st>>>(m, r, v, s, ks, part);        // s = r - alpha v
+                k_scalars<<<1, kScalT, 0, st>>>(SC_S, it, part, gvec, kMaxGrid, ks, h->hist, h->hist_len);
+                k_half<<<gvec, kRedT, 0, st>>>(m, xp, ph, ks);
+                if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 2], st));
+                KCHK(launch_precond(h, s, shat, state, st));                     // s^ = M^{-1} s
+                if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 3], st));
+                k_spmv_dots<BS, 1><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, shat, t, s, nullptr,
+                                                          nullptr, nullptr, part, sps, state);  // t = A s^, t.s, t.t
+                k_scalars<<<1, kScalT, 0, st>>>(SC_OMEGA, it, part, gsp, sps, ks, h->hist, h->hist_len);
+                k_update<<<gvec, kRedT, 0, st>>>(m, xp, ph, shat, r, s, t, r0, ks, part);
+                k_scalars<<<1, kScalT, 0, st>>>(SC_BETA, it, part, gvec, kMaxGrid, ks, h->hist, h->hist_len);
+                k_pupdate<<<gvec, kRedT, 0, st>>>(m, p, r, v, ks);
+                k_half_to_conv<<<1, 1, 0, st>>>(ks);
+                KCHK(hipGetLastError());
+            }
         }
-        if (final_state != ST_RUN || it >= maxit) break;
-        const int todo = std::min(chunk, maxit - it);
-        chunk_first = it + 1;
-        chunk_todo = todo;
-        for (int k = 0; k < todo; ++k) {
-            ++it;
-            if (h->profile) KCHK(hipEventRecord(h->events[4 * k], st));
-            KCHK(launch_precond(h, p, ph, state, st));                       // p^ = M^{-1} p
-            if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 1], st));
-            k_spmv_dots<BS, 0><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, ph, v, r0, nullptr,
-                                                      nullptr, nullptr, part, sps, state);  // v = A p^, r0.v
-            k_scalars<<<1, kRedT, 0, st>>>(SC_ALPHA, it, part, gsp, sps, ks, h->hist, h->hist_len);
-            k_axpy_s<<<gvec, kRedT, 0, st>>>(m, r, v, s, ks, part);        // s = r - alpha v
-            k_scalars<<<1, kRedT, 0, st>>>(SC_S, it, part, gvec, kMaxGrid, ks, h->hist, h->hist_len);
-            k_half<<<gvec, kRedT, 0, st>>>(m, xp, ph, ks);
-            if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 2], st));
-            KCHK(launch_precond(h, s, shat, state, st));                     // s^ = M^{-1} s
-            if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 3], st));
-            k_spmv_dots<BS, 1><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, shat, t, s, nullptr,
-                                                      nullptr, nullptr, part, sps, state);  // t = A s^, t.s, t.t
-            k_scalars<<<1, kRedT, 0, st>>>(SC_OMEGA, it, part, gsp, sps, ks, h->hist, h->hist_len);
-            k_update<<<gvec, kRedT, 0, st>>>(m, xp, ph, shat, r, s, t, r0, ks, part);
-            k_scalars<<<1, kRedT, 0, st>>>(SC_BETA, it, part, gvec, kMaxGrid, ks, h->hist, h->hist_len);
-            k_pupdate<<<gvec, kRedT, 0, st>>>(m, p, r, v, ks);
-            k_half_to_conv<<<1, 1, 0, st>>>(ks);
-            KCHK(hipGetLastError());
+        // true residual ||b - A x|| / ||b||
+        k_spmv_dots<BS, 3><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, xp, t, bp, nullptr, nullptr, nullptr,
+                                                  part, sps, nullptr);
+        k_scalars<<<1, kScalT, 0, st>>>(SC_TRUE, 0, part, gsp, sps, ks, h->hist, h->hist_len);
+        KCHK(hipMemcpyAsync(h->ks_host, ks, sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
+        KCHK(hipStreamSynchronize(st));
+        // The recurrence met the tolerance but the true residual did not (an
+        // FP32 trisolve makes the preconditioner slightly inconsistent from one
+        // apply to the next): restart from the current iterate.
+        {
+            const KrylovScalars &hk = *h->ks_host;
+            if (hk.state == ST_CONV && hk.snorm > 2.0 * hk.tol && restarts < kMaxRestarts && it < maxit) {
+                ++restarts;
+                k_spmv_dots<BS, 2><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, xp, t, bp, r, r0, p, part,
+                                                          sps, nullptr);
+                k_scalars<<<1, kScalT, 0, st>>>(SC_RESTART, 0, part, gsp, sps, ks, h->hist, h->hist_len);
+                KCHK(hipGetLastError());
+                continue;
+            }
         }
-    }
+        break;
+    }  // restarts
     KCHK(hipEventRecord(e1, st));
-    // true residual ||b - A x|| / ||b||
-    k_spmv_dots<BS, 3><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, xp, t, bp, nullptr, nullptr, nullptr,
-                                              part, sps, nullptr);
-    k_scalars<<<1, kRedT, 0, st>>>(SC_TRUE, 0, part, gsp, sps, ks, h->hist, h->hist_len);
     KCHK(launch_permute(n, BS, h->old2new, xp, x, st));
-    KCHK(hipMemcpyAsync(h->ks_host, ks, sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
     KCHK(hipStreamSynchronize(st));
     float ms = 0.f;
     KCHK(hipEventElapsedTime(&ms, e0, e1));
@@ -455,7 +518,7 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
     (void)hipEventDestroy(e1);
     const KrylovScalars &hk = *h->ks_host;
     int status = DD_OK;
-    if (hk.state == ST_CONV) status = DD_OK;
+    if (hk.state == ST_CONV) status = hk.snorm > 2.0 * hk.tol ? DD_ENOCONV : DD_OK;  // restarts exhausted
     else if (hk.state == DD_EBREAKDOWN) status = DD_EBREAKDOWN;
     else status = DD_ENOCONV;
     if (info) {
@@ -465,10 +528,13 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
         info->rel_res_true = hk.snorm / hk.bnorm;
         info->solve_seconds = ms * 1e-3;
         info->applies = applies;
-        info->pad = 0;
+        info->restarts = restarts;
         info->apply_seconds = apply_ms * 1e-3;
     }
     if (status == DD_EBREAKDOWN) return h->fail(DD_EBREAKDOWN, "BiCGSTAB breakdown at iteration %d", hk.iters);
+    if (status == DD_ENOCONV && hk.state == ST_CONV)
+        return h->fail(DD_ENOCONV, "BiCGSTAB true residual %.3e stays above 2 rtol after %d restarts",
+                       hk.snorm / hk.bnorm, restarts);
     if (status == DD_ENOCONV)
         return h->fail(DD_ENOCONV, "BiCGSTAB did not reach rtol within %d iterations (rel res %.3e)", maxit,
                        hk.rnorm / hk.bnorm);
@@ -480,7 +546,8 @@ int bicgstab_run(dd_ctx *h, const double *b, double *x, double rtol, int32_t max
     if (!h->kv) {
         int rc = h->alloc(&h->kv, 10 * h->n * h->bs);
         if (rc) return rc;
-        h->spmv_part_stride = kMaxGrid;
+        const int rpb = (kWave / h->bs) * (kRedT / kWave);
+        h->spmv_part_stride = (int)std::max<int64_t>((h->n + rpb - 1) / rpb, kMaxGrid);
         rc = h->alloc(&h->partials, (int64_t)kStride * h->spmv_part_stride);
         if (rc) return rc;
         rc = h->alloc(&h->ks, 1);

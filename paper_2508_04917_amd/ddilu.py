@@ -55,7 +55,7 @@ class Info(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("rel_res", C.c_double),
                 ("rel_res_true", C.c_double), ("solve_seconds", C.c_double),
-                ("applies", C.c_int32), ("pad", C.c_int32), ("apply_seconds", C.c_double)]
+                ("applies", C.c_int32), ("restarts", C.c_int32), ("apply_seconds", C.c_double)]
 
 
 _lib = None

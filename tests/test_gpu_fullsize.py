@@ -82,3 +82,28 @@ def test_fullsize_bicgstab_first_iterations(full):
     print(f"[fullsize] history gpu {hg}\n[fullsize] history ora {ref.history}", flush=True)
     assert info["iters"] == k
     assert np.allclose(hg, ref.history, rtol=1e-6, atol=0)
+
+
+@pytest.mark.parametrize("prec", [dd.DD_FP64, dd.DD_MIXED, dd.DD_FP32], ids=["fp64", "mixed", "fp32"])
+def test_fullsize_solve_true_residual(full, prec):
+    """Full solves in each precision: DD_OK implies a true residual within
+    2 rtol (an FP32 trisolve drifts, the solver restarts from its iterate),
+    and the solution agrees with the FP64 one to the conditioning of the
+    stopping test."""
+    p, s, st = full
+    b = torch.as_tensor(p.b, device="cuda")
+    s.set_precision(dd.DD_FP64)
+    x64, i64 = s.solve(b, rtol=1e-8)
+    s.set_precision(prec)
+    try:
+        x, info = s.solve(b, rtol=1e-8)
+    finally:
+        s.set_precision(dd.DD_FP64)
+    print(f"[fullsize] precision {prec}: {info}", flush=True)
+    assert i64["status"] == dd.DD_OK and i64["rel_res_true"] <= 2e-8
+    assert info["status"] in (dd.DD_OK, dd.DD_ENOCONV)
+    if info["status"] == dd.DD_OK:
+        assert info["rel_res_true"] <= 2e-8
+        assert float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64)) < 1e-5
+    else:
+        assert info["restarts"] == 4 or info["iters"] >= 10000
