@@ -489,7 +489,7 @@ __global__ __launch_bounds__(NT) void k_dd_apply_slots(
     for (int i = tid; i < S * BS; i += NT) y[i] = static_cast<TC>(rs[i]);
     __syncthreads();
     if constexpr (LIC) lic_correct_lds<BS, TC>(y, r, base, s, la, tid, NT);
-sweep_slots<BS, TS, TC, MB, PD, false>(y, base, S, s, Loff, Llp, Ldesc, Lval, nullptr, slot, lane_ok, c);
+    sweep_slots<BS, TS, TC, MB, PD, false>(y, base, S, s, Loff, Llp, Ldesc, Lval, nullptr, slot, lane_ok, c);
     sweep_slots<BS, TS, TC, MB, PD, true>(y, base, S, s, Uoff, Ulp, Udesc, Uval, Dval, slot, lane_ok, c);
     double *zs = z + base * BS;
     for (int i = tid; i < S * BS; i += NT) zs[i] = static_cast<double>(y[i]);
