@@ -35,27 +35,79 @@ namespace ddilu {
 // Learned interface correction inside the apply: once the subdomain's r is
 // in LDS, every row with cut faces adds sum_f C_f r_J (J in a neighbouring
 // subdomain, read from r in global memory; faces in CSR order).  One lane per
-// (row, component), so the update order is fixed.
+// (row, component), so the update order is fixed.  Each lane handles two
+// rows per pass and fetches in three dependent steps (row record; column
+// and coefficients of up to kLicFaces faces; r_J), with positions past the
+// end clamped to valid ones and discarded by selects, so the loads of a step
+// are all in flight together.  Rows with more faces finish in a loop.
 struct LicArgs {
-    const int32_t *bsub, *brow, *fptr, *fJ;
+    const int32_t *bsub;
+    const int4 *brow;  // {row, first face, face count, 0}
+    const int32_t *fJ;
     const float *C;
 };
+
+constexpr int kLicFaces = 3;  // a 7-point row has at most 3 cut faces unless a subdomain is one cell thin
 
 template <int BS, typename TC>
 __device__ __forceinline__ void lic_correct_lds(TC *__restrict__ y, const double *__restrict__ r, int64_t base, int s,
                                                 const LicArgs &la, int tid, int nt) {
     const int32_t b0 = la.bsub[s], b1 = la.bsub[s + 1];
-    for (int item = tid; item < (b1 - b0) * BS; item += nt) {
-        const int k = item / BS, c = item % BS;
-        const int64_t gi = la.brow[b0 + k];
-        double acc = 0.0;
-        for (int32_t f = la.fptr[gi]; f < la.fptr[gi + 1]; ++f) {
-            const int64_t J = la.fJ[f];
-            const float *Cf = la.C + (int64_t)f * BS * BS + c * BS;
+    const int nitems = (b1 - b0) * BS;
+    for (int i0 = tid; i0 < nitems; i0 += 2 * nt) {
+        int item[2];
+        bool ok[2];
+        int4 ri[2];
 #pragma unroll
-            for (int d = 0; d < BS; ++d) acc += (double)Cf[d] * r[J * BS + d];
+        for (int u = 0; u < 2; ++u) {
+            ok[u] = i0 + u * nt < nitems;
+            item[u] = ok[u] ? i0 + u * nt : i0;
+            ri[u] = la.brow[b0 + item[u] / BS];
         }
-        y[(gi - base) * BS + c] += static_cast<TC>(acc);
+        __builtin_amdgcn_sched_barrier(0);
+        int64_t J[2][kLicFaces];
+        float cf[2][kLicFaces][BS];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int c = item[u] % BS;
+#pragma unroll
+            for (int k = 0; k < kLicFaces; ++k) {
+                const int32_t f = ri[u].y + min(k, ri[u].z - 1);
+                J[u][k] = la.fJ[f];
+                const float *Cf = la.C + (int64_t)f * BS * BS + c * BS;
+#pragma unroll
+                for (int d = 0; d < BS; ++d) cf[u][k][d] = Cf[d];
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        double rv[2][kLicFaces][BS];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int k = 0; k < kLicFaces; ++k)
+#pragma unroll
+                for (int d = 0; d < BS; ++d) rv[u][k][d] = r[J[u][k] * BS + d];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (!ok[u]) continue;
+            const int c = item[u] % BS;
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < kLicFaces; ++k) {
+                double t = acc;
+#pragma unroll
+                for (int d = 0; d < BS; ++d) t += (double)cf[u][k][d] * rv[u][k][d];
+                acc = k < ri[u].z ? t : acc;
+            }
+            for (int32_t f = ri[u].y + kLicFaces; f < ri[u].y + ri[u].z; ++f) {
+                const int64_t Jf = la.fJ[f];
+                const float *Cf = la.C + (int64_t)f * BS * BS + c * BS;
+#pragma unroll
+                for (int d = 0; d < BS; ++d) acc += (double)Cf[d] * r[Jf * BS + d];
+            }
+            y[(ri[u].x - base) * BS + c] += static_cast<TC>(acc);
+        }
     }
     __syncthreads();
 }
@@ -527,7 +579,7 @@ static void factor_ptrs(const dd_ctx *h, bool slots, const TS **lv, const TS **u
 }
 
 static LicArgs lic_args(const dd_ctx *h) {
-    return LicArgs{h->lic.bsub, h->lic.brow, h->lic.fptr, h->lic.fJ, h->lic.C};
+    return LicArgs{h->lic.bsub, h->lic.brow, h->lic.fJ, h->lic.C};
 }
 
 template <int BS, typename TS, typename TC, int NT, int MB, bool LIC>

@@ -60,7 +60,7 @@ struct Lic {
     int32_t *fptr = nullptr;      // [n+1] faces of each row (CSR order)
     int32_t *fI = nullptr, *fJ = nullptr, *fq = nullptr;  // [nf] row, column, block position in A
     int32_t *diag = nullptr;      // [n] diagonal block position of each row of A
-    int32_t *brow = nullptr;      // [nb] rows with faces, ascending
+    int4 *brow = nullptr;         // [nb] rows with faces, ascending: {row, first face, face count, 0}
     int32_t *bsub = nullptr;      // [nsub+1] first entry of brow of each subdomain
     float *X = nullptr;           // [nf*27] features
     float *C = nullptr;           // [nf*9] coefficients

@@ -58,10 +58,10 @@ __global__ void k_bflag(int64_t n, const int32_t *__restrict__ fptr, int32_t *fl
 }
 
 __global__ void k_bfill(int64_t n, int S, const int32_t *__restrict__ fptr, const int32_t *__restrict__ bpos,
-                        int32_t *brow, int32_t *bsub) {
+                        int4 *brow, int32_t *bsub) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    if (fptr[i + 1] > fptr[i]) brow[bpos[i]] = (int32_t)i;
+    if (fptr[i + 1] > fptr[i]) brow[bpos[i]] = make_int4((int32_t)i, fptr[i], fptr[i + 1] - fptr[i], 0);
     if (i % S == 0) bsub[i / S] = bpos[i];  // first boundary row of the subdomain
 }
 
