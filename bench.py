@@ -196,6 +196,19 @@ def main():
                 log(f"WARNING: {k} solve ended with status {rec[k]['status']}")
         return rec
 
+    # reference: a plain device copy of 1 GiB (read + write), outside the timed region
+    csrc = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    cdst = torch.empty_like(csrc)
+    cev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    cdst.copy_(csrc)
+    cev[0].record()
+    for _ in range(5):
+        cdst.copy_(csrc)
+    cev[1].record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * csrc.numel() * 8 * 5 / (cev[0].elapsed_time(cev[1]) * 1e-3) / 1e9
+    del csrc, cdst
+
     for w in range(args.warmup):
         log(f"warmup step {w + 1}/{args.warmup}")
         step()
@@ -275,7 +288,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(gbs64, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs64 / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "k_dd_apply_slots<3, double, double, 1024, 3, 1, false>",
-                     "bytes_per_launch": bytes64},
+                     "bytes_per_launch": bytes64, "copy_GBs": round(copy_gbs, 1),
+                     "frac_of_copy": round(gbs64 / copy_gbs, 4)},
         "cpu_baseline": None,
     }
 

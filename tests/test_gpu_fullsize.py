@@ -107,3 +107,37 @@ def test_fullsize_solve_true_residual(full, prec):
         assert float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64)) < 1e-5
     else:
         assert info["restarts"] == 4 or info["iters"] >= 10000
+
+
+def test_fullsize_learned_correction(full):
+    """The learned interface correction at full size with the shipped
+    parameters: faces bit-exact, features and MLP coefficients on sampled
+    faces, and the corrected apply (with the GPU's coefficients) against the
+    oracle's corrected apply."""
+    from paper_2508_04917_amd.lic import load_params
+    p, s, st = full
+    L = O.LicOracle(st)
+    print(f"[fullsize] oracle faces: {L.nf}", flush=True)
+    P = load_params()[0]
+    dd.lic_setup(s.h)
+    dd.lic_set_params(s.h, torch.as_tensor(P, device="cuda"))
+    try:
+        fI, fJ, X = dd.lic_get_faces(s.h)
+        assert np.array_equal(np_(fI), L.faces[0]) and np.array_equal(np_(fJ), L.faces[1])
+        idx = np.random.default_rng(33).choice(L.nf, 4096, replace=False)
+        Xg = np_(X)[idx].astype(np.float64)
+        assert np.allclose(Xg, L.X[idx], rtol=1e-6, atol=1e-7)
+        Cg = dd.lic_get_coeffs(s.h, L.nf)
+        Co = O.mlp_forward(P.astype(np.float64), L.X[idx])[2].reshape(-1, 3, 3)
+        ce = np.linalg.norm(np_(Cg)[idx] - Co) / np.linalg.norm(Co)
+        print(f"[fullsize] sampled MLP coefficients rel err {ce:.2e}", flush=True)
+        assert ce < 1e-5
+        dd.lic_set_coeffs(s.h, Cg)
+        r = np.random.default_rng(34).standard_normal(st.n * 3)
+        zg = np_(s.apply(torch.as_tensor(r, device="cuda")))
+        zo = L.apply(np_(Cg).astype(np.float64), r)
+        err = np.linalg.norm(zg - zo) / np.linalg.norm(zo)
+        print(f"[fullsize] corrected apply rel err {err:.2e}", flush=True)
+        assert err < 1e-12
+    finally:
+        dd.lic_set_params(s.h, None)
