@@ -333,7 +333,7 @@ static int build_slots(dd_ctx *h, hipStream_t st) {
     for (int w = 0; w < 2; ++w) {
         Sweep &s = h->sw[w];
         RCHK(h->alloc(&s.desc, h->n));
-        RCHK(h->alloc(&s.sval64, h->n * h->slots * bb));
+        RCHK(h->alloc(&s.sval64, h->n * (h->slots + w) * bb));  // upper: + inv_D
         HCHK(launch_pack_slots(h, w, st));
     }
     return DD_OK;
@@ -344,7 +344,7 @@ static int ensure_fp32(dd_ctx *h, hipStream_t st) {
     if (h->sw[0].val32 && h->sw[1].val32 && h->sw[1].d32 && (!h->slots || h->sw[0].sval32)) return DD_OK;
     for (int w = 0; w < 2; ++w) {
         if (!h->sw[w].val32) RCHK(h->alloc(&h->sw[w].val32, h->sw[w].nblk * bb));
-        if (h->slots && !h->sw[w].sval32) RCHK(h->alloc(&h->sw[w].sval32, h->n * h->slots * bb));
+        if (h->slots && !h->sw[w].sval32) RCHK(h->alloc(&h->sw[w].sval32, h->n * (h->slots + w) * bb));
     }
     if (!h->sw[1].d32) RCHK(h->alloc(&h->sw[1].d32, h->n * bb));
     HCHK(launch_cast32(h, st));

@@ -430,62 +430,70 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t slice_rsrc(const void *p, int6
 
 constexpr uint32_t kOobOffset = 0x80000000u;  // beyond every slice (slices < 2 GiB)
 
-template <typename TS, int BS>
-__device__ __forceinline__ void buf_load_row(__amdgpu_buffer_rsrc_t rs, uint32_t off, TS *v) {
-    if constexpr (sizeof(TS) == 8 && BS == 3) {
-        struct D2 { double x, y; };
-        const D2 a = __builtin_bit_cast(D2, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
-        v[0] = a.x;
-        v[1] = a.y;
-        v[2] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off + 16, 0, 0));
-    } else if constexpr (sizeof(TS) == 4 && BS == 3) {
-        // 64 + 32 bits (the 96-bit builtin is avoided: this compiler lowers
-        // it to a single dword load)
-        struct F2 { float x, y; };
-        const F2 a = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
-        v[0] = a.x;
-        v[1] = a.y;
-        v[2] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + 8, 0, 0));
-    } else if constexpr (sizeof(TS) == 8) {
-        v[0] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+// N consecutive values starting at byte offset off, in the widest loads
+// that fit (16, then 8, then 4 bytes).
+template <typename TS, int N>
+__device__ __forceinline__ void buf_load_run(__amdgpu_buffer_rsrc_t rs, uint32_t off, TS (&v)[N]) {
+    constexpr int PER16 = 16 / (int)sizeof(TS);
+    int i = 0;
+#pragma unroll
+    for (; i + PER16 <= N; i += PER16) {
+        struct Q { TS x[PER16]; };
+        const Q q = __builtin_bit_cast(Q, __builtin_amdgcn_raw_buffer_load_b128(rs, off + i * (uint32_t)sizeof(TS), 0, 0));
+#pragma unroll
+        for (int j = 0; j < PER16; ++j) v[i + j] = q.x[j];
+    }
+    if constexpr (sizeof(TS) == 4) {
+        if (i + 2 <= N) {
+            struct F2 { float x, y; };
+            const F2 q = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(rs, off + i * 4u, 0, 0));
+            v[i] = q.x;
+            v[i + 1] = q.y;
+            i += 2;
+        }
+        if (i < N) v[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + i * 4u, 0, 0));
     } else {
-        v[0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+        if (i < N) v[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off + i * 8u, 0, 0));
     }
 }
 
 struct SlotRsrc {
-    __amdgpu_buffer_rsrc_t desc, val, dval;
+    __amdgpu_buffer_rsrc_t desc, val;
 };
 
+// Per position, the BS lanes of its row each read one contiguous run: lane c
+// holds row c of every slot block (and, in the upper sweep, row c of inv_D),
+// NV = (MB [+1]) * BS values, so a lane issues ceil(NV * sizeof(TS) / 16)
+// loads rather than two per block.
 template <int BS, typename TS, int MB, bool UPPER>
 __device__ __forceinline__ void slot_fetch(SlotRegs<BS, TS, MB> &R, const SlotRsrc &rs, int32_t p0, int32_t p1,
                                            int slot, bool lane_ok, int c) {
-    constexpr int BB = BS * BS;
+    constexpr int NV = (MB + (UPPER ? 1 : 0)) * BS;
     const int32_t p = p0 + slot;
     R.ok = lane_ok && p < p1;
     const uint32_t pd = R.ok ? (uint32_t)p * 8u : kOobOffset;
     R.desc = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(rs.desc, pd, 0, 0));
+    TS vals[NV];
+    const uint32_t off = R.ok ? (uint32_t)((p * BS * NV + c * NV) * sizeof(TS)) : kOobOffset;
+    buf_load_run<TS, NV>(rs.val, off, vals);
 #pragma unroll
-    for (int k = 0; k < MB; ++k) {
-        const uint32_t off = R.ok ? (uint32_t)(((p * MB + k) * BB + c * BS) * sizeof(TS)) : kOobOffset;
-        buf_load_row<TS, BS>(rs.val, off, R.v[k]);
-    }
-    if constexpr (UPPER) {
-        const uint32_t off = R.ok ? (uint32_t)((p * BB + c * BS) * sizeof(TS)) : kOobOffset;
-        buf_load_row<TS, BS>(rs.dval, off, R.d);
-    }
+    for (int k = 0; k < MB; ++k)
+#pragma unroll
+        for (int d = 0; d < BS; ++d) R.v[k][d] = vals[k * BS + d];
+    if constexpr (UPPER)
+#pragma unroll
+        for (int d = 0; d < BS; ++d) R.d[d] = vals[MB * BS + d];
 }
 
 template <int BS, typename TS, typename TC, int MB, int PD, bool UPPER>
 __device__ __forceinline__ void sweep_slots(TC *__restrict__ y, int64_t base, int S, int s,
                                             const int32_t *__restrict__ off, const int32_t *__restrict__ lp,
                                             const uint64_t *__restrict__ desc, const TS *__restrict__ sval,
-                                            const TS *__restrict__ dval, int slot, bool lane_ok, int c) {
-    constexpr int BB = BS * BS;
+                                            int slot, bool lane_ok, int c) {
+    constexpr int PS = (MB + (UPPER ? 1 : 0)) * BS * BS;  // values per position
     SlotRsrc rs;
     rs.desc = slice_rsrc(desc + base, (int64_t)S * 8);
-    rs.val = slice_rsrc(sval + base * MB * BB, (int64_t)S * MB * BB * sizeof(TS));
-    rs.dval = slice_rsrc(UPPER ? dval + base * BB : sval, UPPER ? (int64_t)S * BB * sizeof(TS) : 0);
+    rs.val = slice_rsrc(sval + base * PS, (int64_t)S * PS * sizeof(TS));
     const int32_t o = off[s];
     const int nl = off[s + 1] - o - 1;
     SlotRegs<BS, TS, MB> R[PD + 1];
@@ -524,7 +532,7 @@ __global__ __launch_bounds__(NT) void k_dd_apply_slots(
     const double *__restrict__ r, double *__restrict__ z, int S, const int32_t *__restrict__ Loff,
     const int32_t *__restrict__ Llp, const uint64_t *__restrict__ Ldesc, const TS *__restrict__ Lval,
     const int32_t *__restrict__ Uoff, const int32_t *__restrict__ Ulp, const uint64_t *__restrict__ Udesc,
-    const TS *__restrict__ Uval, const TS *__restrict__ Dval, const int32_t *__restrict__ state, LicArgs la) {
+    const TS *__restrict__ Uval, const int32_t *__restrict__ state, LicArgs la) {
     if (state != nullptr && *state != 0) return;
     constexpr int RPW = kWave / BS;
     extern __shared__ unsigned char dd_smem[];
@@ -541,8 +549,8 @@ __global__ __launch_bounds__(NT) void k_dd_apply_slots(
     for (int i = tid; i < S * BS; i += NT) y[i] = static_cast<TC>(rs[i]);
     __syncthreads();
     if constexpr (LIC) lic_correct_lds<BS, TC>(y, r, base, s, la, tid, NT);
-    sweep_slots<BS, TS, TC, MB, PD, false>(y, base, S, s, Loff, Llp, Ldesc, Lval, nullptr, slot, lane_ok, c);
-    sweep_slots<BS, TS, TC, MB, PD, true>(y, base, S, s, Uoff, Ulp, Udesc, Uval, Dval, slot, lane_ok, c);
+    sweep_slots<BS, TS, TC, MB, PD, false>(y, base, S, s, Loff, Llp, Ldesc, Lval, slot, lane_ok, c);
+    sweep_slots<BS, TS, TC, MB, PD, true>(y, base, S, s, Uoff, Ulp, Udesc, Uval, slot, lane_ok, c);
     double *zs = z + base * BS;
     for (int i = tid; i < S * BS; i += NT) zs[i] = static_cast<double>(y[i]);
 }
@@ -584,7 +592,7 @@ static LicArgs lic_args(const dd_ctx *h) {
 
 template <int BS, typename TS, typename TC, int NT, int MB, bool LIC>
 static hipError_t launch_slots(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st,
-                               const TS *lv, const TS *uv, const TS *dv) {
+                               const TS *lv, const TS *uv) {
     constexpr int PD = sizeof(TS) == 8 ? DDILU_PD64 : DDILU_PD32;
     auto kern = k_dd_apply_slots<BS, TS, TC, NT, MB, PD, LIC>;
     static bool done = false;
@@ -592,17 +600,17 @@ static hipError_t launch_slots(dd_ctx *h, const double *r, double *z, const int3
     if (e != hipSuccess) return e;
     const int lds = h->S * BS * (int)sizeof(TC);
     kern<<<h->nsub, NT, lds, st>>>(r, z, h->S, h->lev[0].off, h->lev[0].ptr, h->sw[0].desc, lv, h->lev[1].off,
-                                   h->lev[1].ptr, h->sw[1].desc, uv, dv, state, lic_args(h));
+                                   h->lev[1].ptr, h->sw[1].desc, uv, state, lic_args(h));
     return hipGetLastError();
 }
 
 template <int BS, typename TS, typename TC, int NT, bool LIC>
 static hipError_t launch_slots_mb(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st,
-                                  const TS *lv, const TS *uv, const TS *dv) {
+                                  const TS *lv, const TS *uv) {
     switch (h->slots) {
-        case 1: return launch_slots<BS, TS, TC, NT, 1, LIC>(h, r, z, state, st, lv, uv, dv);
-        case 2: return launch_slots<BS, TS, TC, NT, 2, LIC>(h, r, z, state, st, lv, uv, dv);
-        default: return launch_slots<BS, TS, TC, NT, 3, LIC>(h, r, z, state, st, lv, uv, dv);
+        case 1: return launch_slots<BS, TS, TC, NT, 1, LIC>(h, r, z, state, st, lv, uv);
+        case 2: return launch_slots<BS, TS, TC, NT, 2, LIC>(h, r, z, state, st, lv, uv);
+        default: return launch_slots<BS, TS, TC, NT, 3, LIC>(h, r, z, state, st, lv, uv);
     }
 }
 
@@ -621,8 +629,8 @@ static hipError_t launch_typed(dd_ctx *h, const double *r, double *z, const int3
         const TS *lv, *uv, *dv;
         factor_ptrs<TS>(h, true, &lv, &uv, &dv);
         if constexpr (BS == 3)
-            if (lic) return launch_slots_mb<BS, TS, TC, NT, true>(h, r, z, state, st, lv, uv, dv);
-        return launch_slots_mb<BS, TS, TC, NT, false>(h, r, z, state, st, lv, uv, dv);
+            if (lic) return launch_slots_mb<BS, TS, TC, NT, true>(h, r, z, state, st, lv, uv);
+        return launch_slots_mb<BS, TS, TC, NT, false>(h, r, z, state, st, lv, uv);
     }
     const TS *lv, *uv, *dv;
     factor_ptrs<TS>(h, false, &lv, &uv, &dv);
@@ -694,8 +702,8 @@ template <int NT>
 static hipError_t launch_adjoint_nt(dd_ctx *h, const double *g, double *a, hipStream_t st) {
     constexpr int RPP = (kWave / 3) * (NT / kWave);
     if (h->max_level_width > RPP) return hipErrorInvalidValue;
-    const double *lv = h->lic.adj_val[0], *uv = h->lic.adj_val[1], *dv = h->lic.adj_d;
-    return launch_slots_mb<3, double, double, NT, false>(h, g, a, nullptr, st, lv, uv, dv);
+    const double *lv = h->lic.adj_val[0], *uv = h->lic.adj_val[1];
+    return launch_slots_mb<3, double, double, NT, false>(h, g, a, nullptr, st, lv, uv);
 }
 
 hipError_t launch_apply_adjoint(dd_ctx *h, const double *g, double *a, hipStream_t st) {

@@ -32,12 +32,14 @@ struct Sweep {
     int64_t nblk = 0;
     int32_t max_row = 0;        // most blocks of any row in this sweep
     // Slot layout (when every row has at most kMaxSlots blocks): position p
-    // owns MB consecutive block slots p*MB .. p*MB+MB-1 (MB = the handle's
-    // slot count); unused slots hold zero blocks.  The address of a block is
-    // then a function of the position alone, so a sweep can issue its loads
-    // without first reading row offsets.
+    // owns MB block slots (MB = the handle's slot count; unused slots hold
+    // zero blocks) and, in the upper sweep, its inv_D block.  Per position the
+    // values are stored as BS runs, run i = row i of every slot block then
+    // row i of inv_D, so the BS lanes of a row each read one contiguous run.
+    // The address of a block is a function of the position alone, so a sweep
+    // can issue its loads without first reading row offsets.
     uint64_t *desc = nullptr;   // [n] local row | column of slot k << 16(k+1); 0xFFFF empty
-    double *sval64 = nullptr;   // [n*MB*bb]
+    double *sval64 = nullptr;   // [n*MB*bb] lower, [n*(MB+1)*bb] upper
     float *sval32 = nullptr;
 };
 
@@ -68,8 +70,7 @@ struct Lic {
     double *wpart = nullptr, *rpart = nullptr;
     double *Z = nullptr, *G = nullptr, *A = nullptr;
     int32_t work_q = 0;
-    double *adj_val[2] = {nullptr, nullptr};  // transposed slot streams (U^T lower, L^T upper)
-    double *adj_d = nullptr;                  // inv_D^T per upper position
+    double *adj_val[2] = {nullptr, nullptr};  // transposed slot streams (U^T lower, L^T + inv_D^T upper)
 };
 
 // Device scalars of one BiCGSTAB run (all FP64 except the control words).

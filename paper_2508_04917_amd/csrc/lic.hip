@@ -297,16 +297,18 @@ __global__ void k_adam(int np, float *P, const float *__restrict__ G, float *M, 
 // ------------------------------------------------------------ adjoint streams
 // Values of the transposed sweeps in the slot layout (same positions and
 // columns as the forward sweeps, which requires a structurally symmetric
-// pattern): lower sweep of U^T: slot k of row I holds (Uhat_{J_k I})^T;
-// upper sweep of L^T: slot k holds (L_{K_k I})^T; diagonal inv_D_I^T.
+// pattern; lane-contiguous runs as in the forward streams): lower sweep of
+// U^T: slot k of row I holds (Uhat_{J_k I})^T; upper sweep of L^T: slot k
+// holds (L_{K_k I})^T, followed by inv_D_I^T.
 __global__ void k_pack_adjoint(int64_t n, int S, int which, int MB, const int32_t *__restrict__ tptr,
                                const int32_t *__restrict__ tcol, const double *__restrict__ lu,
-                               const double *__restrict__ invd, const int32_t *__restrict__ rows, double *sval,
-                               double *dval) {
+                               const double *__restrict__ invd, const int32_t *__restrict__ rows, double *sval) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int64_t base = (p / S) * (int64_t)S;
     const int64_t gi = base + rows[p];
+    const int NV = (MB + which) * 3;
+    double *o = sval + p * 3 * NV;
     int k = 0;
     for (int32_t q = tptr[gi]; q < tptr[gi + 1] && k < MB; ++q) {
         const int32_t c = tcol[q];
@@ -316,11 +318,8 @@ __global__ void k_pack_adjoint(int64_t n, int S, int which, int MB, const int32_
                 if (tcol[r] == gi) qt = r;
             double blk[9];
             if (qt < 0) {
-                for (int e = 0; e < 9; ++e) sval[(p * MB + k) * 9 + e] = 0.0;
-                ++k;
-                continue;
-            }
-            if (which == 0) {  // Uhat_{c,gi} = inv_D_c U_{c,gi}
+                for (int e = 0; e < 9; ++e) blk[e] = 0.0;
+            } else if (which == 0) {  // Uhat_{c,gi} = inv_D_c U_{c,gi}
                 const double *a = invd + (int64_t)c * 9, *b = lu + (int64_t)qt * 9;
                 for (int i = 0; i < 3; ++i)
                     for (int j = 0; j < 3; ++j) {
@@ -331,18 +330,18 @@ __global__ void k_pack_adjoint(int64_t n, int S, int which, int MB, const int32_
             } else {  // L_{c,gi}
                 for (int e = 0; e < 9; ++e) blk[e] = lu[(int64_t)qt * 9 + e];
             }
-            double *o = sval + (p * MB + k) * 9;
             for (int i = 0; i < 3; ++i)
-                for (int j = 0; j < 3; ++j) o[i * 3 + j] = blk[j * 3 + i];
+                for (int j = 0; j < 3; ++j) o[i * NV + k * 3 + j] = blk[j * 3 + i];
             ++k;
         }
     }
     for (; k < MB; ++k)
-        for (int e = 0; e < 9; ++e) sval[(p * MB + k) * 9 + e] = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) o[i * NV + k * 3 + j] = 0.0;
     if (which == 1) {
         const double *a = invd + gi * 9;
         for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) dval[p * 9 + i * 3 + j] = a[j * 3 + i];
+            for (int j = 0; j < 3; ++j) o[i * NV + MB * 3 + j] = a[j * 3 + i];
     }
 }
 
@@ -410,17 +409,13 @@ int lic_setup(dd_ctx *h, hipStream_t st) {
     const int bb = 9;
     for (int w = 0; w < 2; ++w) {
         if (!L.adj_val[w]) {
-            rc = h->alloc(&L.adj_val[w], h->n * h->slots * bb);
+            rc = h->alloc(&L.adj_val[w], h->n * (h->slots + w) * bb);
             if (rc) return rc;
         }
     }
-    if (!L.adj_d) {
-        rc = h->alloc(&L.adj_d, h->n * bb);
-        if (rc) return rc;
-    }
     for (int w = 0; w < 2; ++w)
         k_pack_adjoint<<<g, T, 0, st>>>(h->n, h->S, w, h->slots, h->tptr, h->tcol, h->lu, h->invd,
-                                        h->lev[w].rows, L.adj_val[w], L.adj_d);
+                                        h->lev[w].rows, L.adj_val[w]);
     e = hipStreamSynchronize(st);
     for (void *q : {(void *)cnt, (void *)flag, (void *)bpos}) {
         h->allocs.erase(std::find(h->allocs.begin(), h->allocs.end(), q));

@@ -568,31 +568,41 @@ __global__ void k_pack_slots(int64_t n, int S, int which, int MB, const int32_t 
     const int32_t lr = rows[p];
     const int64_t gi = base + lr;
     const double *inv = invd + gi * BB;
+    // lane-contiguous runs: row i of every slot block, then (upper sweep)
+    // row i of inv_D, NV values per row i, PS = BS * NV per position
+    const int NV = (MB + which) * BS;
+    double *o = sval + p * BS * NV;
     uint64_t dsc = (uint64_t)(uint16_t)lr;
     int k = 0;
     for (int32_t q = tptr[gi]; q < tptr[gi + 1] && k < MB; ++q) {
         const int32_t c = tcol[q];
         if (which == 0 ? (c < gi) : (c > gi)) {
-            const int64_t slot = p * MB + k;
             dsc |= (uint64_t)(uint16_t)(c - base) << (16 * (k + 1));
+            double t[BB];
             if (which == 0) {
 #pragma unroll
-                for (int e = 0; e < BB; ++e) sval[slot * BB + e] = lu[(int64_t)q * BB + e];
+                for (int e = 0; e < BB; ++e) t[e] = lu[(int64_t)q * BB + e];
             } else {
-                double t[BB];
                 blk_mul<BS>(inv, lu + (int64_t)q * BB, t);
-#pragma unroll
-                for (int e = 0; e < BB; ++e) sval[slot * BB + e] = t[e];
             }
+#pragma unroll
+            for (int i = 0; i < BS; ++i)
+#pragma unroll
+                for (int j = 0; j < BS; ++j) o[i * NV + k * BS + j] = t[i * BS + j];
             ++k;
         }
     }
     for (int e = k; e < 3; ++e) dsc |= (uint64_t)0xffffu << (16 * (e + 1));
-    for (; k < MB; ++k) {
-        const int64_t slot = p * MB + k;
+    for (; k < MB; ++k)
 #pragma unroll
-        for (int e = 0; e < BB; ++e) sval[slot * BB + e] = 0.0;
-    }
+        for (int i = 0; i < BS; ++i)
+#pragma unroll
+            for (int j = 0; j < BS; ++j) o[i * NV + k * BS + j] = 0.0;
+    if (which == 1)
+#pragma unroll
+        for (int i = 0; i < BS; ++i)
+#pragma unroll
+            for (int j = 0; j < BS; ++j) o[i * NV + MB * BS + j] = inv[i * BS + j];
     desc[p] = dsc;
 }
 
@@ -639,7 +649,7 @@ hipError_t launch_cast32(dd_ctx *h, hipStream_t st) {
     k_cast32<<<(unsigned)((m + T - 1) / T), T, 0, st>>>(m, h->sw[1].d64, h->sw[1].d32);
     if (h->slots) {
         for (int w = 0; w < 2; ++w) {
-            const int64_t ms = h->n * h->slots * bb;
+            const int64_t ms = h->n * (h->slots + w) * bb;  // the upper stream carries inv_D
             k_cast32<<<(unsigned)((ms + T - 1) / T), T, 0, st>>>(ms, h->sw[w].sval64, h->sw[w].sval32);
         }
     }
