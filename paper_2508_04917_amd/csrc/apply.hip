@@ -112,6 +112,39 @@ __device__ __forceinline__ void lic_correct_lds(TC *__restrict__ y, const double
     __syncthreads();
 }
 
+// The subdomain's slice of r into LDS: each thread issues kLoadU loads
+// before it waits for any (a plain strided loop would wait for every load
+// in turn), positions past the end clamped to a valid one and not stored.
+constexpr int kLoadU = 8;
+
+template <typename TC>
+__device__ __forceinline__ void load_slice(TC *__restrict__ y, const double *__restrict__ rs, int m, int tid,
+                                           int nt) {
+    for (int i0 = tid; i0 < m; i0 += kLoadU * nt) {
+        double v[kLoadU];
+#pragma unroll
+        for (int u = 0; u < kLoadU; ++u) v[u] = rs[min(i0 + u * nt, m - 1)];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < kLoadU; ++u)
+            if (i0 + u * nt < m) y[i0 + u * nt] = static_cast<TC>(v[u]);
+    }
+}
+
+// LDS back to the subdomain's slice of z, kLoadU values per thread at a time.
+template <typename TC>
+__device__ __forceinline__ void store_slice(double *__restrict__ zs, const TC *__restrict__ y, int m, int tid,
+                                            int nt) {
+    for (int i0 = tid; i0 < m; i0 += kLoadU * nt) {
+        TC v[kLoadU];
+#pragma unroll
+        for (int u = 0; u < kLoadU; ++u) v[u] = y[min(i0 + u * nt, m - 1)];
+#pragma unroll
+        for (int u = 0; u < kLoadU; ++u)
+            if (i0 + u * nt < m) zs[i0 + u * nt] = static_cast<double>(v[u]);
+    }
+}
+
 // ------------------------------------------------------------------------
 // Variant 1: plain level loop (levels of any width, rows of any length).
 template <int BS, typename TS, typename TC, int NT, bool LIC>
@@ -137,7 +170,7 @@ __global__ __launch_bounds__(NT) void k_dd_apply(
     const bool lane_ok = rl < RPW;
 
     const double *rs = r + base * BS;
-    for (int i = tid; i < S * BS; i += NT) y[i] = static_cast<TC>(rs[i]);
+    load_slice<TC>(y, rs, S * BS, tid, NT);
     __syncthreads();
     if constexpr (LIC) lic_correct_lds<BS, TC>(y, r, base, s, la, tid, NT);
 
@@ -199,7 +232,7 @@ __global__ __launch_bounds__(NT) void k_dd_apply(
     }
 
     double *zs = z + base * BS;
-    for (int i = tid; i < S * BS; i += NT) zs[i] = static_cast<double>(y[i]);
+    store_slice<TC>(zs, y, S * BS, tid, NT);
 }
 
 // ------------------------------------------------------------------------
@@ -356,12 +389,12 @@ __global__ __launch_bounds__(NT) void k_dd_apply_pipe(
     const int slot = wave * RPW + rl;
 
     const double *rs = r + base * BS;
-    for (int i = tid; i < S * BS; i += NT) y[i] = static_cast<TC>(rs[i]);
+    load_slice<TC>(y, rs, S * BS, tid, NT);
     __syncthreads();
     sweep_csr<BS, TS, TC, MB, false>(y, base, s, Loff, Llp, Lrow, Lbp, Lcol, Lval, nullptr, slot, lane_ok, c);
     sweep_csr<BS, TS, TC, MB, true>(y, base, s, Uoff, Ulp, Urow, Ubp, Ucol, Uval, Dval, slot, lane_ok, c);
     double *zs = z + base * BS;
-    for (int i = tid; i < S * BS; i += NT) zs[i] = static_cast<double>(y[i]);
+    store_slice<TC>(zs, y, S * BS, tid, NT);
 }
 
 // ------------------------------------------------------------------------
@@ -545,14 +578,17 @@ __global__ __launch_bounds__(NT) void k_dd_apply_slots(
     const bool lane_ok = rl < RPW;
     const int slot = wave * RPW + rl;
 
+    // the launch may use fewer threads than NT: just enough wavefronts for
+    // the widest level, so no wavefront is idle at every level
+    const int nt = blockDim.x;
     const double *rs = r + base * BS;
-    for (int i = tid; i < S * BS; i += NT) y[i] = static_cast<TC>(rs[i]);
+    load_slice<TC>(y, rs, S * BS, tid, nt);
     __syncthreads();
-    if constexpr (LIC) lic_correct_lds<BS, TC>(y, r, base, s, la, tid, NT);
+    if constexpr (LIC) lic_correct_lds<BS, TC>(y, r, base, s, la, tid, nt);
     sweep_slots<BS, TS, TC, MB, PD, false>(y, base, S, s, Loff, Llp, Ldesc, Lval, slot, lane_ok, c);
     sweep_slots<BS, TS, TC, MB, PD, true>(y, base, S, s, Uoff, Ulp, Udesc, Uval, slot, lane_ok, c);
     double *zs = z + base * BS;
-    for (int i = tid; i < S * BS; i += NT) zs[i] = static_cast<double>(y[i]);
+    store_slice<TC>(zs, y, S * BS, tid, nt);
 }
 
 // ------------------------------------------------------------------------
@@ -599,7 +635,10 @@ static hipError_t launch_slots(dd_ctx *h, const double *r, double *z, const int3
     hipError_t e = allow_full_lds(kern, done);
     if (e != hipSuccess) return e;
     const int lds = h->S * BS * (int)sizeof(TC);
-    kern<<<h->nsub, NT, lds, st>>>(r, z, h->S, h->lev[0].off, h->lev[0].ptr, h->sw[0].desc, lv, h->lev[1].off,
+    // wavefronts for the widest level (at most NT / 64)
+    constexpr int RPW = kWave / BS;
+    const int nt = std::max(kWave, std::min(NT, (h->max_level_width + RPW - 1) / RPW * kWave));
+    kern<<<h->nsub, nt, lds, st>>>(r, z, h->S, h->lev[0].off, h->lev[0].ptr, h->sw[0].desc, lv, h->lev[1].off,
                                    h->lev[1].ptr, h->sw[1].desc, uv, state, lic_args(h));
     return hipGetLastError();
 }
