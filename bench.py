@@ -302,7 +302,7 @@ def main():
         },
         "roofline": {"bound": "hbm", "achieved": round(gbs64, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs64 / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_dd_apply_slots<3, double, double, 1024, 3, 1, false>",
+                     "traffic": traffic, "kernel": "k_dd_apply_slots<3, double, double, 1024, 3, 2, false>",
                      "bytes_per_launch": bytes64, "copy_GBs": round(copy_gbs, 1),
                      "frac_of_copy": round(gbs64 / copy_gbs, 4)},
         "cpu_baseline": None,

@@ -6,6 +6,12 @@ import glob
 import os
 import subprocess
 import sys
+import tempfile
+
+try:
+    from . import asmcheck
+except ImportError:  # run as a script
+    import asmcheck
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -24,28 +30,48 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
+# Sources whose device assembly is checked after compilation (their kernels
+# schedule loads by hand; see asmcheck.py).
+CHECKED = ("apply.hip",)
+
+
 def build(verbose: bool = False) -> str:
     objs = []
     procs = []
-    for src in sources():
-        obj = os.path.join(CSRC, os.path.basename(src)[:-4] + ".o")
-        cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        procs.append((subprocess.Popen(cmd), src))
-        objs.append(obj)
-    for p, src in procs:
-        if p.wait() != 0:
-            raise RuntimeError(f"hipcc failed on {src}")
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    with tempfile.TemporaryDirectory(prefix="ddilu_build_") as tmp:
+        for src in sources():
+            name = os.path.basename(src)[:-4]
+            obj = os.path.join(CSRC, name + ".o")
+            cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+            if os.path.basename(src) in CHECKED:
+                # keep the device assembly this object is made from
+                obj = os.path.join(tmp, name + ".o")
+                cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj, "-save-temps=obj"]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((subprocess.Popen(cmd, cwd=tmp), src))
+            objs.append(obj)
+        for p, src in procs:
+            if p.wait() != 0:
+                raise RuntimeError(f"hipcc failed on {src}")
+        for name in CHECKED:
+            asm = os.path.join(tmp, f"{name[:-4]}-hip-amdgcn-amd-amdhsa-gfx950.s")
+            n = asmcheck.check_file(asm)
+            if verbose:
+                print(f"{name}: {n} slot kernels pass the in-flight register check", flush=True)
+        _link(objs, verbose)
+    return LIB
+
+
+def _link(objs, verbose):
+    out = LIB + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(out, LIB)
     for o in objs:
         os.remove(o)
-    return LIB
 
 
 if __name__ == "__main__":

@@ -21,13 +21,16 @@
 #include "internal.h"
 
 // Prefetch depth (levels loaded ahead) of the slot-layout kernel, per factor
-// storage type.  Depths 1 to 3 measure the same at 160^3 (the per-level time
-// is not set by load latency), so the default takes the fewest registers.
+// storage type.  Once wavefronts without rows skip their loads, a level's
+// time is mostly the latency of its own loads, which a deeper prefetch
+// hides.  FP64 factors stop at 2: at 3 the four register sets of the upper
+// sweep no longer fit the 128 registers a wavefront of a 1024-lane
+// workgroup may hold.
 #ifndef DDILU_PD64
-#define DDILU_PD64 1
+#define DDILU_PD64 2
 #endif
 #ifndef DDILU_PD32
-#define DDILU_PD32 1
+#define DDILU_PD32 3
 #endif
 
 namespace ddilu {
@@ -401,36 +404,190 @@ __global__ __launch_bounds__(NT) void k_dd_apply_pipe(
 // Variant 3: slot layout.  Position p's blocks sit in fixed slots
 // p*MB..p*MB+MB-1 (zero blocks pad short rows), and its row and columns sit
 // in one 64-bit descriptor.  No load depends on another load, so the loads of
-// level l+PD are issued while level l computes: PD+1 register sets rotate.
-// The main loop is unrolled by PD+1 (each set keeps its registers) and has no
-// early exit, and every lane issues the same loads in the same order (fetches
-// past the last level re-read the last level), so the compiler can count
-// outstanding loads exactly and each level waits only for its own set, not
-// for the whole queue.
-template <int BS, typename TS, int MB>
-struct SlotRegs {
-    bool ok;
-    uint64_t desc;
-    TS v[MB][BS];
-    TS d[BS];
+// level l+PD are issued while level l computes: PD+1 register sets rotate,
+// and the main loop is unrolled by PD+1 so that each set keeps its registers.
+//
+// A wavefront holding no row of a level skips that level's loads (about half
+// of all wavefront-levels at 16x20x20 subdomains, whose levels run from 1 to
+// 256 rows): the loads would only return zeros, and they cost issue slots of
+// the vector memory pipeline the busy wavefronts need.  Because the number
+// of loads a wavefront has in flight then depends on the level, the loads
+// and their waits are written out here (the compiler's own waits, counted
+// over both sides of the skip, would wait for the prefetched level too).
+// The loads of one fetch are buffer loads behind one scalar branch on the
+// wavefront's busy flag.  Before level l computes, the wavefront waits until
+// only the loads of levels l+1..l+PD-1 it actually issued are outstanding,
+// and then passes the registers of level l through an empty asm statement
+// ("claim"), so that no read of them is scheduled before the wait.  The
+// compiler does not know these registers are being loaded: the build checks
+// the generated code, over its control-flow graph, for any instruction that
+// touches a register between the load into it and its claim (a copy or a
+// spill would read it before the data arrives).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// Register image of the NB bytes one lane loads per position: 16-byte pieces,
+// then an 8-byte and a 4-byte piece when NB is not a multiple of 16.
+template <int NB>
+struct RawRun {
+    static constexpr int N16 = NB / 16;
+    static constexpr bool T8 = (NB % 16) >= 8;
+    static constexpr bool T4 = (NB % 8) >= 4;
+    static constexpr int NLOAD = N16 + (T8 ? 1 : 0) + (T4 ? 1 : 0);
+    u32x4 q[N16 > 0 ? N16 : 1];
+    u32x2 h;
+    uint32_t w;
 };
 
+template <int BS, typename TS, int MB, bool UPPER>
+struct SlotRegs {
+    static constexpr int NV = (MB + (UPPER ? 1 : 0)) * BS;  // values per lane and position
+    static constexpr int NB = NV * (int)sizeof(TS);
+    static constexpr int NLOAD = 1 + RawRun<NB>::NLOAD;    // descriptor + values
+    bool ok;
+    u32x2 desc;
+    RawRun<NB> run;
+};
+
+// Buffer resource (base, byte size) in scalar registers.
+__device__ __forceinline__ u32x4 slice_srd(const void *p, int64_t bytes) {
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    u32x4 r;
+    r.x = (uint32_t)a;
+    r.y = (uint32_t)(a >> 32) & 0xffffu;  // stride 0
+    r.z = (uint32_t)bytes;
+    r.w = 0x00020000u;                    // raw 32-bit data, as the buffer builtins use
+    return r;
+}
+
+constexpr uint32_t kOobOffset = 0x80000000u;  // beyond every slice (slices < 2 GiB)
+
+// One buffer load of a piece.  The destination is an in/out operand: on the
+// path where the fetch is skipped it keeps its old (unused) value, so the
+// compiler has no reason to copy it, and it cannot share a register with the
+// offset, which is live across the loads of a fetch.
+template <int OFF>
+__device__ __forceinline__ void vm_load(u32x4 &d, uint32_t voff, const u32x4 &srd) {
+    asm volatile("buffer_load_dwordx4 %[d], %[o], %[s], 0 offen offset:%[k]" : [d] "+v"(d) : [o] "v"(voff), [s] "s"(srd), [k] "n"(OFF));
+}
+template <int OFF>
+__device__ __forceinline__ void vm_load(u32x2 &d, uint32_t voff, const u32x4 &srd) {
+    asm volatile("buffer_load_dwordx2 %[d], %[o], %[s], 0 offen offset:%[k]" : [d] "+v"(d) : [o] "v"(voff), [s] "s"(srd), [k] "n"(OFF));
+}
+template <int OFF>
+__device__ __forceinline__ void vm_load(uint32_t &d, uint32_t voff, const u32x4 &srd) {
+    asm volatile("buffer_load_dword %[d], %[o], %[s], 0 offen offset:%[k]" : [d] "+v"(d) : [o] "v"(voff), [s] "s"(srd), [k] "n"(OFF));
+}
+
+// Wait until no vector memory operation is outstanding.
+__device__ __forceinline__ void vm_wait_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Wait until at most n*K vector memory operations are outstanding (n = 0, 1
+// or 2, wavefront-uniform).
+template <int K>
+__device__ __forceinline__ void vm_wait_n(int n) {
+    static_assert(K >= 0 && 2 * K < 64, "vmcnt has six bits");
+    asm volatile(
+        "s_cmp_eq_u32 %[n], 0\n\t"
+        "s_cbranch_scc1 1f\n\t"
+        "s_cmp_eq_u32 %[n], 1\n\t"
+        "s_cbranch_scc1 2f\n\t"
+        "s_waitcnt vmcnt(%[k2])\n\t"
+        "s_branch 3f\n"
+        "2:\n\t"
+        "s_waitcnt vmcnt(%[k])\n\t"
+        "s_branch 3f\n"
+        "1:\n\t"
+        "s_waitcnt vmcnt(0)\n"
+        "3:"
+        :
+        : [n] "s"(__builtin_amdgcn_readfirstlane(n)), [k] "n"(K), [k2] "n"(2 * K)
+        : "scc", "memory");
+}
+
+template <int I, int N>
+struct LoadPieces {
+    template <int NB>
+    static __device__ __forceinline__ void run(RawRun<NB> &r, uint32_t off, const u32x4 &srd) {
+        vm_load<16 * I>(r.q[I], off, srd);
+        LoadPieces<I + 1, N>::run(r, off, srd);
+    }
+};
+template <int N>
+struct LoadPieces<N, N> {
+    template <int NB>
+    static __device__ __forceinline__ void run(RawRun<NB> &, uint32_t, const u32x4 &) {}
+};
+
+// Per position, the BS lanes of its row each read one contiguous run: lane c
+// holds row c of every slot block (and, in the upper sweep, row c of inv_D).
+// A lane without a row at the level passes an offset past the slice, for
+// which the hardware returns zeros without a memory access (and no lane can
+// address outside its subdomain's slice).
+template <int BS, typename TS, int MB, bool UPPER>
+__device__ __forceinline__ void slot_fetch(SlotRegs<BS, TS, MB, UPPER> &R, const u32x4 &srd_desc,
+                                           const u32x4 &srd_val, int32_t p0, int32_t p1, int slot, bool lane_ok,
+                                           int c, int busy) {
+    using SR = SlotRegs<BS, TS, MB, UPPER>;
+    using RR = RawRun<SR::NB>;
+    const int32_t p = p0 + slot;
+    R.ok = lane_ok && p < p1;
+    const uint32_t pd = R.ok ? (uint32_t)p * 8u : kOobOffset;
+    const uint32_t off = R.ok ? (uint32_t)((p * BS * SR::NV + c * SR::NV) * sizeof(TS)) : kOobOffset;
+    if (busy) {
+        vm_load<0>(R.desc, pd, srd_desc);
+        LoadPieces<0, RR::N16>::run(R.run, off, srd_val);
+        if constexpr (RR::T8) vm_load<16 * RR::N16>(R.run.h, off, srd_val);
+        if constexpr (RR::T4) vm_load<16 * RR::N16 + (RR::T8 ? 8 : 0)>(R.run.w, off, srd_val);
+    }
+}
+
+// Orders every later read of R's registers after the preceding wait.
+template <int BS, typename TS, int MB, bool UPPER>
+__device__ __forceinline__ void slot_claim(SlotRegs<BS, TS, MB, UPPER> &R) {
+    using RR = RawRun<SlotRegs<BS, TS, MB, UPPER>::NB>;
+    asm volatile("; claim %0" : "+v"(R.desc));
+#pragma unroll
+    for (int i = 0; i < RR::N16; ++i) asm volatile("; claim %0" : "+v"(R.run.q[i]));
+    if constexpr (RR::T8) asm volatile("; claim %0" : "+v"(R.run.h));
+    if constexpr (RR::T4) asm volatile("; claim %0" : "+v"(R.run.w));
+}
+
 template <int BS, typename TS, typename TC, int MB, bool UPPER>
-__device__ __forceinline__ void slot_compute(TC *__restrict__ y, const SlotRegs<BS, TS, MB> &R, int c) {
+__device__ __forceinline__ void slot_compute(TC *__restrict__ y, const SlotRegs<BS, TS, MB, UPPER> &R, int c) {
+    using SR = SlotRegs<BS, TS, MB, UPPER>;
+    using RR = RawRun<SR::NB>;
     if (!R.ok) return;
-    const int I = (int)(R.desc & 0xffffu);
+    uint32_t wd[SR::NB / 4];
+#pragma unroll
+    for (int i = 0; i < RR::N16; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) wd[4 * i + j] = R.run.q[i][j];
+    if constexpr (RR::T8) {
+        wd[4 * RR::N16] = R.run.h[0];
+        wd[4 * RR::N16 + 1] = R.run.h[1];
+    }
+    if constexpr (RR::T4) wd[SR::NB / 4 - 1] = R.run.w;
+    TS vals[SR::NV];
+#pragma unroll
+    for (int v = 0; v < SR::NV; ++v) {
+        if constexpr (sizeof(TS) == 8)
+            vals[v] = __builtin_bit_cast(TS, (uint64_t)wd[2 * v] | ((uint64_t)wd[2 * v + 1] << 32));
+        else
+            vals[v] = __builtin_bit_cast(TS, wd[v]);
+    }
+    const uint64_t desc = (uint64_t)R.desc[0] | ((uint64_t)R.desc[1] << 32);
+    const int I = (int)(desc & 0xffffu);
     // gather every LDS operand first (one round of LDS latency), then the
     // fixed-order arithmetic.  An empty slot holds a zero block: it is
-    // applied to y_I (a valid LDS address) instead of being branched around,
-    // so every loaded value has an unconditional use and the factor loads
-    // stay where they were issued.
+    // applied to y_I (a valid LDS address) instead of being branched around.
     constexpr int NI = UPPER ? BS : 1;
     TC yi[NI], yj[MB][BS];
 #pragma unroll
     for (int d = 0; d < NI; ++d) yi[d] = y[I * BS + (UPPER ? d : c)];
 #pragma unroll
     for (int k = 0; k < MB; ++k) {
-        const int J = (int)((R.desc >> (16 * (k + 1))) & 0xffffu);
+        const int J = (int)((desc >> (16 * (k + 1))) & 0xffffu);
         const int Jc = J != 0xffff ? J : I;
 #pragma unroll
         for (int d = 0; d < BS; ++d) yj[k][d] = y[Jc * BS + d];
@@ -440,112 +597,60 @@ __device__ __forceinline__ void slot_compute(TC *__restrict__ y, const SlotRegs<
     if constexpr (UPPER) {
         acc = 0;
 #pragma unroll
-        for (int d = 0; d < BS; ++d) acc += static_cast<TC>(R.d[d]) * yi[d];
+        for (int d = 0; d < BS; ++d) acc += static_cast<TC>(vals[MB * BS + d]) * yi[d];
     } else {
         acc = yi[0];
     }
 #pragma unroll
     for (int k = 0; k < MB; ++k)
 #pragma unroll
-        for (int d = 0; d < BS; ++d) acc -= static_cast<TC>(R.v[k][d]) * yj[k][d];
+        for (int d = 0; d < BS; ++d) acc -= static_cast<TC>(vals[k * BS + d]) * yj[k][d];
     // all lanes of this row read y_I above (same wavefront)
     __asm__ volatile("" ::: "memory");
     y[I * BS + c] = acc;
-}
-
-// Loads go through buffer resources over the workgroup's slice of the
-// descriptor, block and inv_D streams: a lane without a row at a level passes
-// an offset past the slice, for which the hardware returns zeros without a
-// memory access (and no lane can address outside its subdomain's slice).
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t slice_rsrc(const void *p, int64_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
-}
-
-constexpr uint32_t kOobOffset = 0x80000000u;  // beyond every slice (slices < 2 GiB)
-
-// N consecutive values starting at byte offset off, in the widest loads
-// that fit (16, then 8, then 4 bytes).
-template <typename TS, int N>
-__device__ __forceinline__ void buf_load_run(__amdgpu_buffer_rsrc_t rs, uint32_t off, TS (&v)[N]) {
-    constexpr int PER16 = 16 / (int)sizeof(TS);
-    int i = 0;
-#pragma unroll
-    for (; i + PER16 <= N; i += PER16) {
-        struct Q { TS x[PER16]; };
-        const Q q = __builtin_bit_cast(Q, __builtin_amdgcn_raw_buffer_load_b128(rs, off + i * (uint32_t)sizeof(TS), 0, 0));
-#pragma unroll
-        for (int j = 0; j < PER16; ++j) v[i + j] = q.x[j];
-    }
-    if constexpr (sizeof(TS) == 4) {
-        if (i + 2 <= N) {
-            struct F2 { float x, y; };
-            const F2 q = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(rs, off + i * 4u, 0, 0));
-            v[i] = q.x;
-            v[i + 1] = q.y;
-            i += 2;
-        }
-        if (i < N) v[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + i * 4u, 0, 0));
-    } else {
-        if (i < N) v[i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off + i * 8u, 0, 0));
-    }
-}
-
-struct SlotRsrc {
-    __amdgpu_buffer_rsrc_t desc, val;
-};
-
-// Per position, the BS lanes of its row each read one contiguous run: lane c
-// holds row c of every slot block (and, in the upper sweep, row c of inv_D),
-// NV = (MB [+1]) * BS values, so a lane issues ceil(NV * sizeof(TS) / 16)
-// loads rather than two per block.
-template <int BS, typename TS, int MB, bool UPPER>
-__device__ __forceinline__ void slot_fetch(SlotRegs<BS, TS, MB> &R, const SlotRsrc &rs, int32_t p0, int32_t p1,
-                                           int slot, bool lane_ok, int c) {
-    constexpr int NV = (MB + (UPPER ? 1 : 0)) * BS;
-    const int32_t p = p0 + slot;
-    R.ok = lane_ok && p < p1;
-    const uint32_t pd = R.ok ? (uint32_t)p * 8u : kOobOffset;
-    R.desc = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(rs.desc, pd, 0, 0));
-    TS vals[NV];
-    const uint32_t off = R.ok ? (uint32_t)((p * BS * NV + c * NV) * sizeof(TS)) : kOobOffset;
-    buf_load_run<TS, NV>(rs.val, off, vals);
-#pragma unroll
-    for (int k = 0; k < MB; ++k)
-#pragma unroll
-        for (int d = 0; d < BS; ++d) R.v[k][d] = vals[k * BS + d];
-    if constexpr (UPPER)
-#pragma unroll
-        for (int d = 0; d < BS; ++d) R.d[d] = vals[MB * BS + d];
 }
 
 template <int BS, typename TS, typename TC, int MB, int PD, bool UPPER>
 __device__ __forceinline__ void sweep_slots(TC *__restrict__ y, int64_t base, int S, int s,
                                             const int32_t *__restrict__ off, const int32_t *__restrict__ lp,
                                             const uint64_t *__restrict__ desc, const TS *__restrict__ sval,
-                                            int slot, bool lane_ok, int c) {
-    constexpr int PS = (MB + (UPPER ? 1 : 0)) * BS * BS;  // values per position
-    SlotRsrc rs;
-    rs.desc = slice_rsrc(desc + base, (int64_t)S * 8);
-    rs.val = slice_rsrc(sval + base * PS, (int64_t)S * PS * sizeof(TS));
+                                            int slot, int wrow0, bool lane_ok, int c) {
+    static_assert(PD >= 1 && PD <= 3, "prefetch depth 1 to 3");
+    using SR = SlotRegs<BS, TS, MB, UPPER>;
+    constexpr int PS = SR::NV * BS;  // values per position
+    const u32x4 srd_desc = slice_srd(desc + base, (int64_t)S * 8);
+    const u32x4 srd_val = slice_srd(sval + base * PS, (int64_t)S * PS * sizeof(TS));
     const int32_t o = off[s];
     const int nl = off[s + 1] - o - 1;
-    SlotRegs<BS, TS, MB> R[PD + 1];
+    SR R[PD + 1];
+    int busy[PD + 1];
     // level bounds are read one fetch ahead, so their scalar loads complete
     // during a level's update instead of after the barrier that follows it
     int32_t q0 = lp[o], q1 = lp[o + 1];
-    auto fetch = [&](SlotRegs<BS, TS, MB> &Rk, int l) {
-        slot_fetch<BS, TS, MB, UPPER>(Rk, rs, q0, q1, slot, lane_ok, c);
+    auto fetch = [&](int k, int l) {
+        busy[k] = q0 + wrow0 < q1 ? 1 : 0;
+        slot_fetch<BS, TS, MB, UPPER>(R[k], srd_desc, srd_val, q0, q1, slot, lane_ok, c, busy[k]);
         const int ln = l + 1 < nl ? l + 1 : nl - 1;
         q0 = lp[o + ln];
         q1 = lp[o + ln + 1];
     };
 #pragma unroll
-    for (int u = 0; u < PD; ++u) fetch(R[u], u);
+    for (int u = 0; u < PD; ++u) fetch(u, u);
     const int nfull = nl - nl % (PD + 1);
     for (int l0 = 0; l0 < nfull; l0 += PD + 1) {
 #pragma unroll
         for (int u = 0; u <= PD; ++u) {
-            fetch(R[(u + PD) % (PD + 1)], l0 + u + PD);
+            // set u holds level l = l0+u; the loads issued after its own are
+            // those of levels l+1..l+PD-1 (sets u+1..u+PD-1), by the
+            // wavefronts that had rows there
+            if constexpr (PD == 3)
+                vm_wait_n<SR::NLOAD>(busy[(u + 1) % (PD + 1)] + busy[(u + 2) % (PD + 1)]);
+            else if constexpr (PD == 2)
+                vm_wait_n<SR::NLOAD>(busy[(u + 1) % (PD + 1)]);
+            else
+                vm_wait_all();
+            slot_claim(R[u]);
+            fetch((u + PD) % (PD + 1), l0 + u + PD);
             slot_compute<BS, TS, TC, MB, UPPER>(y, R[u], c);
             __syncthreads();
         }
@@ -554,10 +659,16 @@ __device__ __forceinline__ void sweep_slots(TC *__restrict__ y, int64_t base, in
 #pragma unroll
     for (int u = 0; u < PD; ++u) {
         if (u < rem) {
+            vm_wait_all();
+            slot_claim(R[u]);
             slot_compute<BS, TS, TC, MB, UPPER>(y, R[u], c);
             __syncthreads();
         }
     }
+    // nothing may still be loading into these registers once they are free
+    vm_wait_all();
+#pragma unroll
+    for (int u = 0; u <= PD; ++u) slot_claim(R[u]);
 }
 
 template <int BS, typename TS, typename TC, int NT, int MB, int PD, bool LIC>
@@ -585,8 +696,9 @@ __global__ __launch_bounds__(NT) void k_dd_apply_slots(
     load_slice<TC>(y, rs, S * BS, tid, nt);
     __syncthreads();
     if constexpr (LIC) lic_correct_lds<BS, TC>(y, r, base, s, la, tid, nt);
-    sweep_slots<BS, TS, TC, MB, PD, false>(y, base, S, s, Loff, Llp, Ldesc, Lval, slot, lane_ok, c);
-    sweep_slots<BS, TS, TC, MB, PD, true>(y, base, S, s, Uoff, Ulp, Udesc, Uval, slot, lane_ok, c);
+    const int wrow0 = __builtin_amdgcn_readfirstlane(wave) * RPW;  // first slot of this wavefront
+    sweep_slots<BS, TS, TC, MB, PD, false>(y, base, S, s, Loff, Llp, Ldesc, Lval, slot, wrow0, lane_ok, c);
+    sweep_slots<BS, TS, TC, MB, PD, true>(y, base, S, s, Uoff, Ulp, Udesc, Uval, slot, wrow0, lane_ok, c);
     double *zs = z + base * BS;
     store_slice<TC>(zs, y, S * BS, tid, nt);
 }
