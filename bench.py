@@ -101,6 +101,55 @@ def kernels_only(args, p, sub, ptr_d, col_d, val_d, dd, torch):
     print(json.dumps(out), flush=True)
 
 
+ABLATIONS = {
+    1: "plain level loop (reference for 4-8)",
+    4: "split: lower + diagonal scaling, then upper, two kernels",
+    5: "vector in global memory instead of LDS",
+    6: "vertex-centric: one thread per block row",
+    7: "ILU0 form: unscaled U, row sums scaled by inv(U_II)",
+    8: "synchronisation-free sweeps, per-row flags in LDS (Algorithm 4)",
+    3: "production: slot layout, hand-scheduled prefetch",
+}
+
+
+def ablation(args, p, sub, ptr_d, col_d, val_d, dd, torch):
+    """FP64 apply kernel variants on the same factors: bursts of applies per
+    variant, timed with events, outputs compared with the production
+    kernel's.  Bytes are the method's algorithmic bytes per apply for all
+    variants (the same factors and vectors are needed by each)."""
+    h = dd.dd_partition(p.nx, p.ny, p.nz, p.bs, ptr_d, col_d, val_d, sub=sub)
+    dd.ilu0_factor(h, dd.DD_FP64)
+    nbytes = dd.dd_get_info(h)["apply_bytes"]
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(11)
+    r = torch.randn(p.n * p.bs, dtype=torch.float64, device="cuda:0", generator=g)
+    z = torch.empty_like(r)
+    ref = torch.empty_like(r)
+    dd.dd_set_apply_variant(h, 3)
+    dd.dd_trsv_apply(h, r, ref)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    inf = dd.dd_get_info(h)
+    out = {"workload": args.workload, "subdomain": [inf["sx"], inf["sy"], inf["sz"]], "n_subdomains": inf["nsub"],
+           "bytes_per_apply": nbytes, "applies": args.applies, "variants": {}}
+    for v, what in ABLATIONS.items():
+        log(f"variant {v}: {what}")
+        dd.dd_set_apply_variant(h, v)
+        dd.dd_trsv_apply(h, r, z)
+        ev[0].record()
+        for _ in range(args.applies):
+            dd.dd_trsv_apply(h, r, z)
+        ev[1].record()
+        torch.cuda.synchronize()
+        us = 1e3 * ev[0].elapsed_time(ev[1]) / args.applies
+        diff = float(torch.linalg.vector_norm(z - ref) / torch.linalg.vector_norm(ref))
+        out["variants"][str(v)] = {"what": what, "us_per_apply": round(us, 2),
+                                   "GB/s": round(nbytes / us / 1e3, 1), "rel_diff_vs_variant3": diff}
+        log(f"  {us:.1f} us per apply, {nbytes / us / 1e3:.1f} GB/s, rel diff {diff:.1e}")
+    dd.dd_set_apply_variant(h, 0)
+    h.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,9 +161,10 @@ def main():
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--cpu-applies", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="full", choices=["full", "kernels"],
+    ap.add_argument("--mode", default="full", choices=["full", "kernels", "ablation"],
                     help="kernels: only a copy kernel of known size and bursts of applies "
-                         "(the short program the rocprofv3 counter runs profile)")
+                         "(the short program the rocprofv3 counter runs profile); "
+                         "ablation: the FP64 apply kernel variants, timed on the same factors")
     ap.add_argument("--applies", type=int, default=10)
     args = ap.parse_args()
 
@@ -149,6 +199,9 @@ def main():
 
     if args.mode == "kernels":
         kernels_only(args, p, sub, ptr_d, col_d, val_d, dd, torch)
+        return
+    if args.mode == "ablation":
+        ablation(args, p, sub, ptr_d, col_d, val_d, dd, torch)
         return
 
     def step():

@@ -210,15 +210,26 @@ int dd_spmv(dd_handle h, const double *x, double *y, void *hip_stream);
 int bicgstab_solve(dd_handle h, const double *b, double *x, double rtol,
                    int32_t maxit, void *hip_stream, dd_solve_info *info);
 
-/* Choose the kernel dd_trsv_apply uses (all compute the same z; they differ
- * in how factor data is fetched): 0 = automatic (the fastest one the
- * handle's shape allows), 1 = plain level loop (levels of any width),
- * 2 = level loop with the next level's blocks prefetched into registers
- * (levels no wider than one workgroup pass), 3 = fixed per-row block
- * slots so that no load depends on another and a level's loads are issued
- * while the previous level computes (rows of at most 3 off-diagonal blocks
- * per sweep, levels no wider than one pass).  A variant the shape does not
- * allow falls back to 1.  Returns DD_EINVAL for other values. */
+/* Choose the kernel dd_trsv_apply (and bicgstab_solve) uses; all compute the
+ * same z up to rounding order.  0 = automatic (the fastest one the handle's
+ * shape allows), 1 = plain level loop (levels of any width), 2 = level loop
+ * with the next level's blocks prefetched into registers (levels no wider
+ * than one workgroup pass), 3 = fixed per-row block slots so that no load
+ * depends on another and later levels' loads are issued while a level
+ * computes (rows of at most 3 off-diagonal blocks per sweep, levels no wider
+ * than one pass).  A variant the shape does not allow falls back to 1.
+ *
+ * 4-8 are ablations of the plain level loop (1), each changing one thing,
+ * after the kernel variants of Section 5.2 (Tables 3-4): 4 = lower sweep
+ * with the diagonal scaling and upper sweep as two kernels (split ILD_U0
+ * against fused ILDU0), 5 = the subdomain's vector in global memory instead
+ * of LDS, 6 = vertex-centric (one thread per block row), 7 = ILU0 form of
+ * the upper sweep (unscaled U, each row's sum multiplied by inv(U_II)),
+ * 8 = synchronisation-free sweeps with per-row flags in LDS (Algorithm 4).
+ * They run with DD_FP64 and without the learned correction only: the apply
+ * and the solve return DD_EINVAL otherwise (also for 8 when the vector and
+ * one flag byte per row exceed 160 KB of LDS).  Returns DD_EINVAL for
+ * values outside 0..8. */
 int dd_set_apply_variant(dd_handle h, int32_t variant);
 
 /* Switch per-apply timing inside bicgstab_solve on (1) or off (0): a HIP

@@ -308,6 +308,7 @@ static int build_sweep(dd_ctx *h, int which, hipStream_t st, int32_t *cnt) {
     HCHK(hipMemcpyAsync(&maxrow, h->status + 4, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HCHK(hipStreamSynchronize(st));
     if (w.bcol) { release(h, w.bcol); release(h, w.val64); w.bcol = nullptr; w.val64 = nullptr; }
+    if (w.uraw) { release(h, w.uraw); w.uraw = nullptr; }
     if (w.val32) { release(h, w.val32); w.val32 = nullptr; }
     w.nblk = total;
     w.max_row = maxrow;
@@ -446,10 +447,24 @@ extern "C" int dd_get_factors(dd_handle h, int32_t *ptr, int32_t *col, double *f
 }
 
 // ------------------------------------------------------------------ apply
+// Checks the apply variant against the handle's state and builds what an
+// ablation variant needs beyond the production streams (the unscaled U
+// blocks of variant 7, once per factorisation).
+static int prepare_variant(dd_ctx *h, const char *who, hipStream_t st) {
+    if (const char *why = variant_unsupported(h, h->variant)) return h->fail(DD_EINVAL, "%s: %s", who, why);
+    Sweep &U = h->sw[1];
+    if (h->variant == 7 && !U.uraw) {
+        RCHK(h->alloc(&U.uraw, U.nblk * h->bs * h->bs));
+        HCHK(launch_pack_unscaled(h, st));
+    }
+    return DD_OK;
+}
+
 extern "C" int dd_trsv_apply(dd_handle h, const double *r, double *z, void *hip_stream) {
     if (!h) return set_global_error(DD_EINVAL, "dd_trsv_apply: null handle");
     if (!h->factored) return h->fail(DD_ESTATE, "dd_trsv_apply before ilu0_factor");
     if (!r || !z || r == z) return h->fail(DD_EINVAL, "dd_trsv_apply: r and z must be distinct device buffers");
+    RCHK(prepare_variant(h, "dd_trsv_apply", as_stream(hip_stream)));
     HCHK(launch_apply(h, r, z, nullptr, as_stream(hip_stream)));
     return DD_OK;
 }
@@ -467,12 +482,13 @@ extern "C" int bicgstab_solve(dd_handle h, const double *b, double *x, double rt
     if (!h->factored) return h->fail(DD_ESTATE, "bicgstab_solve before ilu0_factor");
     if (!b || !x || b == x) return h->fail(DD_EINVAL, "bicgstab_solve: b and x must be distinct device buffers");
     if (!(rtol > 0.0) || maxit < 0) return h->fail(DD_EINVAL, "bicgstab_solve: bad rtol or maxit");
+    if (h->pc_kind == 0) RCHK(prepare_variant(h, "bicgstab_solve", as_stream(hip_stream)));
     return bicgstab_run(h, b, x, rtol, maxit, as_stream(hip_stream), info);
 }
 
 extern "C" int dd_set_apply_variant(dd_handle h, int32_t variant) {
     if (!h) return set_global_error(DD_EINVAL, "dd_set_apply_variant: null handle");
-    if (variant < 0 || variant > 3) return h->fail(DD_EINVAL, "dd_set_apply_variant: variant must be 0..3");
+    if (variant < 0 || variant > 8) return h->fail(DD_EINVAL, "dd_set_apply_variant: variant must be 0..8");
     h->variant = variant;
     return DD_OK;
 }

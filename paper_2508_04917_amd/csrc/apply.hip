@@ -150,46 +150,58 @@ __device__ __forceinline__ void store_slice(double *__restrict__ zs, const TC *_
 
 // ------------------------------------------------------------------------
 // Variant 1: plain level loop (levels of any width, rows of any length).
-template <int BS, typename TS, typename TC, int NT, bool LIC>
-__global__ __launch_bounds__(NT) void k_dd_apply(
-    const double *__restrict__ r, double *__restrict__ z, int S,
-    const int32_t *__restrict__ Loff, const int32_t *__restrict__ Llp, const uint16_t *__restrict__ Lrow,
-    const int32_t *__restrict__ Lbp, const uint16_t *__restrict__ Lcol, const TS *__restrict__ Lval,
-    const int32_t *__restrict__ Uoff, const int32_t *__restrict__ Ulp, const uint16_t *__restrict__ Urow,
-    const int32_t *__restrict__ Ubp, const uint16_t *__restrict__ Ucol, const TS *__restrict__ Uval,
-    const TS *__restrict__ Dval, const int32_t *__restrict__ state, LicArgs la) {
-    if (state != nullptr && *state != 0) return;  // enclosing solve already finished
+// The sweeps are shared with the ablation variants below.  VC selects the
+// vertex-centric mapping (one thread per block row, all BS components)
+// instead of BS lanes per row.
+template <int NT, bool VC, int BS>
+struct RowMap {
+    static constexpr int RPW = kWave / BS;                     // block rows per wavefront (lane mapping)
+    static constexpr int RPP = VC ? NT : RPW * (NT / kWave);  // block rows per pass of the workgroup
+    int slot, c;
+    bool ok;
+    __device__ __forceinline__ RowMap() {
+        const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+        slot = VC ? tid : wave * RPW + lane / BS;
+        c = VC ? 0 : lane % BS;
+        ok = VC || lane / BS < RPW;
+    }
+};
+
+// y_I = y_I - sum_{J<I} L_IJ y_J, level by level.
+template <int BS, typename TS, typename TC, int NT, bool VC>
+__device__ __forceinline__ void plain_lower(TC *__restrict__ y, int64_t base, int s, const int32_t *__restrict__ Loff,
+                                            const int32_t *__restrict__ Llp, const uint16_t *__restrict__ Lrow,
+                                            const int32_t *__restrict__ Lbp, const uint16_t *__restrict__ Lcol,
+                                            const TS *__restrict__ Lval) {
     constexpr int BB = BS * BS;
-    constexpr int RPW = kWave / BS;          // block rows per wavefront
-    constexpr int RPP = RPW * (NT / kWave);  // block rows per pass of the workgroup
-    extern __shared__ unsigned char dd_smem[];
-    TC *y = reinterpret_cast<TC *>(dd_smem);
-
-    const int s = blockIdx.x;
-    const int64_t base = (int64_t)s * S;
-    const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1), wave = tid / kWave;
-    const int c = lane % BS, rl = lane / BS;
-    const bool lane_ok = rl < RPW;
-
-    const double *rs = r + base * BS;
-    load_slice<TC>(y, rs, S * BS, tid, NT);
-    __syncthreads();
-    if constexpr (LIC) lic_correct_lds<BS, TC>(y, r, base, s, la, tid, NT);
-
-    // lower sweep: y_I = r_I - sum_{J<I} L_IJ y_J
-    {
-        const int32_t o = Loff[s];
-        const int nl = Loff[s + 1] - o - 1;
-        for (int l = 0; l < nl; ++l) {
-            const int32_t p0 = Llp[o + l], p1 = Llp[o + l + 1];
-            for (int32_t pb = p0; pb < p1; pb += RPP) {
-                const int32_t p = pb + wave * RPW + rl;
-                if (lane_ok && p < p1) {
-                    const int64_t gp = base + p;
-                    const int I = Lrow[gp];
+    const RowMap<NT, VC, BS> m;
+    const int32_t o = Loff[s];
+    const int nl = Loff[s + 1] - o - 1;
+    for (int l = 0; l < nl; ++l) {
+        const int32_t p0 = Llp[o + l], p1 = Llp[o + l + 1];
+        for (int32_t pb = p0; pb < p1; pb += m.RPP) {
+            const int32_t p = pb + m.slot;
+            if (m.ok && p < p1) {
+                const int64_t gp = base + p;
+                const int I = Lrow[gp];
+                const int32_t b1 = Lbp[gp + 1];
+                if constexpr (VC) {
+                    TC acc[BS];
+#pragma unroll
+                    for (int c = 0; c < BS; ++c) acc[c] = y[I * BS + c];
+                    for (int32_t b = Lbp[gp]; b < b1; ++b) {
+                        const int J = Lcol[b];
+                        const TS *blk = Lval + (int64_t)b * BB;
+#pragma unroll
+                        for (int c = 0; c < BS; ++c)
+#pragma unroll
+                            for (int d = 0; d < BS; ++d) acc[c] -= static_cast<TC>(blk[c * BS + d]) * y[J * BS + d];
+                    }
+#pragma unroll
+                    for (int c = 0; c < BS; ++c) y[I * BS + c] = acc[c];
+                } else {
+                    const int c = m.c;
                     TC acc = y[I * BS + c];
-                    const int32_t b1 = Lbp[gp + 1];
                     for (int32_t b = Lbp[gp]; b < b1; ++b) {
                         const int J = Lcol[b];
                         const TS *blk = Lval + (int64_t)b * BB + c * BS;
@@ -199,26 +211,65 @@ __global__ __launch_bounds__(NT) void k_dd_apply(
                     y[I * BS + c] = acc;
                 }
             }
-            __syncthreads();
         }
+        __syncthreads();
     }
+}
 
-    // upper sweep with the scaling fused: z_I = inv_D_I y_I - sum_{K>I} Uhat_IK z_K
-    {
-        const int32_t o = Uoff[s];
-        const int nl = Uoff[s + 1] - o - 1;
-        for (int l = 0; l < nl; ++l) {
-            const int32_t p0 = Ulp[o + l], p1 = Ulp[o + l + 1];
-            for (int32_t pb = p0; pb < p1; pb += RPP) {
-                const int32_t p = pb + wave * RPW + rl;
-                if (lane_ok && p < p1) {
-                    const int64_t gp = base + p;
-                    const int I = Urow[gp];
-                    const TS *dblk = Dval + gp * BB + c * BS;
-                    TC acc = 0;
+// Upper sweep, level by level.  SCALE: z_I = inv_D_I y_I - sum_{K>I} Uhat_IK z_K
+// (the diagonal scaling fused in); otherwise z_I = y_I - sum Uhat_IK z_K
+// (unit diagonal, the scaling already applied).
+template <int BS, typename TS, typename TC, int NT, bool VC, bool SCALE>
+__device__ __forceinline__ void plain_upper(TC *__restrict__ y, int64_t base, int s, const int32_t *__restrict__ Uoff,
+                                            const int32_t *__restrict__ Ulp, const uint16_t *__restrict__ Urow,
+                                            const int32_t *__restrict__ Ubp, const uint16_t *__restrict__ Ucol,
+                                            const TS *__restrict__ Uval, const TS *__restrict__ Dval) {
+    constexpr int BB = BS * BS;
+    const RowMap<NT, VC, BS> m;
+    const int32_t o = Uoff[s];
+    const int nl = Uoff[s + 1] - o - 1;
+    for (int l = 0; l < nl; ++l) {
+        const int32_t p0 = Ulp[o + l], p1 = Ulp[o + l + 1];
+        for (int32_t pb = p0; pb < p1; pb += m.RPP) {
+            const int32_t p = pb + m.slot;
+            if (m.ok && p < p1) {
+                const int64_t gp = base + p;
+                const int I = Urow[gp];
+                const int32_t b1 = Ubp[gp + 1];
+                if constexpr (VC) {
+                    TC acc[BS];
 #pragma unroll
-                    for (int d = 0; d < BS; ++d) acc += static_cast<TC>(dblk[d]) * y[I * BS + d];
-                    const int32_t b1 = Ubp[gp + 1];
+                    for (int c = 0; c < BS; ++c) {
+                        if constexpr (SCALE) {
+                            acc[c] = 0;
+#pragma unroll
+                            for (int d = 0; d < BS; ++d)
+                                acc[c] += static_cast<TC>(Dval[gp * BB + c * BS + d]) * y[I * BS + d];
+                        } else {
+                            acc[c] = y[I * BS + c];
+                        }
+                    }
+                    for (int32_t b = Ubp[gp]; b < b1; ++b) {
+                        const int K = Ucol[b];
+                        const TS *blk = Uval + (int64_t)b * BB;
+#pragma unroll
+                        for (int c = 0; c < BS; ++c)
+#pragma unroll
+                            for (int d = 0; d < BS; ++d) acc[c] -= static_cast<TC>(blk[c * BS + d]) * y[K * BS + d];
+                    }
+#pragma unroll
+                    for (int c = 0; c < BS; ++c) y[I * BS + c] = acc[c];
+                } else {
+                    const int c = m.c;
+                    TC acc;
+                    if constexpr (SCALE) {
+                        const TS *dblk = Dval + gp * BB + c * BS;
+                        acc = 0;
+#pragma unroll
+                        for (int d = 0; d < BS; ++d) acc += static_cast<TC>(dblk[d]) * y[I * BS + d];
+                    } else {
+                        acc = y[I * BS + c];
+                    }
                     for (int32_t b = Ubp[gp]; b < b1; ++b) {
                         const int K = Ucol[b];
                         const TS *blk = Uval + (int64_t)b * BB + c * BS;
@@ -230,12 +281,31 @@ __global__ __launch_bounds__(NT) void k_dd_apply(
                     y[I * BS + c] = acc;
                 }
             }
-            __syncthreads();
         }
+        __syncthreads();
     }
+}
 
-    double *zs = z + base * BS;
-    store_slice<TC>(zs, y, S * BS, tid, NT);
+template <int BS, typename TS, typename TC, int NT, bool LIC>
+__global__ __launch_bounds__(NT) void k_dd_apply(
+    const double *__restrict__ r, double *__restrict__ z, int S,
+    const int32_t *__restrict__ Loff, const int32_t *__restrict__ Llp, const uint16_t *__restrict__ Lrow,
+    const int32_t *__restrict__ Lbp, const uint16_t *__restrict__ Lcol, const TS *__restrict__ Lval,
+    const int32_t *__restrict__ Uoff, const int32_t *__restrict__ Ulp, const uint16_t *__restrict__ Urow,
+    const int32_t *__restrict__ Ubp, const uint16_t *__restrict__ Ucol, const TS *__restrict__ Uval,
+    const TS *__restrict__ Dval, const int32_t *__restrict__ state, LicArgs la) {
+    if (state != nullptr && *state != 0) return;  // enclosing solve already finished
+    extern __shared__ unsigned char dd_smem[];
+    TC *y = reinterpret_cast<TC *>(dd_smem);
+    const int s = blockIdx.x;
+    const int64_t base = (int64_t)s * S;
+    const int tid = threadIdx.x;
+    load_slice<TC>(y, r + base * BS, S * BS, tid, NT);
+    __syncthreads();
+    if constexpr (LIC) lic_correct_lds<BS, TC>(y, r, base, s, la, tid, NT);
+    plain_lower<BS, TS, TC, NT, false>(y, base, s, Loff, Llp, Lrow, Lbp, Lcol, Lval);
+    plain_upper<BS, TS, TC, NT, false, true>(y, base, s, Uoff, Ulp, Urow, Ubp, Ucol, Uval, Dval);
+    store_slice<TC>(z + base * BS, y, S * BS, tid, NT);
 }
 
 // ------------------------------------------------------------------------
@@ -704,6 +774,278 @@ __global__ __launch_bounds__(NT) void k_dd_apply_slots(
 }
 
 // ------------------------------------------------------------------------
+// Ablation variants (FP64 factors and arithmetic, no learned correction).
+// Each differs from the plain level loop (variant 1) in one respect, so that
+// timing it against variant 1 isolates what that respect is worth on this
+// GPU; together they recast the paper's kernel variants (Section 5.2 and
+// Tables 3-4) for the lane-parallel mapping used here:
+//   4  split: lower sweep + diagonal scaling, then the upper sweep with unit
+//      diagonal, as two kernels with the intermediate vector in global memory
+//      (the paper's ILD_U0 split against fused ILDU0);
+//   5  no LDS: the subdomain's vector lives in z (global memory) throughout
+//      (the paper's no_lds variant);
+//   6  vertex-centric: one thread per block row computes all its components
+//      (the paper's vertex-centric kernel) instead of BS lanes per row;
+//   7  ILU0 form of the upper sweep: the U blocks as factored (same layout
+//      and order as Uhat), and the row's sum is multiplied by inv(U_II) at
+//      the end (the BS lanes of the row exchange their sums), instead of the
+//      pre-scaled Uhat = inv(U_II) U of ILDU0 (the paper's ILU0 against
+//      unit-diagonal ILDU0 comparison);
+//   8  synchronisation-free sweeps (Algorithm 4): no level barriers, one
+//      wavefront per row, each waiting on per-row completion flags in LDS.
+
+// 4a: y = L^{-1} r, then w_I = inv_D_I y_I for every row, stored to z.
+template <int BS, int NT>
+__global__ __launch_bounds__(NT) void k_abl_lower_scale(
+    const double *__restrict__ r, double *__restrict__ z, int S, const int32_t *__restrict__ Loff,
+    const int32_t *__restrict__ Llp, const uint16_t *__restrict__ Lrow, const int32_t *__restrict__ Lbp,
+    const uint16_t *__restrict__ Lcol, const double *__restrict__ Lval, const uint16_t *__restrict__ Urow,
+    const double *__restrict__ Dval, const int32_t *__restrict__ state) {
+    if (state != nullptr && *state != 0) return;
+    constexpr int BB = BS * BS;
+    extern __shared__ unsigned char dd_smem[];
+    double *y = reinterpret_cast<double *>(dd_smem);
+    const int s = blockIdx.x;
+    const int64_t base = (int64_t)s * S;
+    const int tid = threadIdx.x;
+    load_slice<double>(y, r + base * BS, S * BS, tid, NT);
+    __syncthreads();
+    plain_lower<BS, double, double, NT, false>(y, base, s, Loff, Llp, Lrow, Lbp, Lcol, Lval);
+    const RowMap<NT, false, BS> m;
+    for (int32_t pb = 0; pb < S; pb += m.RPP) {  // rows are independent here
+        const int32_t p = pb + m.slot;
+        if (m.ok && p < S) {
+            const int64_t gp = base + p;
+            const int I = Urow[gp];
+            const double *dblk = Dval + gp * BB + m.c * BS;
+            double acc = 0;
+#pragma unroll
+            for (int d = 0; d < BS; ++d) acc += dblk[d] * y[I * BS + d];
+            __asm__ volatile("" ::: "memory");  // the row's lanes (one wavefront) read y_I first
+            y[I * BS + m.c] = acc;
+        }
+    }
+    __syncthreads();
+    store_slice<double>(z + base * BS, y, S * BS, tid, NT);
+}
+
+// 4b: z_I = w_I - sum_{K>I} Uhat_IK z_K, in place on z.
+template <int BS, int NT>
+__global__ __launch_bounds__(NT) void k_abl_upper_unit(
+    double *z, int S, const int32_t *__restrict__ Uoff, const int32_t *__restrict__ Ulp,
+    const uint16_t *__restrict__ Urow, const int32_t *__restrict__ Ubp, const uint16_t *__restrict__ Ucol,
+    const double *__restrict__ Uval, const int32_t *__restrict__ state) {
+    if (state != nullptr && *state != 0) return;
+    extern __shared__ unsigned char dd_smem[];
+    double *y = reinterpret_cast<double *>(dd_smem);
+    const int s = blockIdx.x;
+    const int64_t base = (int64_t)s * S;
+    const int tid = threadIdx.x;
+    load_slice<double>(y, z + base * BS, S * BS, tid, NT);
+    __syncthreads();
+    plain_upper<BS, double, double, NT, false, false>(y, base, s, Uoff, Ulp, Urow, Ubp, Ucol, Uval, nullptr);
+    store_slice<double>(z + base * BS, y, S * BS, tid, NT);
+}
+
+// 5 and 6: the plain level loop with the vector in global memory (z) or
+// with one thread per row.
+template <int BS, int NT, bool GLOBAL, bool VC>
+__global__ __launch_bounds__(NT) void k_abl_plain(
+    const double *__restrict__ r, double *__restrict__ z, int S, const int32_t *__restrict__ Loff,
+    const int32_t *__restrict__ Llp, const uint16_t *__restrict__ Lrow, const int32_t *__restrict__ Lbp,
+    const uint16_t *__restrict__ Lcol, const double *__restrict__ Lval, const int32_t *__restrict__ Uoff,
+    const int32_t *__restrict__ Ulp, const uint16_t *__restrict__ Urow, const int32_t *__restrict__ Ubp,
+    const uint16_t *__restrict__ Ucol, const double *__restrict__ Uval, const double *__restrict__ Dval,
+    const int32_t *__restrict__ state) {
+    if (state != nullptr && *state != 0) return;
+    extern __shared__ unsigned char dd_smem[];
+    const int s = blockIdx.x;
+    const int64_t base = (int64_t)s * S;
+    const int tid = threadIdx.x;
+    double *y = GLOBAL ? z + base * BS : reinterpret_cast<double *>(dd_smem);
+    if constexpr (GLOBAL) {
+        for (int i = tid; i < S * BS; i += NT) y[i] = r[base * BS + i];
+    } else {
+        load_slice<double>(y, r + base * BS, S * BS, tid, NT);
+    }
+    __syncthreads();
+    plain_lower<BS, double, double, NT, VC>(y, base, s, Loff, Llp, Lrow, Lbp, Lcol, Lval);
+    plain_upper<BS, double, double, NT, VC, true>(y, base, s, Uoff, Ulp, Urow, Ubp, Ucol, Uval, Dval);
+    if constexpr (!GLOBAL) store_slice<double>(z + base * BS, y, S * BS, tid, NT);
+}
+
+// 7: the upper sweep in ILU0 form, z_I = inv(U_II) (y_I - sum_{K>I} U_IK z_K):
+// the U blocks as factored (packed in the same sweep order as Uhat), and the
+// BS lanes of a row exchange their sums before the scaling.
+template <int BS, int NT>
+__global__ __launch_bounds__(NT) void k_abl_ilu0(
+    const double *__restrict__ r, double *__restrict__ z, int S, const int32_t *__restrict__ Loff,
+    const int32_t *__restrict__ Llp, const uint16_t *__restrict__ Lrow, const int32_t *__restrict__ Lbp,
+    const uint16_t *__restrict__ Lcol, const double *__restrict__ Lval, const int32_t *__restrict__ Uoff,
+    const int32_t *__restrict__ Ulp, const uint16_t *__restrict__ Urow, const int32_t *__restrict__ Ubp,
+    const uint16_t *__restrict__ Ucol, const double *__restrict__ Uraw, const double *__restrict__ Dval,
+    const int32_t *__restrict__ state) {
+    if (state != nullptr && *state != 0) return;
+    constexpr int BB = BS * BS;
+    extern __shared__ unsigned char dd_smem[];
+    double *y = reinterpret_cast<double *>(dd_smem);
+    const int s = blockIdx.x;
+    const int64_t base = (int64_t)s * S;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    load_slice<double>(y, r + base * BS, S * BS, tid, NT);
+    __syncthreads();
+    plain_lower<BS, double, double, NT, false>(y, base, s, Loff, Llp, Lrow, Lbp, Lcol, Lval);
+    const RowMap<NT, false, BS> m;
+    const int32_t o = Uoff[s];
+    const int nl = Uoff[s + 1] - o - 1;
+    for (int l = 0; l < nl; ++l) {
+        const int32_t p0 = Ulp[o + l], p1 = Ulp[o + l + 1];
+        for (int32_t pb = p0; pb < p1; pb += m.RPP) {
+            const int32_t p = pb + m.slot;
+            const bool row = m.ok && p < p1;
+            const int64_t gp = base + p;
+            int I = 0;
+            double acc = 0;
+            if (row) {
+                I = Urow[gp];
+                acc = y[I * BS + m.c];
+                const int32_t b1 = Ubp[gp + 1];
+                for (int32_t b = Ubp[gp]; b < b1; ++b) {
+                    const int K = Ucol[b];
+                    const double *blk = Uraw + (int64_t)b * BB + m.c * BS;
+#pragma unroll
+                    for (int d = 0; d < BS; ++d) acc -= blk[d] * y[K * BS + d];
+                }
+            }
+            // the row's BS sums, from its BS consecutive lanes (all lanes take part)
+            double sum[BS];
+#pragma unroll
+            for (int d = 0; d < BS; ++d) sum[d] = __shfl(acc, lane - m.c + d);
+            if (row) {
+                const double *inv = Dval + gp * BB + m.c * BS;
+                double zc = 0;
+#pragma unroll
+                for (int d = 0; d < BS; ++d) zc += inv[d] * sum[d];
+                y[I * BS + m.c] = zc;
+            }
+        }
+        __syncthreads();
+    }
+    store_slice<double>(z + base * BS, y, S * BS, tid, NT);
+}
+
+// 8: Algorithm 4 recast for the whole apply.  No barrier between levels:
+// wavefront w takes the positions w, w + W, w + 2W, ... of a sweep (W
+// wavefronts, positions in sweep order, so every dependency of a row sits at
+// an earlier position).  The wavefront that holds the earliest unfinished
+// row can therefore always proceed, and no wavefront waits on a row it holds
+// itself.  Lane k of the row's wavefront owns its k-th off-diagonal block:
+// it waits until the block's column row is complete (a byte flag per row in
+// LDS), multiplies the block by that row's values, and lane 0 sums the
+// products in block order, writes the row and then sets its flag.  Every
+// wait is bounded: after kSpinMax polls the workgroup gives up (an abort
+// flag in LDS ends every other wait too) and writes NaN over its slice of z,
+// so a wait that could not end shows up as a wrong result, never as a hang.
+constexpr int kSpinMax = 1 << 20;
+
+struct SpinShared {
+    uint8_t *done;
+    int *abort;
+};
+
+template <int BS, int NT, bool UPPER>
+__device__ __forceinline__ void spin_sweep(double *__restrict__ y, const SpinShared &sh, int64_t base, int S,
+                                           const uint16_t *__restrict__ prow, const int32_t *__restrict__ bp,
+                                           const uint16_t *__restrict__ col, const double *__restrict__ val,
+                                           const double *__restrict__ dval) {
+    constexpr int BB = BS * BS;
+    constexpr uint8_t kWant = UPPER ? 2 : 1;
+    constexpr int W = NT / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int32_t p = threadIdx.x / kWave; p < S; p += W) {
+        if (__builtin_amdgcn_readfirstlane(*(volatile int *)sh.abort)) break;
+        const int64_t gp = base + p;
+        const int I = prow[gp];
+        const int32_t b0 = bp[gp];
+        const int nb = bp[gp + 1] - b0;  // at most 64 (kMaxRowBlocks)
+        double prod[BS];
+#pragma unroll
+        for (int c = 0; c < BS; ++c) prod[c] = 0;
+        if (lane < nb) {
+            const int J = col[b0 + lane];
+            for (int it = 0; *(volatile uint8_t *)(sh.done + J) < kWant; ++it) {
+                if (it >= kSpinMax || *(volatile int *)sh.abort) {
+                    *(volatile int *)sh.abort = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            const double *blk = val + (int64_t)(b0 + lane) * BB;
+#pragma unroll
+            for (int c = 0; c < BS; ++c)
+#pragma unroll
+                for (int d = 0; d < BS; ++d) prod[c] += blk[c * BS + d] * y[J * BS + d];
+        }
+        double acc[BS];
+#pragma unroll
+        for (int c = 0; c < BS; ++c) {
+            if constexpr (UPPER) {
+                acc[c] = 0;
+#pragma unroll
+                for (int d = 0; d < BS; ++d) acc[c] += dval[gp * BB + c * BS + d] * y[I * BS + d];
+            } else {
+                acc[c] = y[I * BS + c];
+            }
+        }
+        for (int k = 0; k < nb; ++k)
+#pragma unroll
+            for (int c = 0; c < BS; ++c) acc[c] -= __shfl(prod[c], k);
+        if (lane == 0) {
+#pragma unroll
+            for (int c = 0; c < BS; ++c) y[I * BS + c] = acc[c];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            *(volatile uint8_t *)(sh.done + I) = kWant;
+        }
+    }
+}
+
+template <int BS, int NT>
+__global__ __launch_bounds__(NT) void k_abl_spin(
+    const double *__restrict__ r, double *__restrict__ z, int S, const uint16_t *__restrict__ Lrow,
+    const int32_t *__restrict__ Lbp, const uint16_t *__restrict__ Lcol, const double *__restrict__ Lval,
+    const uint16_t *__restrict__ Urow, const int32_t *__restrict__ Ubp, const uint16_t *__restrict__ Ucol,
+    const double *__restrict__ Uval, const double *__restrict__ Dval, const int32_t *__restrict__ state) {
+    if (state != nullptr && *state != 0) return;
+    extern __shared__ unsigned char dd_smem[];
+    double *y = reinterpret_cast<double *>(dd_smem);
+    SpinShared sh;
+    sh.done = dd_smem + (size_t)S * BS * sizeof(double);
+    sh.abort = reinterpret_cast<int *>(dd_smem + (((size_t)S * BS * sizeof(double) + S + 3) & ~(size_t)3));
+    const int s = blockIdx.x;
+    const int64_t base = (int64_t)s * S;
+    const int tid = threadIdx.x;
+    load_slice<double>(y, r + base * BS, S * BS, tid, NT);
+    for (int i = tid; i < S; i += NT) sh.done[i] = 0;
+    if (tid == 0) *sh.abort = 0;
+    __syncthreads();
+    spin_sweep<BS, NT, false>(y, sh, base, S, Lrow, Lbp, Lcol, Lval, nullptr);
+    __syncthreads();  // the upper sweep reads y_I of rows other wavefronts finished
+    spin_sweep<BS, NT, true>(y, sh, base, S, Urow, Ubp, Ucol, Uval, Dval);
+    __syncthreads();
+    if (*(volatile int *)sh.abort) {
+        for (int i = tid; i < S * BS; i += NT) z[base * BS + i] = __builtin_nan("");
+    } else {
+        store_slice<double>(z + base * BS, y, S * BS, tid, NT);
+    }
+}
+
+int spin_lds_bytes(const dd_ctx *h) {
+    return (int)((((size_t)h->S * h->bs * sizeof(double) + h->S + 3) & ~(size_t)3) + sizeof(int));
+}
+
+// ------------------------------------------------------------------------
 // Host side: variant choice and launch.
 template <typename K>
 static hipError_t allow_full_lds(K kern, bool &done) {
@@ -718,6 +1060,14 @@ static bool compute_fp64(int precision) { return precision != DD_FP32; }
 
 int apply_lds_bytes(const dd_ctx *h, int precision) {
     return h->S * h->bs * (compute_fp64(precision) ? 8 : 4);
+}
+
+const char *variant_unsupported(const dd_ctx *h, int v) {
+    if (v < 4) return nullptr;
+    if (h->precision != DD_FP64) return "apply variants 4-8 are FP64 ablations (set precision DD_FP64)";
+    if (h->lic.active) return "apply variants 4-8 do not apply the learned correction (clear its parameters)";
+    if (v == 8 && spin_lds_bytes(h) > 163840) return "apply variant 8: vector and row flags exceed the LDS";
+    return nullptr;
 }
 
 template <typename TS>
@@ -765,6 +1115,63 @@ static hipError_t launch_slots_mb(dd_ctx *h, const double *r, double *z, const i
     }
 }
 
+// Ablation variants 4-8 (FP64; the API rejects other precisions and the
+// learned correction for them).
+template <int BS, int NT>
+static hipError_t launch_ablation(dd_ctx *h, int variant, const double *r, double *z, const int32_t *state,
+                                  hipStream_t st) {
+    const Sweep &L = h->sw[0], &U = h->sw[1];
+    const Levels &LL = h->lev[0], &UL = h->lev[1];
+    const int lds = h->S * BS * (int)sizeof(double);
+    const unsigned g = (unsigned)h->nsub;
+    hipError_t e = hipSuccess;
+    switch (variant) {
+        case 4: {
+            auto k1 = k_abl_lower_scale<BS, NT>;
+            auto k2 = k_abl_upper_unit<BS, NT>;
+            static bool d1 = false, d2 = false;
+            if ((e = allow_full_lds(k1, d1)) != hipSuccess || (e = allow_full_lds(k2, d2)) != hipSuccess) return e;
+            k1<<<g, NT, lds, st>>>(r, z, h->S, LL.off, LL.ptr, L.prow, L.bptr, L.bcol, L.val64, U.prow, U.d64, state);
+            k2<<<g, NT, lds, st>>>(z, h->S, UL.off, UL.ptr, U.prow, U.bptr, U.bcol, U.val64, state);
+            break;
+        }
+        case 5:
+            k_abl_plain<BS, NT, true, false><<<g, NT, 0, st>>>(r, z, h->S, LL.off, LL.ptr, L.prow, L.bptr, L.bcol,
+                                                               L.val64, UL.off, UL.ptr, U.prow, U.bptr, U.bcol,
+                                                               U.val64, U.d64, state);
+            break;
+        case 6: {
+            auto k = k_abl_plain<BS, NT, false, true>;
+            static bool d = false;
+            if ((e = allow_full_lds(k, d)) != hipSuccess) return e;
+            k<<<g, NT, lds, st>>>(r, z, h->S, LL.off, LL.ptr, L.prow, L.bptr, L.bcol, L.val64, UL.off, UL.ptr,
+                                  U.prow, U.bptr, U.bcol, U.val64, U.d64, state);
+            break;
+        }
+        case 7: {
+            auto k = k_abl_ilu0<BS, NT>;
+            static bool d = false;
+            if ((e = allow_full_lds(k, d)) != hipSuccess) return e;
+            if (!U.uraw) return hipErrorInvalidValue;  // built by the API before the first launch
+            k<<<g, NT, lds, st>>>(r, z, h->S, LL.off, LL.ptr, L.prow, L.bptr, L.bcol, L.val64, UL.off, UL.ptr,
+                                  U.prow, U.bptr, U.bcol, U.uraw, U.d64, state);
+            break;
+        }
+        case 8: {
+            auto k = k_abl_spin<BS, NT>;
+            static bool d = false;
+            const int sl = spin_lds_bytes(h);
+            if (sl > 163840) return hipErrorInvalidValue;  // vector + flags must fit the LDS
+            if ((e = allow_full_lds(k, d)) != hipSuccess) return e;
+            k<<<g, NT, sl, st>>>(r, z, h->S, L.prow, L.bptr, L.bcol, L.val64, U.prow, U.bptr, U.bcol, U.val64,
+                                 U.d64, state);
+            break;
+        }
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <int BS, typename TS, typename TC, int NT>
 static hipError_t launch_typed(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st) {
     const Sweep &L = h->sw[0], &U = h->sw[1];
@@ -773,6 +1180,11 @@ static hipError_t launch_typed(dd_ctx *h, const double *r, double *z, const int3
     const bool one_pass = h->max_level_width <= RPP;
     const bool lic = BS == 3 && h->lic.active;
     int variant = h->variant;
+    if (variant >= 4) {
+        if constexpr (sizeof(TS) == 8 && sizeof(TC) == 8)
+            return launch_ablation<BS, NT>(h, variant, r, z, state, st);
+        return hipErrorInvalidValue;  // rejected by the API before launch
+    }
     if (variant == 0) variant = h->slots ? 3 : 2;
     if (variant == 3 && (!one_pass || !h->slots)) variant = 1;
     if (variant == 2 && (!one_pass || lic)) variant = 1;

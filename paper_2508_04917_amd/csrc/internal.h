@@ -28,6 +28,7 @@ struct Sweep {
     double *val64 = nullptr;    // [nblk*bb] L blocks (lower) or Uhat (upper)
     float *val32 = nullptr;     // FP32 copy (built on demand)
     double *d64 = nullptr;      // upper only: inv_D per position [n*bb]
+    double *uraw = nullptr;     // upper only, built on demand: U blocks without the inv_D scaling [nblk*bb]
     float *d32 = nullptr;
     int64_t nblk = 0;
     int32_t max_row = 0;        // most blocks of any row in this sweep
@@ -109,7 +110,7 @@ struct dd_ctx {
     int32_t max_level_width = 0;  // widest level of any subdomain, L or U
     int32_t profile = 0;          // time every apply inside bicgstab_solve
     int32_t slots = 0;            // MB of the slot layout (0: CSR layout only)
-    int32_t variant = 0;          // apply kernel: 0 auto, 1 simple, 2 pipelined CSR, 3 slots
+    int32_t variant = 0;          // apply kernel: 0 auto, 1 simple, 2 pipelined CSR, 3 slots, 4-8 ablations
     double *hist = nullptr;       // optional residual history (device, caller-owned)
     ddilu::Lic lic;
     int32_t pc_kind = 0;          // preconditioner of bicgstab_solve: 0 DD-ILU0, 1 global ILU0
@@ -177,6 +178,7 @@ hipError_t launch_level_lists(dd_ctx *h, int which, hipStream_t st);
 hipError_t launch_bilu0(dd_ctx *h, hipStream_t st);
 hipError_t launch_pack_count(dd_ctx *h, int which, int32_t *cnt, hipStream_t st);
 hipError_t launch_pack_fill(dd_ctx *h, int which, hipStream_t st);
+hipError_t launch_pack_unscaled(dd_ctx *h, hipStream_t st);
 hipError_t launch_cast32(dd_ctx *h, hipStream_t st);
 hipError_t launch_pack_slots(dd_ctx *h, int which, hipStream_t st);
 hipError_t launch_max_count(int64_t n, const int32_t *cnt, int32_t *out, hipStream_t st);
@@ -185,6 +187,10 @@ hipError_t launch_export_factors(dd_ctx *h, double *f, hipStream_t st);
 hipError_t launch_apply(dd_ctx *h, const double *r, double *z, const int32_t *state,
                         hipStream_t st);
 int apply_lds_bytes(const dd_ctx *h, int precision);
+int spin_lds_bytes(const dd_ctx *h);
+// 0 if the handle's precision and correction allow apply variant v, else the
+// reason (for the ablation variants 4-8: FP64 only, no learned correction)
+const char *variant_unsupported(const dd_ctx *h, int v);
 
 // Krylov
 hipError_t launch_spmv(dd_ctx *h, const double *x, double *y, hipStream_t st);

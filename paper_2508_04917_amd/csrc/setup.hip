@@ -498,6 +498,8 @@ __global__ void k_pack_count(int64_t n, int S, int which, const int32_t *tptr, c
     cnt[p] = c;
 }
 
+// which 0: L blocks; 1: Uhat = inv_D U blocks and inv_D; 2: the U blocks as
+// factored (no scaling; val only, same order as for 1).
 template <int BS>
 __global__ void k_pack_fill(int64_t n, int S, int which, const int32_t *tptr, const int32_t *tcol,
                             const double *lu, const double *invd, const int32_t *rows, const int32_t *bptr,
@@ -507,14 +509,14 @@ __global__ void k_pack_fill(int64_t n, int S, int which, const int32_t *tptr, co
     if (p >= n) return;
     const int64_t base = (p / S) * (int64_t)S;
     const int64_t gi = base + rows[p];
-    prow[p] = (uint16_t)rows[p];
+    if (which != 2) prow[p] = (uint16_t)rows[p];
     int32_t b = bptr[p];
     const double *inv = invd + gi * BB;
     for (int32_t q = tptr[gi]; q < tptr[gi + 1]; ++q) {
         const int32_t c = tcol[q];
         if (which == 0 ? (c < gi) : (c > gi)) {
-            bcol[b] = (uint16_t)(c - base);
-            if (which == 0) {
+            if (which != 2) bcol[b] = (uint16_t)(c - base);
+            if (which != 1) {
 #pragma unroll
                 for (int e = 0; e < BB; ++e) val[(int64_t)b * BB + e] = lu[(int64_t)q * BB + e];
             } else {
@@ -530,6 +532,19 @@ __global__ void k_pack_fill(int64_t n, int S, int which, const int32_t *tptr, co
 #pragma unroll
         for (int e = 0; e < BB; ++e) dval[p * BB + e] = inv[e];
     }
+}
+
+hipError_t launch_pack_unscaled(dd_ctx *h, hipStream_t st) {
+    const int T = 256;
+    Sweep &w = h->sw[1];
+    const unsigned g = (unsigned)((h->n + T - 1) / T);
+    if (h->bs == 3)
+        k_pack_fill<3><<<g, T, 0, st>>>(h->n, h->S, 2, h->tptr, h->tcol, h->lu, h->invd, h->lev[1].rows, w.bptr,
+                                        nullptr, nullptr, w.uraw, nullptr);
+    else
+        k_pack_fill<1><<<g, T, 0, st>>>(h->n, h->S, 2, h->tptr, h->tcol, h->lu, h->invd, h->lev[1].rows, w.bptr,
+                                        nullptr, nullptr, w.uraw, nullptr);
+    return hipGetLastError();
 }
 
 hipError_t launch_pack_count(dd_ctx *h, int which, int32_t *cnt, hipStream_t st) {

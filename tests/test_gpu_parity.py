@@ -115,6 +115,63 @@ def test_apply_fp64(name, variant):
         P.ddilu.dd_set_apply_variant(s.h, 0)
 
 
+# Ablation variants of the plain level loop (Section 5.2 kernel variants):
+# 4 split lower+D / upper kernels, 5 vector in global memory, 6 one thread
+# per block row, 7 ILU0-form upper sweep (unscaled U, row sums scaled by
+# inv(U_II)), 8 synchronisation-free sweeps with per-row flags (Algorithm 4).
+# Same z up to rounding order, so the FP64 tolerance applies.
+ABLATIONS = (4, 5, 6, 7, 8)
+
+
+@pytest.mark.parametrize("variant", ABLATIONS)
+@pytest.mark.parametrize("name", list(CASES))
+def test_apply_ablation_fp64(name, variant):
+    p, s, st = case(name)
+    print(f"[ablation v{variant}] {name}", flush=True)
+    P.ddilu.dd_set_apply_variant(s.h, variant)
+    rng = np.random.default_rng(321)
+    try:
+        for trial in range(2):
+            r = rng.standard_normal(st.n * st.bs)
+            z_o = st.apply(r)
+            z_g = np_(s.apply(torch.as_tensor(r, device="cuda")))
+            assert np.isfinite(z_g).all(), f"{name}: non-finite output"
+            err = np.linalg.norm(z_g - z_o) / np.linalg.norm(z_o)
+            assert err < RTOL_FP64, f"{name}: rel err {err:.3e}"
+    finally:
+        P.ddilu.dd_set_apply_variant(s.h, 0)
+
+
+def test_ablation_rejects_reduced_precision():
+    p, s, st = case("rand_ragged")
+    P.ddilu.dd_set_apply_variant(s.h, 5)
+    try:
+        s.set_precision(P.ddilu.DD_MIXED)
+        r = torch.zeros(st.n * st.bs, dtype=torch.float64, device="cuda")
+        with pytest.raises(P.ddilu.DDError, match="FP64 ablations"):
+            s.apply(r)
+    finally:
+        s.set_precision(P.ddilu.DD_FP64)
+        P.ddilu.dd_set_apply_variant(s.h, 0)
+
+
+@pytest.mark.parametrize("variant", (4, 8))
+def test_bicgstab_with_ablation(variant):
+    """The solve runs with an ablation variant as its preconditioner and
+    lands in the iteration band of the default kernel (same M up to
+    rounding)."""
+    p, s, st = case("logn_24_32_40")
+    b = torch.as_tensor(p.b, device="cuda")
+    _, i0 = s.solve(b, rtol=1e-8)
+    P.ddilu.dd_set_apply_variant(s.h, variant)
+    try:
+        x, i1 = s.solve(b, rtol=1e-8)
+    finally:
+        P.ddilu.dd_set_apply_variant(s.h, 0)
+    assert i1["status"] == 0 and i1["rel_res_true"] <= 2e-8
+    assert abs(i1["iters"] - i0["iters"]) <= max(3, i0["iters"] // 10), (i0["iters"], i1["iters"])
+
+
 # FP32 factors (task addition (1), not in the paper).
 # DD_FP32: the GPU computes in FP32 throughout the apply; the oracle applies
 # FP32-rounded factors to the FP32-rounded input in FP64.  The difference is
