@@ -60,7 +60,26 @@ def build(verbose: bool = False) -> str:
             if verbose:
                 print(f"{name}: {n} slot kernels pass the in-flight register check", flush=True)
         _link(objs, verbose)
+    build_rocsparse_ref(verbose)
     return LIB
+
+
+# The vendor-library baseline (rocSPARSE block ILU0 + block triangular
+# solves) used by bench.py --mode rocsparse and its parity test; a library of
+# its own so that libddilu.so does not depend on rocSPARSE.
+REF_SRC = os.path.join(HERE, "rocsparse_ref", "rocsparse_ilu0.cpp")
+REF_LIB = os.path.join(HERE, "rocsparse_ref", "librocsparse_ref.so")
+
+
+def build_rocsparse_ref(verbose: bool = False) -> str:
+    out = REF_LIB + ".tmp"
+    cmd = [HIPCC, "-O2", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950", REF_SRC, "-o", out,
+           "-lrocsparse"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(out, REF_LIB)
+    return REF_LIB
 
 
 def _link(objs, verbose):
