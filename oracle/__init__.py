@@ -51,6 +51,7 @@ def lib():
             "o_block_inverse": (C.c_int, [C.c_int, vp, vp]),
             "o_partition": (C.c_int, [C.c_int] * 6 + [vp]),
             "o_permutation": (C.c_int, [i64, i32, vp, vp, vp]),
+            "o_graph_partition": (C.c_int, [i64, vp, vp, i32, vp]),
             "o_reorder": (C.c_int, [i64, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp]),
             "o_drop": (i64, [i64, C.c_int, i64, vp, vp, vp, vp, vp, vp]),
             "o_levels": (C.c_int, [i64, vp, vp, C.c_int, vp]),
@@ -144,6 +145,17 @@ def partition(nx, ny, nz, sx, sy, sz):
     if rc:
         raise OracleError(rc, "partition")
     return out
+
+
+def graph_partition(n, ptr, col, S):
+    """Parts of exactly S vertices of the matrix graph, by recursive BFS
+    bisection (no geometry; METIS stand-in, see o_graph_partition)."""
+    ptr, col = _i32(ptr), _i32(col)
+    pid = np.empty(n, dtype=np.int32)
+    rc = lib().o_graph_partition(n, _p(ptr), _p(col), S, _p(pid))
+    if rc:
+        raise OracleError(rc, f"graph partition of {n} vertices into parts of {S}")
+    return pid
 
 
 def permutation(part_id, nsub):
@@ -364,8 +376,19 @@ def setup(problem, sub):
     sx, sy, sz = sub
     n = nx * ny * nz
     S = sx * sy * sz
-    nsub = n // S
     pid = partition(nx, ny, nz, sx, sy, sz)
+    return _setup_from_labels(problem, n, bs, S, tuple(sub), pid)
+
+
+def setup_graph(problem, S):
+    """As setup, with the labels of graph_partition (parts of S vertices)."""
+    n = problem.brow_ptr.shape[0] - 1
+    pid = graph_partition(n, problem.brow_ptr, problem.bcol, S)
+    return _setup_from_labels(problem, n, problem.bs, S, (S, 1, 1), pid)
+
+
+def _setup_from_labels(problem, n, bs, S, sub, pid):
+    nsub = n // S
     n2o, o2n = permutation(pid, nsub)
     aptr, acol, aval = reorder(n, bs, problem.brow_ptr, problem.bcol, problem.val, n2o, o2n)
     tptr, tcol, tval = drop(n, bs, S, aptr, acol, aval)

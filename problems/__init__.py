@@ -9,6 +9,8 @@ same arrays, so a parity test compares the two on identical data.
 from .generators import (  # noqa: F401
     Problem,
     stencil_pattern,
+    grid_graph,
+    unstructured_problem,
     laplacian_scalar,
     random_blocks,
     lognormal_field,

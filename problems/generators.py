@@ -109,6 +109,48 @@ def random_blocks(nx: int = 64, ny: int = 64, nz: int = 64, seed: int = 2) -> Pr
     return Problem("random_blocks", nx, ny, nz, 3, ptr, col, val, b, seed)
 
 
+def grid_graph(nx: int, ny: int, nz: int):
+    """Pattern (brow_ptr, bcol) of the 7-point grid operator (5-point in 2D,
+    a path in 1D), diagonal included: a graph with known geometry."""
+    ptr, col, _ = stencil_pattern(nx, ny, nz)
+    return ptr, col
+
+
+def unstructured_problem(n: int, seed: int, bs: int = 3, k: int = 6) -> Problem:
+    """Stand-in for the paper's unstructured matrices (graph-partitioned
+    there with METIS): n random points in the unit cube, each coupled to its
+    k nearest neighbours (pattern symmetrised, diagonal added), numbered in
+    the random order the points were drawn, so the numbering carries no
+    locality.  Draw order from ``default_rng(seed)``: points (n,3), G
+    (n,bs,bs), H (off-diagonal blocks in CSR order, bs,bs), b (n*bs).
+    A_II = (deg_I + 0.5) I + 0.1 (G+G^T)/2, A_IJ = -I + 0.05 H_IJ; returned
+    with nx = n, ny = nz = 1."""
+    from scipy.spatial import cKDTree
+
+    rng = np.random.default_rng(seed)
+    pts = rng.random((n, 3))
+    _, nb = cKDTree(pts).query(pts, k=k + 1)
+    rows = np.repeat(np.arange(n, dtype=np.int64), k)
+    cols = nb[:, 1:].reshape(-1).astype(np.int64)
+    pairs = np.unique(np.concatenate([rows * n + cols, cols * n + rows, np.arange(n, dtype=np.int64) * (n + 1)]))
+    r, c = pairs // n, pairs % n
+    counts = np.bincount(r, minlength=n)
+    ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=ptr[1:])
+    nnzb = c.shape[0]
+    G = rng.standard_normal((n, bs, bs))
+    H = rng.standard_normal((nnzb - n, bs, bs))
+    b = rng.standard_normal(n * bs)
+    eye = np.eye(bs)
+    diag = r == c
+    deg = counts - 1
+    val = np.empty((nnzb, bs, bs), dtype=np.float64)
+    val[diag] = (deg + 0.5)[:, None, None] * eye + 0.1 * 0.5 * (G + G.transpose(0, 2, 1))
+    val[~diag] = -eye + 0.05 * H
+    return Problem("unstructured", n, 1, 1, bs, ptr.astype(np.int32), c.astype(np.int32), val, b, seed,
+                   meta=dict(k=k, max_row_blocks=int(counts.max())))
+
+
 def lognormal_field(rng: np.random.Generator, nx: int, ny: int, nz: int,
                     sigma: float, corr_len: float = 8.0) -> np.ndarray:
     """Log-normal permeability k = exp(sigma * g), g a unit-variance Gaussian field.
