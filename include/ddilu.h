@@ -74,6 +74,17 @@ typedef struct {
     int64_t lds_budget_bytes;  /* LDS per workgroup, or 0                */
 } dd_partition_desc;
 
+/* A matrix graph without geometry (Section 3: labels from a graph
+ * partitioner; Section 5.4: parts balanced to one size). */
+typedef struct {
+    int64_t n;                 /* block rows (graph vertices)             */
+    int32_t bs;                /* 1 or 3                                  */
+    int32_t part_rows;         /* rows per subdomain S (n % S == 0), or 0:
+                                  the largest divisor of n whose vector
+                                  (S*bs*8 bytes) fits the LDS budget      */
+    int64_t lds_budget_bytes;  /* LDS per workgroup, or 0 (device's)      */
+} dd_graph_desc;
+
 /* Sizes of a handle's problem and setup products. */
 typedef struct {
     int64_t n;                 /* block rows                              */
@@ -139,6 +150,24 @@ int dd_device_caps(int32_t *n_cu, int64_t *lds_per_workgroup);
 int dd_partition(const dd_partition_desc *desc, const int32_t *brow_ptr,
                  const int32_t *bcol, const double *val, int64_t nnzb,
                  void *hip_stream, dd_handle *out);
+
+/* Like dd_partition for a matrix whose rows carry no grid position: the
+ * labels come from a graph partitioner instead of geometric cuts (the paper
+ * uses METIS and balances the parts to one size by hand; METIS is not
+ * available, so the partitioner here is recursive BFS bisection into parts
+ * of exactly S vertices: a segment of k parts splits by a BFS inside it
+ * from its smallest vertex, a second BFS from the farthest vertex reached
+ * (smallest index on ties), and the order (distance, index), unreached
+ * vertices last, giving the first floor(k/2)*S vertices to one half).  The
+ * graph is the block pattern (brow_ptr, bcol); it need not be symmetric.
+ * The rest (Algorithm 3 renumbering by label, drop, factorisation, apply,
+ * solve) is the same as for a geometric partition; dd_get_info reports
+ * sx = S, sy = sz = 1.  Arguments, ownership and stream as for
+ * dd_partition.  Returns DD_EINVAL (bad arguments, a row of more than 64
+ * blocks, a column outside [0, n)), DD_ENOTDIV (n not divisible by
+ * part_rows), DD_ELDS, DD_EHIP, DD_ENOMEM. */
+int dd_partition_graph(const dd_graph_desc *d, const int32_t *brow_ptr, const int32_t *bcol,
+                       const double *val, int64_t nnzb, void *hip_stream, dd_handle *out);
 
 /* Sizes of the handle's products (host struct). */
 int dd_get_info(dd_handle h, dd_info *info);

@@ -119,6 +119,9 @@ extern "C" int dd_device_caps(int32_t *n_cu, int64_t *lds_per_workgroup) {
 }
 
 // -------------------------------------------------------------- partition
+static int build_handle(dd_ctx *h, const int32_t *brow_ptr, const int32_t *bcol, const double *val,
+                        hipStream_t st, dd_handle *out);
+
 extern "C" int dd_partition(const dd_partition_desc *d, const int32_t *brow_ptr, const int32_t *bcol,
                             const double *val, int64_t nnzb, void *hip_stream, dd_handle *out) {
     if (!d || !brow_ptr || !bcol || !val || !out) return set_global_error(DD_EINVAL, "dd_partition: null argument");
@@ -160,7 +163,54 @@ extern "C" int dd_partition(const dd_partition_desc *d, const int32_t *brow_ptr,
     h->n = n;
     h->nsub = (int32_t)(n / S);
     h->nnzb = nnzb;
-    hipStream_t st = as_stream(hip_stream);
+    return build_handle(h, brow_ptr, bcol, val, as_stream(hip_stream), out);
+}
+
+extern "C" int dd_partition_graph(const dd_graph_desc *d, const int32_t *brow_ptr, const int32_t *bcol,
+                                  const double *val, int64_t nnzb, void *hip_stream, dd_handle *out) {
+    if (!d || !brow_ptr || !bcol || !val || !out)
+        return set_global_error(DD_EINVAL, "dd_partition_graph: null argument");
+    *out = nullptr;
+    const int64_t n = d->n;
+    if (n <= 0 || n >= (int64_t)1 << 31) return set_global_error(DD_EINVAL, "dd_partition_graph: bad n %lld", (long long)n);
+    if (d->bs != 1 && d->bs != 3) return set_global_error(DD_EINVAL, "dd_partition_graph: bs must be 1 or 3");
+    if (nnzb < n || nnzb >= ((int64_t)1 << 31))
+        return set_global_error(DD_EINVAL, "dd_partition_graph: bad nnzb %lld", (long long)nnzb);
+    int64_t lds = d->lds_budget_bytes;
+    if (lds <= 0) {
+        int32_t c;
+        int rc = dd_device_caps(&c, &lds);
+        if (rc) return rc;
+    }
+    int64_t S = d->part_rows;
+    if (S == 0) {  // the largest divisor of n whose vector fits the LDS budget
+        const int64_t cap = std::min<int64_t>(65535, lds / (8 * d->bs));
+        for (int64_t c = std::min(cap, n); c >= 1 && S == 0; --c)
+            if (n % c == 0) S = c;
+    }
+    if (S <= 0 || n % S)
+        return set_global_error(DD_ENOTDIV, "dd_partition_graph: %lld block rows not divisible by part_rows %lld",
+                                (long long)n, (long long)S);
+    if (S * d->bs * 8 > lds)
+        return set_global_error(DD_ELDS, "subdomain vector of %lld bytes exceeds the LDS budget %lld",
+                                (long long)(S * d->bs * 8), (long long)lds);
+    if (S > 65535) return set_global_error(DD_EINVAL, "subdomain of %lld rows exceeds 65535", (long long)S);
+    dd_ctx *h = new dd_ctx();
+    h->nx = (int32_t)n; h->ny = 1; h->nz = 1; h->bs = d->bs;
+    h->sx = (int32_t)S; h->sy = 1; h->sz = 1;
+    h->graph = 1;
+    h->S = (int32_t)S;
+    h->n = n;
+    h->nsub = (int32_t)(n / S);
+    h->nnzb = nnzb;
+    return build_handle(h, brow_ptr, bcol, val, as_stream(hip_stream), out);
+}
+
+// Everything after the subdomain size is fixed: labels and the permutation
+// (geometric cuts, or the graph partitioner when h->graph), then Algorithm 3.
+static int build_handle(dd_ctx *h, const int32_t *brow_ptr, const int32_t *bcol, const double *val,
+                        hipStream_t st, dd_handle *out) {
+    const int64_t n = h->n, nnzb = h->nnzb;
     const int bb = h->bs * h->bs;
     int rc = 0;
     int32_t *len = nullptr, *src = nullptr;
@@ -187,7 +237,27 @@ extern "C" int dd_partition(const dd_partition_desc *d, const int32_t *brow_ptr,
         }                                                                         \
     } while (0)
     PCHK(hipMemcpyAsync(h->status, init_status, sizeof(init_status), hipMemcpyHostToDevice, st));
-    PCHK(launch_partition(h, st));
+    // the caller's pattern is checked before any kernel indexes through it
+    PCHK(launch_check_rows(n, nnzb, brow_ptr, bcol, h->status, st));
+    {
+        int32_t bad = 0;
+        PCHK(hipMemcpyAsync(&bad, h->status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        PCHK(hipStreamSynchronize(st));
+        if (bad & 1) {
+            h->fail(DD_EINVAL, "a row holds more than %d blocks (or brow_ptr is not monotone within nnzb)",
+                    kMaxRowBlocks);
+            return bail(DD_EINVAL);
+        }
+        if (bad & 2) {
+            h->fail(DD_EINVAL, "a column index lies outside [0, %lld)", (long long)n);
+            return bail(DD_EINVAL);
+        }
+    }
+    if (h->graph) {
+        if ((rc = graph_partition(h, brow_ptr, bcol, st))) return bail(rc);
+    } else {
+        PCHK(launch_partition(h, st));
+    }
     PCHK(launch_row_len(h, brow_ptr, len, st));
     PCHK(exclusive_scan(len, h->aptr, n, h->scan_tmp, st));
     int32_t total = 0, status[8];

@@ -93,6 +93,7 @@ struct dd_ctx {
     int32_t nx = 0, ny = 0, nz = 0, bs = 0;
     int32_t sx = 0, sy = 0, sz = 0;
     int32_t S = 0, nsub = 0;
+    int32_t graph = 0;            // labels from the graph partitioner (no geometry: nx = n, sx = S)
     int64_t n = 0, nnzb = 0;
     int32_t *part_id = nullptr, *new2old = nullptr, *old2new = nullptr;
     // full reordered matrix
@@ -167,6 +168,11 @@ hipError_t exclusive_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *t
 // kernel launchers implemented in the .hip files
 namespace ddilu {
 hipError_t launch_partition(dd_ctx *h, hipStream_t st);
+// labels, new2old and old2new of a graph without geometry (recursive BFS
+// bisection into parts of h->S vertices); DD_OK or an error code
+int graph_partition(dd_ctx *h, const int32_t *ptr, const int32_t *col, hipStream_t st);
+hipError_t launch_check_rows(int64_t n, int64_t nnzb, const int32_t *ptr, const int32_t *col, int32_t *status,
+                             hipStream_t st);
 hipError_t launch_row_len(dd_ctx *h, const int32_t *ptr, int32_t *len, hipStream_t st);
 hipError_t launch_reorder_fill(dd_ctx *h, const int32_t *ptr, const int32_t *col,
                                const double *val, int32_t *src, hipStream_t st);

@@ -176,6 +176,33 @@ __global__ void k_gather_blocks(int64_t nelem, int bb, const int32_t *src, const
     out[e] = val[(int64_t)src[q] * bb + c];
 }
 
+// Input check before any kernel indexes through the caller's pattern: every
+// row has 0..kMaxRowBlocks blocks inside [0, nnzb) (status[0] |= 1), every
+// column is a block row (status[0] |= 2).
+__global__ void k_check_rows(int64_t n, int64_t nnzb, const int32_t *ptr, const int32_t *col, int32_t *status) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t b0 = ptr[i], b1 = ptr[i + 1];
+    if (b0 < 0 || b1 < b0 || b1 - b0 > kMaxRowBlocks || b1 > nnzb) {
+        atomicOr(&status[0], 1);
+        return;
+    }
+    for (int32_t q = b0; q < b1; ++q) {
+        const int32_t c = col[q];
+        if (c < 0 || c >= n) {
+            atomicOr(&status[0], 2);
+            return;
+        }
+    }
+}
+
+hipError_t launch_check_rows(int64_t n, int64_t nnzb, const int32_t *ptr, const int32_t *col, int32_t *status,
+                             hipStream_t st) {
+    const int T = 256;
+    k_check_rows<<<(unsigned)((n + T - 1) / T), T, 0, st>>>(n, nnzb, ptr, col, status);
+    return hipGetLastError();
+}
+
 hipError_t launch_row_len(dd_ctx *h, const int32_t *ptr, int32_t *len, hipStream_t st) {
     const int T = 256;
     k_row_len<<<(unsigned)((h->n + T - 1) / T), T, 0, st>>>(h->n, ptr, h->new2old, len, h->status);

@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "DD_OK", -1: "DD_EINVAL", -2: "DD_ENOTDIV", -3: "DD_ELDS", -4
                 -5: "DD_EBREAKDOWN", -6: "DD_ENOCONV", -7: "DD_EHIP", -8: "DD_ENOMEM", -9: "DD_ESTATE"}
 
 # every symbol include/ddilu.h declares
-EXPORTS = ("dd_auto_subdims", "dd_device_caps", "dd_partition", "dd_get_info", "dd_get_partition",
+EXPORTS = ("dd_auto_subdims", "dd_device_caps", "dd_partition", "dd_partition_graph", "dd_get_info", "dd_get_partition",
            "dd_get_reordered", "ilu0_factor", "dd_set_precision", "dd_get_levels", "dd_get_factors",
            "dd_trsv_apply", "dd_spmv", "bicgstab_solve", "dd_set_apply_variant", "dd_set_profiling",
            "dd_set_residual_history", "dd_global_factor", "dd_global_apply", "dd_set_preconditioner",
@@ -39,6 +39,11 @@ LIC_NPARAM = 6537
 class PartitionDesc(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("bs", C.c_int32),
                 ("sx", C.c_int32), ("sy", C.c_int32), ("sz", C.c_int32), ("n_cu", C.c_int32),
+                ("lds_budget_bytes", C.c_int64)]
+
+
+class GraphDesc(C.Structure):
+    _fields_ = [("n", C.c_int64), ("bs", C.c_int32), ("part_rows", C.c_int32),
                 ("lds_budget_bytes", C.c_int64)]
 
 
@@ -73,6 +78,7 @@ def lib():
             "dd_auto_subdims": (C.c_int, [i32, i32, i32, i32, i64, i32, vp]),
             "dd_device_caps": (C.c_int, [vp, vp]),
             "dd_partition": (C.c_int, [C.POINTER(PartitionDesc), vp, vp, vp, i64, vp, C.POINTER(vp)]),
+            "dd_partition_graph": (C.c_int, [C.POINTER(GraphDesc), vp, vp, vp, i64, vp, C.POINTER(vp)]),
             "dd_get_info": (C.c_int, [vp, C.POINTER(Info)]),
             "dd_get_partition": (C.c_int, [vp, vp, vp, vp, vp]),
             "dd_get_reordered": (C.c_int, [vp, vp, vp, vp, vp]),
@@ -187,6 +193,21 @@ def dd_partition(nx, ny, nz, bs, brow_ptr, bcol, val, sub=(0, 0, 0), n_cu=0, lds
     out = C.c_void_p(None)
     _check(lib().dd_partition(C.byref(d), _ptr(brow_ptr), _ptr(bcol), _ptr(val), nnzb, _stream(stream),
                               C.byref(out)))
+    return Handle(out.value)
+
+
+def dd_partition_graph(n, bs, brow_ptr, bcol, val, part_rows=0, lds_budget_bytes=0, stream=None) -> Handle:
+    """Partition a matrix graph without geometry (recursive BFS bisection
+    into parts of part_rows vertices; 0 = largest divisor of n that fits the
+    LDS), then reorder as dd_partition does."""
+    nnzb = bcol.numel()
+    _dev_check(brow_ptr, torch.int32, n + 1, "brow_ptr")
+    _dev_check(bcol, torch.int32, nnzb, "bcol")
+    _dev_check(val, torch.float64, nnzb * bs * bs, "val")
+    d = GraphDesc(n, bs, part_rows, lds_budget_bytes)
+    out = C.c_void_p(None)
+    _check(lib().dd_partition_graph(C.byref(d), _ptr(brow_ptr), _ptr(bcol), _ptr(val), nnzb, _stream(stream),
+                                    C.byref(out)))
     return Handle(out.value)
 
 

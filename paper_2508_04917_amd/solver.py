@@ -14,14 +14,21 @@ class DDSolver:
     """Partition + factor a BSR matrix on the GPU and keep the handle."""
 
     def __init__(self, nx, ny, nz, bs, brow_ptr, bcol, val, sub=(0, 0, 0), precision=dd.DD_FP64,
-                 n_cu=0, lds_budget_bytes=0, device="cuda"):
+                 n_cu=0, lds_budget_bytes=0, device="cuda", graph_part_rows=None):
+        """graph_part_rows: None for geometric cuts of the nx*ny*nz grid;
+        otherwise partition the matrix graph (no geometry) into parts of that
+        many rows (0 = automatic)."""
         self.device = device
         t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=dt).reshape(-1)
         ptr_d = t(brow_ptr, torch.int32)
         col_d = t(bcol, torch.int32)
         val_d = t(val, torch.float64)
-        self.h = dd.dd_partition(nx, ny, nz, bs, ptr_d, col_d, val_d, sub=sub, n_cu=n_cu,
-                                 lds_budget_bytes=lds_budget_bytes)
+        if graph_part_rows is None:
+            self.h = dd.dd_partition(nx, ny, nz, bs, ptr_d, col_d, val_d, sub=sub, n_cu=n_cu,
+                                     lds_budget_bytes=lds_budget_bytes)
+        else:
+            self.h = dd.dd_partition_graph(nx * ny * nz, bs, ptr_d, col_d, val_d, part_rows=graph_part_rows,
+                                           lds_budget_bytes=lds_budget_bytes)
         del ptr_d, col_d, val_d
         dd.ilu0_factor(self.h, precision)
         self.info = dd.dd_get_info(self.h)

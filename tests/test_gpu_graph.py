@@ -1,0 +1,128 @@
+"""Graph partitions (no geometry): the library's recursive BFS bisection
+against the oracle's, bit for bit, then the whole path on those labels —
+reordered matrix, levels, factors, apply and BiCGSTAB — against the oracle's
+graph-based setup; and the input checks of the partition calls."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from problems import grid_graph, laplacian_scalar, unstructured_problem
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2508_04917_amd import ddilu as dd  # noqa: E402
+from paper_2508_04917_amd.solver import DDSolver  # noqa: E402
+
+CASES = {
+    # name: (problem factory, rows per part)
+    "unstructured_bs3": (lambda: unstructured_problem(6000, seed=11, bs=3), 500),
+    "unstructured_bs1": (lambda: unstructured_problem(4096, seed=12, bs=1), 256),
+    "laplacian16_scalar": (lambda: laplacian_scalar(16, 16, 16, seed=1), 512),
+    "unstructured_one_part": (lambda: unstructured_problem(900, seed=13, bs=3), 900),
+    "unstructured_odd_parts": (lambda: unstructured_problem(7 * 300, seed=14, bs=3), 300),
+}
+
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        make, S = CASES[name]
+        p = make()
+        print(f"[graph {name}] n {p.n} nnzb {p.nnzb} bs {p.bs} S {S}", flush=True)
+        s = DDSolver.from_problem(p, graph_part_rows=S)
+        st = O.setup_graph(p, S)
+        _cache[name] = (p, s, st)
+    return _cache[name]
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def test_worked_example_matches_oracle():
+    ptr, col = grid_graph(4, 4, 1)
+    val = np.where(col == np.repeat(np.arange(16), np.diff(ptr)), 4.0, -1.0)
+    s = DDSolver(16, 1, 1, 1, ptr, col, val, graph_part_rows=4)
+    try:
+        pid, _, _ = dd.dd_get_partition(s.h)
+        assert np.array_equal(np_(pid), O.graph_partition(16, ptr, col, 4))
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_partition_bitexact(name):
+    p, s, st = case(name)
+    pid, n2o, o2n = dd.dd_get_partition(s.h)
+    assert np.array_equal(np_(pid), st.part_id)
+    assert np.array_equal(np_(n2o), st.new2old)
+    assert np.array_equal(np_(o2n), st.old2new)
+    inf = s.info
+    assert (inf["S"], inf["sx"], inf["sy"], inf["sz"]) == (CASES[name][1], CASES[name][1], 1, 1)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_reorder_levels_factors(name):
+    p, s, st = case(name)
+    ptr, col, val = dd.dd_get_reordered(s.h)
+    assert np.array_equal(np_(ptr), st.aptr) and np.array_equal(np_(col), st.acol)
+    assert np.array_equal(np_(val), st.aval.reshape(-1))
+    for which in (0, 1):
+        nlev, lptr, rows = dd.dd_get_levels(s.h, which)
+        onl, optr, orows = st.levels(which)
+        assert np.array_equal(np_(nlev), onl) and np.array_equal(np_(lptr), optr)
+        assert np.array_equal(np_(rows), orows)
+    fptr, fcol, f = dd.dd_get_factors(s.h)
+    assert np.array_equal(np_(fptr), st.tptr) and np.array_equal(np_(fcol), st.tcol)
+    fo = st.f.reshape(-1)
+    assert np.linalg.norm(np_(f) - fo) / np.linalg.norm(fo) < 1e-12
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 4, 8])
+@pytest.mark.parametrize("name", list(CASES))
+def test_apply(name, variant):
+    p, s, st = case(name)
+    dd.dd_set_apply_variant(s.h, variant)
+    try:
+        r = np.random.default_rng(7).standard_normal(p.n * p.bs)
+        z_o = st.apply(r)
+        z_g = np_(s.apply(torch.as_tensor(r, device="cuda")))
+        err = np.linalg.norm(z_g - z_o) / np.linalg.norm(z_o)
+        assert err < 1e-12, f"{name} v{variant}: {err:.2e}"
+    finally:
+        dd.dd_set_apply_variant(s.h, 0)
+
+
+@pytest.mark.parametrize("name", ["unstructured_bs3", "unstructured_bs1", "laplacian16_scalar"])
+def test_bicgstab(name):
+    p, s, st = case(name)
+    ref = st.bicgstab(p.b)
+    x, info = s.solve(torch.as_tensor(p.b, device="cuda"), rtol=1e-8)
+    print(f"[graph {name}] iterations GPU {info['iters']}, oracle {ref.iters}", flush=True)
+    assert info["status"] == 0 and info["rel_res_true"] <= 2e-8
+    assert abs(info["iters"] - ref.iters) <= max(3, ref.iters // 7)
+
+
+def test_rejects_indivisible_and_bad_columns():
+    p = unstructured_problem(1000, seed=15, bs=3)
+    ptr = torch.as_tensor(p.brow_ptr, device="cuda")
+    col = torch.as_tensor(p.bcol, device="cuda")
+    val = torch.as_tensor(p.val.reshape(-1), device="cuda")
+    with pytest.raises(dd.DDError, match="not divisible"):
+        dd.dd_partition_graph(p.n, 3, ptr, col, val, part_rows=300)
+    bad = col.clone()
+    bad[17] = p.n + 5
+    with pytest.raises(dd.DDError, match="column index"):
+        dd.dd_partition_graph(p.n, 3, ptr, bad, val, part_rows=250)
+    q = laplacian_scalar(8, 8, 8, seed=1)
+    qcol = torch.as_tensor(q.bcol, device="cuda").clone()
+    qcol[3] = -1
+    with pytest.raises(dd.DDError, match="column index"):
+        dd.dd_partition(8, 8, 8, 1, torch.as_tensor(q.brow_ptr, device="cuda"), qcol,
+                        torch.as_tensor(q.val.reshape(-1), device="cuda"), sub=(4, 4, 4))
