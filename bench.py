@@ -235,6 +235,49 @@ def rocsparse_cmp(args, p, sub, ptr_d, col_d, val_d, dd, torch):
     print(json.dumps(out), flush=True)
 
 
+def graph_mode(args, p, ptr_d, col_d, val_d, dd, torch):
+    """A matrix without geometry: graph partition (recursive BFS bisection,
+    automatic part size), factor, bursts of FP64 applies, and BiCGSTAB to
+    rtol, each timed."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = dd.dd_partition_graph(p.n, p.bs, ptr_d, col_d, val_d)
+    torch.cuda.synchronize()
+    t_part = time.perf_counter() - t0
+    dd.ilu0_factor(h, dd.DD_FP64)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    inf = dd.dd_get_info(h)
+    nbytes = inf["apply_bytes"]
+    r = torch.randn(p.n * p.bs, dtype=torch.float64, device="cuda:0")
+    z = torch.empty_like(r)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    dd.dd_trsv_apply(h, r, z)
+    ev[0].record()
+    for _ in range(args.applies):
+        dd.dd_trsv_apply(h, r, z)
+    ev[1].record()
+    torch.cuda.synchronize()
+    us = 1e3 * ev[0].elapsed_time(ev[1]) / args.applies
+    b = torch.as_tensor(p.b, device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, info = dd.bicgstab_solve(h, b, rtol=args.rtol, maxit=args.maxit)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    out = {"workload": args.workload, "block_rows": p.n, "blocks": p.nnzb, "bs": p.bs,
+           "part_rows": inf["S"], "n_subdomains": inf["nsub"], "dropped_blocks": p.nnzb - inf["nnzb_dropped"],
+           "max_levels": list(inf["max_levels"]), "partition_s": round(t_part, 3),
+           "setup_s": round(t_setup, 3), "apply_us": round(us, 2), "apply_bytes": nbytes,
+           "apply_GB/s": round(nbytes / us / 1e3, 1),
+           "bicgstab": {"iters": info["iters"], "status": info["status"], "solve_s": round(t_solve, 4),
+                        "rel_res_true": info["rel_res_true"]}}
+    log(f"graph partition {t_part:.3f} s, setup {t_setup:.3f} s, apply {us:.1f} us "
+        f"({nbytes / us / 1e3:.1f} GB/s), BiCGSTAB {info['iters']} it {t_solve:.3f} s")
+    h.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,11 +289,12 @@ def main():
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--cpu-applies", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="full", choices=["full", "kernels", "ablation", "rocsparse"],
+    ap.add_argument("--mode", default="full", choices=["full", "kernels", "ablation", "rocsparse", "graph"],
                     help="kernels: only a copy kernel of known size and bursts of applies "
                          "(the short program the rocprofv3 counter runs profile); "
                          "ablation: the FP64 apply kernel variants, timed on the same factors; "
-                         "rocsparse: rocSPARSE's block ILU0 apply on the decomposed and the full matrix")
+                         "rocsparse: rocSPARSE's block ILU0 apply on the decomposed and the full matrix; "
+                         "graph: graph partition, apply and solve of a workload without geometry")
     ap.add_argument("--applies", type=int, default=10)
     args = ap.parse_args()
 
@@ -283,6 +327,9 @@ def main():
         lic_params = torch.as_tensor(load_params(lic_path)[0], device=dev)
     log(f"device: {n_cu} CUs, {lds} B LDS per workgroup; n={p.n} nnzb={p.nnzb}")
 
+    if args.mode == "graph":
+        graph_mode(args, p, ptr_d, col_d, val_d, dd, torch)
+        return
     if args.mode == "kernels":
         kernels_only(args, p, sub, ptr_d, col_d, val_d, dd, torch)
         return

@@ -40,7 +40,9 @@ __global__ void k_gp_vmin(int64_t n, const int32_t *label, const int32_t *segk, 
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     const int32_t b = label[v];
-    if (segk[b] > 1) atomicMin(&src[b], (int32_t)v);
+    // the plain read skips the atomic once a smaller vertex is in (a stale
+    // read only costs an atomic that does not change the minimum)
+    if (segk[b] > 1 && (int32_t)v < src[b]) atomicMin(&src[b], (int32_t)v);
 }
 
 __global__ void k_gp_src(int64_t n, const int32_t *label, const int32_t *segk, const int32_t *src,
@@ -75,7 +77,8 @@ __global__ void k_gp_far(int64_t n, const int32_t *label, const int32_t *segk, c
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n || dist[v] == kInf) return;
     const int32_t b = label[v];
-    if (segk[b] > 1) atomicMax(&far[b], ((unsigned long long)dist[v] << 32) | (unsigned long long)(~(uint32_t)v));
+    const unsigned long long key = ((unsigned long long)dist[v] << 32) | (unsigned long long)(~(uint32_t)v);
+    if (segk[b] > 1 && key > far[b]) atomicMax(&far[b], key);
 }
 
 __global__ void k_gp_far_src(int32_t nparts, const int32_t *segk, const unsigned long long *far, int32_t *src) {

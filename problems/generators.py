@@ -272,6 +272,8 @@ WORKLOADS = {
     "aniso160_bsr3": (lognormal_problem,
                       dict(nx=160, ny=160, nz=160, seed=5, aniso=(1.0, 1.0, 100.0),
                            name="aniso"), None),
+    # unstructured stand-in (random points, 6 nearest neighbours, random numbering), 2,048,000 block rows
+    "unstructured2m_bsr3": (unstructured_problem, dict(n=2_048_000, seed=21, bs=3), None),
     # unseen evaluation problems for the learned correction, 128^3
     "lognormal128_eval": (lognormal_problem, dict(nx=128, ny=128, nz=128, seed=2000), None),
 }
