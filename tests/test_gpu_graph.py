@@ -126,3 +126,31 @@ def test_rejects_indivisible_and_bad_columns():
     with pytest.raises(dd.DDError, match="column index"):
         dd.dd_partition(8, 8, 8, 1, torch.as_tensor(q.brow_ptr, device="cuda"), qcol,
                         torch.as_tensor(q.val.reshape(-1), device="cuda"), sub=(4, 4, 4))
+
+
+def test_learned_correction_on_graph_partition():
+    """The learned correction needs no geometry: faces, features and the
+    corrected apply on a graph partition match the oracle's (a 7-point
+    log-normal operator, whose rows fit the slot layout the correction
+    requires, partitioned as a graph)."""
+    from problems import lic_init_params, lognormal_problem
+    p = lognormal_problem(16, 12, 8, seed=41, sigma=1.5, corr_len=3.0)
+    s = DDSolver.from_problem(p, graph_part_rows=192)
+    st = O.setup_graph(p, 192)
+    L = O.LicOracle(st)
+    dd.lic_setup(s.h)
+    fI, fJ, X = dd.lic_get_faces(s.h)
+    assert np.array_equal(np_(fI), L.faces[0]) and np.array_equal(np_(fJ), L.faces[1])
+    assert np.allclose(np_(X), L.X, rtol=1e-6, atol=1e-7)
+    P = lic_init_params(3)
+    P[5952:] = np.random.default_rng(3).standard_normal(585) * 0.05
+    Co = L.coeffs(P).astype(np.float32)
+    dd.lic_set_coeffs(s.h, torch.as_tensor(Co, device="cuda"))
+    try:
+        r = np.random.default_rng(8).standard_normal(p.n * 3)
+        zg = np_(s.apply(torch.as_tensor(r, device="cuda")))
+    finally:
+        dd.lic_set_coeffs(s.h, None)
+        s.close()
+    zo = L.apply(Co.astype(np.float64), r)
+    assert np.linalg.norm(zg - zo) / np.linalg.norm(zo) < 1e-12
