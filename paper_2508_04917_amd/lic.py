@@ -162,6 +162,7 @@ def main(argv=None):
     e.add_argument("--seeds", type=int, nargs="+", default=[2000, 2001, 2002, 2003])
     e.add_argument("--sigma", type=float, default=2.0)
     e.add_argument("--no-global", action="store_true")
+    e.add_argument("--workload", default=None, help="a named workload (problems.WORKLOADS) instead of --n/--seeds")
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
     if args.cmd == "train":
@@ -169,8 +170,13 @@ def main(argv=None):
                              nval=args.val, out=args.out)
         print(json.dumps(meta))
     else:
-        from problems import lognormal_problem
+        from problems import lognormal_problem, make_workload
         params, meta = load_params(args.params)
+        if args.workload:
+            res = evaluate(params, make_workload(args.workload), with_global=not args.no_global)
+            res["workload"] = args.workload
+            print(json.dumps(res), flush=True)
+            return
         for seed in args.seeds:
             p = lognormal_problem(args.n, args.n, args.n, seed=seed, sigma=args.sigma)
             res = evaluate(params, p, with_global=not args.no_global)
