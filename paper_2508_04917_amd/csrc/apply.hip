@@ -153,6 +153,42 @@ __device__ __forceinline__ void store_slice(double *__restrict__ zs, const TC *_
 // The sweeps are shared with the ablation variants below.  VC selects the
 // vertex-centric mapping (one thread per block row, all BS components)
 // instead of BS lanes per row.
+// acc[i] -= sum over the row's blocks b in [b0, b1) of block_b row (c0 + i)
+// . y_{col b}, blocks in ascending order (the oracle's order).  The blocks
+// come kRowChunk at a time with every load of a chunk issued before any is
+// used: positions past the row's end re-read its last block and contribute a
+// zero (a select, not a branch, so no load is sunk behind a condition), so a
+// row costs one memory round trip per chunk instead of one per block.
+constexpr int kRowChunk = 4;
+
+template <int BS, typename TS, typename TC, int NC>
+__device__ __forceinline__ void row_blocks(TC (&acc)[NC], const TC *__restrict__ y, int32_t b0, int32_t b1,
+                                           const uint16_t *__restrict__ col, const TS *__restrict__ val, int c0) {
+    constexpr int BB = BS * BS;
+    for (int32_t bb = b0; bb < b1; bb += kRowChunk) {
+        int J[kRowChunk];
+        TS v[kRowChunk][NC][BS];
+#pragma unroll
+        for (int k = 0; k < kRowChunk; ++k) {
+            const int32_t b = min(bb + k, b1 - 1);
+            J[k] = col[b];
+#pragma unroll
+            for (int i = 0; i < NC; ++i)
+#pragma unroll
+                for (int d = 0; d < BS; ++d) v[k][i][d] = val[(int64_t)b * BB + (c0 + i) * BS + d];
+        }
+#pragma unroll
+        for (int k = 0; k < kRowChunk; ++k) {
+            const bool in = bb + k < b1;
+#pragma unroll
+            for (int i = 0; i < NC; ++i)
+#pragma unroll
+                for (int d = 0; d < BS; ++d)
+                    acc[i] -= (in ? static_cast<TC>(v[k][i][d]) : TC(0)) * y[J[k] * BS + d];
+        }
+    }
+}
+
 template <int NT, bool VC, int BS>
 struct RowMap {
     static constexpr int RPW = kWave / BS;                     // block rows per wavefront (lane mapping)
@@ -173,7 +209,6 @@ __device__ __forceinline__ void plain_lower(TC *__restrict__ y, int64_t base, in
                                             const int32_t *__restrict__ Llp, const uint16_t *__restrict__ Lrow,
                                             const int32_t *__restrict__ Lbp, const uint16_t *__restrict__ Lcol,
                                             const TS *__restrict__ Lval) {
-    constexpr int BB = BS * BS;
     const RowMap<NT, VC, BS> m;
     const int32_t o = Loff[s];
     const int nl = Loff[s + 1] - o - 1;
@@ -189,26 +224,14 @@ __device__ __forceinline__ void plain_lower(TC *__restrict__ y, int64_t base, in
                     TC acc[BS];
 #pragma unroll
                     for (int c = 0; c < BS; ++c) acc[c] = y[I * BS + c];
-                    for (int32_t b = Lbp[gp]; b < b1; ++b) {
-                        const int J = Lcol[b];
-                        const TS *blk = Lval + (int64_t)b * BB;
-#pragma unroll
-                        for (int c = 0; c < BS; ++c)
-#pragma unroll
-                            for (int d = 0; d < BS; ++d) acc[c] -= static_cast<TC>(blk[c * BS + d]) * y[J * BS + d];
-                    }
+                    row_blocks<BS, TS, TC, BS>(acc, y, Lbp[gp], b1, Lcol, Lval, 0);
 #pragma unroll
                     for (int c = 0; c < BS; ++c) y[I * BS + c] = acc[c];
                 } else {
                     const int c = m.c;
-                    TC acc = y[I * BS + c];
-                    for (int32_t b = Lbp[gp]; b < b1; ++b) {
-                        const int J = Lcol[b];
-                        const TS *blk = Lval + (int64_t)b * BB + c * BS;
-#pragma unroll
-                        for (int d = 0; d < BS; ++d) acc -= static_cast<TC>(blk[d]) * y[J * BS + d];
-                    }
-                    y[I * BS + c] = acc;
+                    TC acc[1] = {y[I * BS + c]};
+                    row_blocks<BS, TS, TC, 1>(acc, y, Lbp[gp], b1, Lcol, Lval, c);
+                    y[I * BS + c] = acc[0];
                 }
             }
         }
@@ -249,36 +272,24 @@ __device__ __forceinline__ void plain_upper(TC *__restrict__ y, int64_t base, in
                             acc[c] = y[I * BS + c];
                         }
                     }
-                    for (int32_t b = Ubp[gp]; b < b1; ++b) {
-                        const int K = Ucol[b];
-                        const TS *blk = Uval + (int64_t)b * BB;
-#pragma unroll
-                        for (int c = 0; c < BS; ++c)
-#pragma unroll
-                            for (int d = 0; d < BS; ++d) acc[c] -= static_cast<TC>(blk[c * BS + d]) * y[K * BS + d];
-                    }
+                    row_blocks<BS, TS, TC, BS>(acc, y, Ubp[gp], b1, Ucol, Uval, 0);
 #pragma unroll
                     for (int c = 0; c < BS; ++c) y[I * BS + c] = acc[c];
                 } else {
                     const int c = m.c;
-                    TC acc;
+                    TC acc[1];
                     if constexpr (SCALE) {
                         const TS *dblk = Dval + gp * BB + c * BS;
-                        acc = 0;
+                        acc[0] = 0;
 #pragma unroll
-                        for (int d = 0; d < BS; ++d) acc += static_cast<TC>(dblk[d]) * y[I * BS + d];
+                        for (int d = 0; d < BS; ++d) acc[0] += static_cast<TC>(dblk[d]) * y[I * BS + d];
                     } else {
-                        acc = y[I * BS + c];
+                        acc[0] = y[I * BS + c];
                     }
-                    for (int32_t b = Ubp[gp]; b < b1; ++b) {
-                        const int K = Ucol[b];
-                        const TS *blk = Uval + (int64_t)b * BB + c * BS;
-#pragma unroll
-                        for (int d = 0; d < BS; ++d) acc -= static_cast<TC>(blk[d]) * y[K * BS + d];
-                    }
+                    row_blocks<BS, TS, TC, 1>(acc, y, Ubp[gp], b1, Ucol, Uval, c);
                     // every lane of this row has read y_I above (same wavefront)
                     __asm__ volatile("" ::: "memory");
-                    y[I * BS + c] = acc;
+                    y[I * BS + c] = acc[0];
                 }
             }
         }
@@ -906,22 +917,16 @@ __global__ __launch_bounds__(NT) void k_abl_ilu0(
             const bool row = m.ok && p < p1;
             const int64_t gp = base + p;
             int I = 0;
-            double acc = 0;
+            double acc[1] = {0.0};
             if (row) {
                 I = Urow[gp];
-                acc = y[I * BS + m.c];
-                const int32_t b1 = Ubp[gp + 1];
-                for (int32_t b = Ubp[gp]; b < b1; ++b) {
-                    const int K = Ucol[b];
-                    const double *blk = Uraw + (int64_t)b * BB + m.c * BS;
-#pragma unroll
-                    for (int d = 0; d < BS; ++d) acc -= blk[d] * y[K * BS + d];
-                }
+                acc[0] = y[I * BS + m.c];
+                row_blocks<BS, double, double, 1>(acc, y, Ubp[gp], Ubp[gp + 1], Ucol, Uraw, m.c);
             }
             // the row's BS sums, from its BS consecutive lanes (all lanes take part)
             double sum[BS];
 #pragma unroll
-            for (int d = 0; d < BS; ++d) sum[d] = __shfl(acc, lane - m.c + d);
+            for (int d = 0; d < BS; ++d) sum[d] = __shfl(acc[0], lane - m.c + d);
             if (row) {
                 const double *inv = Dval + gp * BB + m.c * BS;
                 double zc = 0;
