@@ -71,7 +71,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+            raise ImportError(f"{LIB_PATH} is not built (run python -m paper_2508_04917_amd.build)")
         L = C.CDLL(LIB_PATH)
         vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         sig = {
