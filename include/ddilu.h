@@ -240,13 +240,13 @@ int bicgstab_solve(dd_handle h, const double *b, double *x, double rtol,
                    int32_t maxit, void *hip_stream, dd_solve_info *info);
 
 /* Choose the kernel dd_trsv_apply (and bicgstab_solve) uses; all compute the
- * same z up to rounding order.  0 = automatic (the fastest one the handle's
- * shape allows), 1 = plain level loop (levels of any width), 2 = level loop
- * with the next level's blocks prefetched into registers (levels no wider
- * than one workgroup pass), 3 = fixed per-row block slots so that no load
- * depends on another and later levels' loads are issued while a level
- * computes (rows of at most 3 off-diagonal blocks per sweep, levels no wider
- * than one pass).  A variant the shape does not allow falls back to 1.
+ * same z up to rounding order.  0 = automatic (3 where the handle's shape
+ * allows it, else 1), 1 = plain level loop (a row's blocks loaded four at a
+ * time), 2 = level loop in workgroup-pass chunks with the next chunk's
+ * blocks prefetched into registers, 3 = fixed per-row block slots so that
+ * no load depends on another and later levels' loads are issued while a
+ * level computes (rows of at most 3 off-diagonal blocks per sweep, levels no
+ * wider than one pass).  A variant the shape does not allow falls back to 1.
  *
  * 4-8 are ablations of the plain level loop (1), each changing one thing,
  * after the kernel variants of Section 5.2 (Tables 3-4): 4 = lower sweep

@@ -321,13 +321,16 @@ __global__ __launch_bounds__(NT) void k_dd_apply(
 }
 
 // ------------------------------------------------------------------------
-// Variant 2: levels no wider than one workgroup pass, rows in the CSR
-// layout.  The factor data of a level does not depend on the solve, so it is
-// fetched ahead: while level l computes from LDS, the blocks of level l+1 are
-// in flight into registers and the row metadata of level l+2 behind them.
-// The level barrier only orders LDS traffic, so HBM latency overlaps the
-// level chain.  Rows with more than MB blocks take the extra blocks through a
-// direct (unpipelined) loop.
+// Variant 2: rows in the CSR layout, levels of any width.  A sweep is a
+// sequence of chunks — one workgroup pass of one level — with a barrier
+// after the last chunk of each level only (the rows of a level are
+// independent).  The factor data of a chunk does not depend on the solve,
+// so it is fetched ahead: while chunk k computes from LDS, the blocks of
+// chunk k+1 are in flight into registers and the row metadata of chunk k+2
+// behind them.  The first MB blocks of a row are fetched without branches
+// (positions past the row's end re-read its last block and contribute a
+// zero through a select); rows with more blocks take the rest through a
+// direct loop.
 template <int BS, typename TS, int MB>
 struct LevelRegs {
     bool ok;
@@ -354,20 +357,16 @@ __device__ __forceinline__ void csr_fetch(LevelRegs<BS, TS, MB> &R, const LevelM
     R.nb = m.nb;
 #pragma unroll
     for (int k = 0; k < MB; ++k) {
-        if (k < R.nb) {
-            const int64_t b = R.b0 + k;
-            R.J[k] = col[b];
-            const TS *blk = val + b * BB + c * BS;
+        const int64_t b = R.nb > 0 ? R.b0 + min(k, R.nb - 1) : 0;  // always a valid block
+        R.J[k] = col[b];
+        const TS *blk = val + b * BB + c * BS;
 #pragma unroll
-            for (int d = 0; d < BS; ++d) R.v[k][d] = blk[d];
-        }
+        for (int d = 0; d < BS; ++d) R.v[k][d] = blk[d];
     }
     if constexpr (UPPER) {
-        if (m.ok) {
-            const TS *dblk = dval + m.gp * BB + c * BS;
+        const TS *dblk = dval + (m.ok ? m.gp : 0) * BB + c * BS;
 #pragma unroll
-            for (int d = 0; d < BS; ++d) R.d[d] = dblk[d];
-        }
+        for (int d = 0; d < BS; ++d) R.d[d] = dblk[d];
     }
 }
 
@@ -387,11 +386,10 @@ __device__ __forceinline__ void csr_compute(TC *__restrict__ y, const LevelRegs<
     }
 #pragma unroll
     for (int k = 0; k < MB; ++k) {
-        if (k < R.nb) {
-            const int J = R.J[k];
+        const bool in = k < R.nb;
+        const int J = R.J[k];
 #pragma unroll
-            for (int d = 0; d < BS; ++d) acc -= static_cast<TC>(R.v[k][d]) * y[J * BS + d];
-        }
+        for (int d = 0; d < BS; ++d) acc -= (in ? static_cast<TC>(R.v[k][d]) : TC(0)) * y[J * BS + d];
     }
     for (int k = MB; k < R.nb; ++k) {  // rows longer than the register window
         const int64_t b = R.b0 + k;
@@ -405,20 +403,36 @@ __device__ __forceinline__ void csr_compute(TC *__restrict__ y, const LevelRegs<
     y[I * BS + c] = acc;
 }
 
+// Position of a chunk: level l, first position pb of the pass, level end p1.
+struct Chunk {
+    int l;
+    int32_t pb, p1;
+};
+
 template <int BS, typename TS, typename TC, int MB, bool UPPER>
 __device__ __forceinline__ void sweep_csr(TC *__restrict__ y, int64_t base, int s, const int32_t *__restrict__ off,
                                           const int32_t *__restrict__ lp, const uint16_t *__restrict__ prow,
                                           const int32_t *__restrict__ bp, const uint16_t *__restrict__ col,
                                           const TS *__restrict__ val, const TS *__restrict__ dval, int slot,
-                                          bool lane_ok, int c) {
+                                          bool lane_ok, int c, int rpp) {
     const int32_t o = off[s];
     const int nl = off[s + 1] - o - 1;
     if (nl <= 0) return;
-    auto meta = [&](int l) -> LevelMeta {
+    auto next = [&](Chunk k) -> Chunk {
+        k.pb += rpp;
+        if (k.pb >= k.p1) {
+            ++k.l;
+            if (k.l < nl) {
+                k.pb = lp[o + k.l];
+                k.p1 = lp[o + k.l + 1];
+            }
+        }
+        return k;
+    };
+    auto meta = [&](const Chunk &k) -> LevelMeta {
         LevelMeta m;
-        const int32_t p0 = lp[o + l], p1 = lp[o + l + 1];
-        const int32_t p = p0 + slot;
-        m.ok = lane_ok && p < p1;
+        const int32_t p = k.pb + slot;
+        m.ok = lane_ok && k.l < nl && p < k.p1;
         m.gp = base + p;
         if (m.ok) {
             m.I = prow[m.gp];
@@ -431,25 +445,30 @@ __device__ __forceinline__ void sweep_csr(TC *__restrict__ y, int64_t base, int 
         }
         return m;
     };
+    auto last_of_level = [&](const Chunk &k) { return k.pb + rpp >= k.p1; };
     // Two register sets alternate between "being computed" and "being
     // filled"; the loop is unrolled by two so that neither is copied (a copy
     // of a register with a load in flight would wait for the load).
     LevelRegs<BS, TS, MB> A, B;
-    LevelMeta mA = meta(0);
+    Chunk kA{0, lp[o], lp[o + 1]};
+    LevelMeta mA = meta(kA);
     csr_fetch<BS, TS, MB, UPPER>(A, mA, col, val, dval, c);
-    LevelMeta mB;
-    mB.ok = false;
-    if (nl > 1) mB = meta(1);
-    for (int l = 0; l < nl; l += 2) {
-        if (l + 1 < nl) csr_fetch<BS, TS, MB, UPPER>(B, mB, col, val, dval, c);
-        if (l + 2 < nl) mA = meta(l + 2);
+    Chunk kB = next(kA);
+    LevelMeta mB = meta(kB);
+    while (kA.l < nl) {
+        if (kB.l < nl) csr_fetch<BS, TS, MB, UPPER>(B, mB, col, val, dval, c);
+        const Chunk kA2 = next(kB);
+        if (kA2.l < nl) mA = meta(kA2);
         csr_compute<BS, TS, TC, MB, UPPER>(y, A, col, val, c);
-        __syncthreads();
-        if (l + 1 >= nl) break;
-        if (l + 2 < nl) csr_fetch<BS, TS, MB, UPPER>(A, mA, col, val, dval, c);
-        if (l + 3 < nl) mB = meta(l + 3);
+        if (last_of_level(kA)) __syncthreads();
+        if (kB.l >= nl) break;
+        if (kA2.l < nl) csr_fetch<BS, TS, MB, UPPER>(A, mA, col, val, dval, c);
+        const Chunk kB2 = next(kA2);
+        if (kB2.l < nl) mB = meta(kB2);
         csr_compute<BS, TS, TC, MB, UPPER>(y, B, col, val, c);
-        __syncthreads();
+        if (last_of_level(kB)) __syncthreads();
+        kA = kA2;
+        kB = kB2;
     }
 }
 
@@ -476,8 +495,9 @@ __global__ __launch_bounds__(NT) void k_dd_apply_pipe(
     const double *rs = r + base * BS;
     load_slice<TC>(y, rs, S * BS, tid, NT);
     __syncthreads();
-    sweep_csr<BS, TS, TC, MB, false>(y, base, s, Loff, Llp, Lrow, Lbp, Lcol, Lval, nullptr, slot, lane_ok, c);
-    sweep_csr<BS, TS, TC, MB, true>(y, base, s, Uoff, Ulp, Urow, Ubp, Ucol, Uval, Dval, slot, lane_ok, c);
+    constexpr int RPP = RPW * (NT / kWave);
+    sweep_csr<BS, TS, TC, MB, false>(y, base, s, Loff, Llp, Lrow, Lbp, Lcol, Lval, nullptr, slot, lane_ok, c, RPP);
+    sweep_csr<BS, TS, TC, MB, true>(y, base, s, Uoff, Ulp, Urow, Ubp, Ucol, Uval, Dval, slot, lane_ok, c, RPP);
     double *zs = z + base * BS;
     store_slice<TC>(zs, y, S * BS, tid, NT);
 }
@@ -1191,9 +1211,12 @@ static hipError_t launch_typed(dd_ctx *h, const double *r, double *z, const int3
             return launch_ablation<BS, NT>(h, variant, r, z, state, st);
         return hipErrorInvalidValue;  // rejected by the API before launch
     }
-    if (variant == 0) variant = h->slots ? 3 : 2;
+    // automatic: the slot kernel where the shape allows it, else the plain
+    // loop (measured faster than the pipelined one on rows of up to 17
+    // blocks: 438 against 730 us at 2M unstructured rows)
+    if (variant == 0) variant = 3;
     if (variant == 3 && (!one_pass || !h->slots)) variant = 1;
-    if (variant == 2 && (!one_pass || lic)) variant = 1;
+    if (variant == 2 && lic) variant = 1;  // the correction runs in 1 and 3
     if (variant == 3) {
         const TS *lv, *uv, *dv;
         factor_ptrs<TS>(h, true, &lv, &uv, &dv);

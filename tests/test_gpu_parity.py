@@ -93,8 +93,9 @@ def test_factors_fp64(name):
     assert np.linalg.norm(fg - fo) / np.linalg.norm(fo) < RTOL_FP64
 
 
-# apply kernels: 1 plain level loop, 2 prefetch a level ahead (row offsets),
-# 3 fixed block slots with loads two levels ahead (0 = automatic choice)
+# apply kernels: 1 plain level loop, 2 workgroup-pass chunks with the next
+# chunk prefetched (row offsets), 3 fixed block slots with loads issued
+# levels ahead (0 = automatic choice)
 VARIANTS = (0, 1, 2, 3)
 
 
