@@ -54,7 +54,10 @@ def prepare_problem(p, sub, nq, probe_seed):
 
 
 def train(nprob=256, epochs=10, nq=16, n=48, sub=(16, 16, 16), lr=1e-3, init_seed=0, order_seed=1,
-          first_seed=1000, nval=4, first_val_seed=1900, out=None):
+          first_seed=1000, nval=4, first_val_seed=1900, out=None, lr_final=None):
+    """Adam over the training problems, one step per problem, epochs in a
+    seeded order; the learning rate decays geometrically from lr to lr_final
+    over the epochs (constant when lr_final is None)."""
     from problems import lic_init_params, training_order, training_problem
     probs = []
     t0 = time.time()
@@ -79,13 +82,15 @@ def train(nprob=256, epochs=10, nq=16, n=48, sub=(16, 16, 16), lr=1e-3, init_see
     hist, vhist, meta = [], [], {}
     t1 = time.time()
     for ep in range(epochs):
+        lr_ep = lr if lr_final is None or epochs == 1 else lr * (lr_final / lr) ** (ep / (epochs - 1))
         h = dd.lic_train([q[0].h for q in probs], [q[1] for q in probs], [q[2] for q in probs],
-                         [q[3] for q in probs], params, m, v, 1, order[ep:ep + 1], lr=lr, step0=ep * nprob)
+                         [q[3] for q in probs], params, m, v, 1, order[ep:ep + 1], lr=lr_ep, step0=ep * nprob)
         hist.append(float(h[0]))
         vhist.append(val_loss(params))
         _log(f"epoch {ep + 1}/{epochs}: mean loss {hist[-1]:.4f}, held-out {vhist[-1]:.4f} "
              f"({time.time() - t1:.1f}s)")
         meta = {"nprob": nprob, "epochs": ep + 1, "nq": nq, "grid": n, "subdomain": list(sub), "lr": lr,
+                "lr_final": lr_final,
                 "init_seed": init_seed, "order_seed": order_seed, "first_seed": first_seed,
                 "loss_history": hist, "val_seeds": [first_val_seed, first_val_seed + nval - 1],
                 "val_loss_history": vhist, "train_seconds": time.time() - t1}
@@ -154,6 +159,7 @@ def main(argv=None):
     t.add_argument("--probes", type=int, default=16)
     t.add_argument("--grid", type=int, default=48)
     t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--lr-final", type=float, default=None)
     t.add_argument("--val", type=int, default=4)
     t.add_argument("--out", default=DEFAULT_PARAMS)
     e = sp.add_parser("eval")
@@ -167,7 +173,7 @@ def main(argv=None):
     torch.cuda.set_device(0)
     if args.cmd == "train":
         params, meta = train(nprob=args.problems, epochs=args.epochs, nq=args.probes, n=args.grid, lr=args.lr,
-                             nval=args.val, out=args.out)
+                             nval=args.val, out=args.out, lr_final=args.lr_final)
         print(json.dumps(meta))
     else:
         from problems import lognormal_problem, make_workload
