@@ -160,7 +160,7 @@ __device__ __forceinline__ void store_slice(double *__restrict__ zs, const TC *_
 // used: positions past the row's end re-read its last block and contribute a
 // zero (a select, not a branch, so no load is sunk behind a condition), so a
 // row costs one memory round trip per chunk instead of one per block.
-constexpr int kRowChunk = 4;
+constexpr int kRowChunk = 4;  // 8 measured slower (more re-read positions on short rows)
 
 template <int BS, typename TS, typename TC, int NC>
 __device__ __forceinline__ void row_blocks(TC (&acc)[NC], const TC *__restrict__ y, int32_t b0, int32_t b1,
