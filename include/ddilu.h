@@ -81,8 +81,13 @@ typedef struct {
     int32_t bs;                /* 1 or 3                                  */
     int32_t part_rows;         /* rows per subdomain S (n % S == 0), or 0:
                                   the largest divisor of n whose vector
-                                  (S*bs*8 bytes) fits the LDS budget      */
+                                  (S*bs*8 bytes) fits the LDS budget and
+                                  that leaves at least n_cu parts (else the
+                                  largest that fits), as dd_auto_subdims
+                                  does for boxes                          */
     int64_t lds_budget_bytes;  /* LDS per workgroup, or 0 (device's)      */
+    int32_t n_cu;              /* compute units, or 0 (device's)          */
+    int32_t reserved;          /* 0                                       */
 } dd_graph_desc;
 
 /* Sizes of a handle's problem and setup products. */

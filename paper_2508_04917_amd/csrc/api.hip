@@ -177,16 +177,25 @@ extern "C" int dd_partition_graph(const dd_graph_desc *d, const int32_t *brow_pt
     if (nnzb < n || nnzb >= ((int64_t)1 << 31))
         return set_global_error(DD_EINVAL, "dd_partition_graph: bad nnzb %lld", (long long)nnzb);
     int64_t lds = d->lds_budget_bytes;
-    if (lds <= 0) {
+    int32_t n_cu = d->n_cu;
+    if (lds <= 0 || n_cu <= 0) {
         int32_t c;
-        int rc = dd_device_caps(&c, &lds);
+        int64_t l;
+        int rc = dd_device_caps(&c, &l);
         if (rc) return rc;
+        if (lds <= 0) lds = l;
+        if (n_cu <= 0) n_cu = c;
     }
     int64_t S = d->part_rows;
-    if (S == 0) {  // the largest divisor of n whose vector fits the LDS budget
+    if (S == 0) {  // largest divisor of n that fits the LDS, preferring at least n_cu parts
         const int64_t cap = std::min<int64_t>(65535, lds / (8 * d->bs));
-        for (int64_t c = std::min(cap, n); c >= 1 && S == 0; --c)
-            if (n % c == 0) S = c;
+        int64_t fit = 0, full = 0;
+        for (int64_t c = std::min(cap, n); c >= 1 && full == 0; --c) {
+            if (n % c) continue;
+            if (fit == 0) fit = c;
+            if (n / c >= n_cu) full = c;
+        }
+        S = full ? full : fit;
     }
     if (S <= 0 || n % S)
         return set_global_error(DD_ENOTDIV, "dd_partition_graph: %lld block rows not divisible by part_rows %lld",

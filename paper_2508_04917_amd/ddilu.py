@@ -44,7 +44,7 @@ class PartitionDesc(C.Structure):
 
 class GraphDesc(C.Structure):
     _fields_ = [("n", C.c_int64), ("bs", C.c_int32), ("part_rows", C.c_int32),
-                ("lds_budget_bytes", C.c_int64)]
+                ("lds_budget_bytes", C.c_int64), ("n_cu", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -196,7 +196,8 @@ def dd_partition(nx, ny, nz, bs, brow_ptr, bcol, val, sub=(0, 0, 0), n_cu=0, lds
     return Handle(out.value)
 
 
-def dd_partition_graph(n, bs, brow_ptr, bcol, val, part_rows=0, lds_budget_bytes=0, stream=None) -> Handle:
+def dd_partition_graph(n, bs, brow_ptr, bcol, val, part_rows=0, lds_budget_bytes=0, n_cu=0,
+                       stream=None) -> Handle:
     """Partition a matrix graph without geometry (recursive BFS bisection
     into parts of part_rows vertices; 0 = largest divisor of n that fits the
     LDS), then reorder as dd_partition does."""
@@ -204,7 +205,7 @@ def dd_partition_graph(n, bs, brow_ptr, bcol, val, part_rows=0, lds_budget_bytes
     _dev_check(brow_ptr, torch.int32, n + 1, "brow_ptr")
     _dev_check(bcol, torch.int32, nnzb, "bcol")
     _dev_check(val, torch.float64, nnzb * bs * bs, "val")
-    d = GraphDesc(n, bs, part_rows, lds_budget_bytes)
+    d = GraphDesc(n, bs, part_rows, lds_budget_bytes, n_cu, 0)
     out = C.c_void_p(None)
     _check(lib().dd_partition_graph(C.byref(d), _ptr(brow_ptr), _ptr(bcol), _ptr(val), nnzb, _stream(stream),
                                     C.byref(out)))

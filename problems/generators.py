@@ -274,6 +274,8 @@ WORKLOADS = {
                            name="aniso"), None),
     # unstructured stand-in (random points, 6 nearest neighbours, random numbering), 2,048,000 block rows
     "unstructured2m_bsr3": (unstructured_problem, dict(n=2_048_000, seed=21, bs=3), None),
+    # the scalar (1x1) counterpart: the CSR path on an unstructured graph, 4,096,000 rows
+    "unstructured4m_scalar": (unstructured_problem, dict(n=4_096_000, seed=22, bs=1), None),
     # unseen evaluation problems for the learned correction, 128^3
     "lognormal128_eval": (lognormal_problem, dict(nx=128, ny=128, nz=128, seed=2000), None),
 }

@@ -154,3 +154,18 @@ def test_learned_correction_on_graph_partition():
         s.close()
     zo = L.apply(Co.astype(np.float64), r)
     assert np.linalg.norm(zg - zo) / np.linalg.norm(zo) < 1e-12
+
+
+def test_automatic_part_size():
+    """part_rows = 0: the largest divisor of n whose vector fits the LDS and
+    that leaves at least n_cu parts, else the largest that fits."""
+    p = unstructured_problem(64000, seed=16, bs=1)
+    ptr = torch.as_tensor(p.brow_ptr, device="cuda")
+    col = torch.as_tensor(p.bcol, device="cuda")
+    val = torch.as_tensor(p.val.reshape(-1), device="cuda")
+    for n_cu, lds, S in ((8, 163840, 8000), (2, 163840, 16000), (4, 80000, 8000), (1000, 163840, 64)):
+        h = dd.dd_partition_graph(p.n, 1, ptr, col, val, part_rows=0, lds_budget_bytes=lds, n_cu=n_cu)
+        try:
+            assert dd.dd_get_info(h)["S"] == S, (n_cu, lds)
+        finally:
+            h.close()
