@@ -25,6 +25,7 @@ CASES = {
     "laplacian16_scalar": (lambda: laplacian_scalar(16, 16, 16, seed=1), 512),
     "unstructured_one_part": (lambda: unstructured_problem(900, seed=13, bs=3), 900),
     "unstructured_odd_parts": (lambda: unstructured_problem(7 * 300, seed=14, bs=3), 300),
+    "unstructured_jacobi": (lambda: unstructured_problem(240, seed=17, bs=3), 1),
 }
 
 _cache = {}
@@ -107,6 +108,21 @@ def test_bicgstab(name):
     print(f"[graph {name}] iterations GPU {info['iters']}, oracle {ref.iters}", flush=True)
     assert info["status"] == 0 and info["rel_res_true"] <= 2e-8
     assert abs(info["iters"] - ref.iters) <= max(3, ref.iters // 7)
+
+
+def test_isolated_vertices_match_oracle():
+    n, S = 48, 4
+    ptr = np.arange(n + 1, dtype=np.int32)
+    col = np.arange(n, dtype=np.int32)
+    val = np.full(n, 2.0)
+    s = DDSolver(n, 1, 1, 1, ptr, col, val, graph_part_rows=S)
+    try:
+        pid, _, _ = dd.dd_get_partition(s.h)
+        assert np.array_equal(np_(pid), O.graph_partition(n, ptr, col, S))
+        r = torch.as_tensor(np.arange(n, dtype=np.float64), device="cuda")
+        assert np.allclose(np_(s.apply(r)), np.arange(n) / 2.0, rtol=0, atol=1e-15)
+    finally:
+        s.close()
 
 
 def test_rejects_indivisible_and_bad_columns():

@@ -97,3 +97,26 @@ def test_setup_graph_apply_inverts_factors():
     z2 = O.apply_ilu0(p.n, 3, st.tptr, st.tcol, st.lu, r)
     assert np.linalg.norm(z - z2) / np.linalg.norm(z) < 1e-12
     assert np.array_equal(np.bincount(st.part_id), np.full(10, 200))
+
+
+def test_isolated_vertices_give_index_ranges():
+    """No couplings at all (a block-diagonal matrix): every BFS reaches only
+    its source, the unreached rest keeps index order, so the parts are
+    consecutive index ranges; a segment [lo, hi) of k parts gives its first
+    floor(k/2)*S vertices to its own label."""
+    n, S = 48, 4
+    ptr = np.arange(n + 1, dtype=np.int32)
+    col = np.arange(n, dtype=np.int32)
+    part = np.empty(n, dtype=np.int32)
+
+    def rec(lo, hi, b):
+        k = (hi - lo) // S
+        if k == 1:
+            part[lo:hi] = b
+            return
+        k0 = k // 2
+        rec(lo, lo + k0 * S, b)
+        rec(lo + k0 * S, hi, b + k0)
+
+    rec(0, n, 0)
+    assert np.array_equal(O.graph_partition(n, ptr, col, S), part)
