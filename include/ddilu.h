@@ -127,6 +127,9 @@ typedef struct {
     double apply_seconds;      /* summed duration of those applies (event
                                   pairs on the stream; 0 unless profiling
                                   was switched on with dd_set_profiling)  */
+    int32_t fused;             /* 1 when each apply ran in one launch with
+                                  the SpMV after it (dd_set_fusion)       */
+    int32_t reserved;
 } dd_solve_info;
 
 /* Automatic subdomain extents (host only, no device access).
@@ -270,6 +273,24 @@ int dd_set_apply_variant(dd_handle h, int32_t variant);
  * event pair on the solve's stream brackets every preconditioner apply and
  * the summed durations are reported in dd_solve_info.apply_seconds. */
 int dd_set_profiling(dd_handle h, int32_t on);
+
+/* Run each preconditioner apply of bicgstab_solve and the SpMV that
+ * follows it in Algorithm 1 (v = A M^{-1} p, t = A M^{-1} s, with their dot
+ * products) as one launch (on = 1) or as two (on = 0, the default).  The
+ * fused launch has one workgroup per subdomain for the apply and one per
+ * subdomain for that subdomain's rows of the product; a product workgroup
+ * starts once the subdomains its rows read have been applied (per-subdomain
+ * completion flags in device memory, waits bounded), so the product fills
+ * the compute units the apply's last partial round leaves idle.  It is used
+ * where the apply runs the slot kernel (variant 0 or 3 with a shape that
+ * allows it), without per-apply profiling and with the DD preconditioner;
+ * otherwise the solve uses two launches.  The result is the same up to the
+ * order in which the dot products' partial sums are grouped.
+ * dd_solve_info.fused reports which was used.  Off by default: every
+ * workgroup of the launch reserves the apply's LDS, so the product runs at
+ * one workgroup per CU, and at 160^3 (640 subdomains) a fused iteration
+ * measured 8% slower than two launches. */
+int dd_set_fusion(dd_handle h, int32_t on);
 
 /* Record the residual history of later bicgstab_solve calls on h: entry j
  * of hist (device double[len]) receives ||r_j||/||b|| after iteration j

@@ -578,6 +578,12 @@ extern "C" int dd_set_profiling(dd_handle h, int32_t on) {
     return DD_OK;
 }
 
+extern "C" int dd_set_fusion(dd_handle h, int32_t on) {
+    if (!h) return set_global_error(DD_EINVAL, "dd_set_fusion: null handle");
+    h->fuse = on ? 1 : 0;
+    return DD_OK;
+}
+
 extern "C" int dd_set_residual_history(dd_handle h, double *hist, int32_t len) {
     if (!h) return set_global_error(DD_EINVAL, "dd_set_residual_history: null handle");
     if (hist && len <= 0) return h->fail(DD_EINVAL, "dd_set_residual_history: len must be positive");

@@ -19,6 +19,7 @@
 // the type of the LDS vector and of the arithmetic (double for DD_FP64 and
 // DD_MIXED, float for DD_FP32).  Input r and output z are always FP64.
 #include "internal.h"
+#include "spmv.h"
 
 // Prefetch depth (levels loaded ahead) of the slot-layout kernel, per factor
 // storage type.  Once wavefronts without rows skip their loads, a level's
@@ -773,17 +774,16 @@ __device__ __forceinline__ void sweep_slots(TC *__restrict__ y, int64_t base, in
     for (int u = 0; u <= PD; ++u) slot_claim(R[u]);
 }
 
-template <int BS, typename TS, typename TC, int NT, int MB, int PD, bool LIC>
-__global__ __launch_bounds__(NT) void k_dd_apply_slots(
-    const double *__restrict__ r, double *__restrict__ z, int S, const int32_t *__restrict__ Loff,
-    const int32_t *__restrict__ Llp, const uint64_t *__restrict__ Ldesc, const TS *__restrict__ Lval,
-    const int32_t *__restrict__ Uoff, const int32_t *__restrict__ Ulp, const uint64_t *__restrict__ Udesc,
-    const TS *__restrict__ Uval, const int32_t *__restrict__ state, LicArgs la) {
-    if (state != nullptr && *state != 0) return;
+// One subdomain's apply with the slot layout: r's slice into LDS (plus the
+// learned correction), the lower sweep, the upper sweep with the diagonal
+// scaling, and the slice back to z.
+template <int BS, typename TS, typename TC, int MB, int PD, bool LIC>
+__device__ __forceinline__ void apply_slots_sub(
+    TC *__restrict__ y, int s, const double *__restrict__ r, double *__restrict__ z, int S,
+    const int32_t *__restrict__ Loff, const int32_t *__restrict__ Llp, const uint64_t *__restrict__ Ldesc,
+    const TS *__restrict__ Lval, const int32_t *__restrict__ Uoff, const int32_t *__restrict__ Ulp,
+    const uint64_t *__restrict__ Udesc, const TS *__restrict__ Uval, const LicArgs &la) {
     constexpr int RPW = kWave / BS;
-    extern __shared__ unsigned char dd_smem[];
-    TC *y = reinterpret_cast<TC *>(dd_smem);
-    const int s = blockIdx.x;
     const int64_t base = (int64_t)s * S;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1), wave = tid / kWave;
@@ -791,8 +791,8 @@ __global__ __launch_bounds__(NT) void k_dd_apply_slots(
     const bool lane_ok = rl < RPW;
     const int slot = wave * RPW + rl;
 
-    // the launch may use fewer threads than NT: just enough wavefronts for
-    // the widest level, so no wavefront is idle at every level
+    // the launch may use fewer threads than the kernel's bound: just enough
+    // wavefronts for the widest level, so no wavefront is idle at every level
     const int nt = blockDim.x;
     const double *rs = r + base * BS;
     load_slice<TC>(y, rs, S * BS, tid, nt);
@@ -803,6 +803,154 @@ __global__ __launch_bounds__(NT) void k_dd_apply_slots(
     sweep_slots<BS, TS, TC, MB, PD, true>(y, base, S, s, Uoff, Ulp, Udesc, Uval, slot, wrow0, lane_ok, c);
     double *zs = z + base * BS;
     store_slice<TC>(zs, y, S * BS, tid, nt);
+}
+
+template <int BS, typename TS, typename TC, int NT, int MB, int PD, bool LIC>
+__global__ __launch_bounds__(NT) void k_dd_apply_slots(
+    const double *__restrict__ r, double *__restrict__ z, int S, const int32_t *__restrict__ Loff,
+    const int32_t *__restrict__ Llp, const uint64_t *__restrict__ Ldesc, const TS *__restrict__ Lval,
+    const int32_t *__restrict__ Uoff, const int32_t *__restrict__ Ulp, const uint64_t *__restrict__ Udesc,
+    const TS *__restrict__ Uval, const int32_t *__restrict__ state, LicArgs la) {
+    if (state != nullptr && *state != 0) return;
+    extern __shared__ unsigned char dd_smem[];
+    apply_slots_sub<BS, TS, TC, MB, PD, LIC>(reinterpret_cast<TC *>(dd_smem), blockIdx.x, r, z, S, Loff, Llp, Ldesc,
+                                             Lval, Uoff, Ulp, Udesc, Uval, la);
+}
+
+// ------------------------------------------------------------------------
+// The apply and the SpMV behind it (BiCGSTAB's y = A M^{-1} x) in one launch.
+//
+// Separate launches leave the chip half idle while the apply's last partial
+// round of subdomains runs (640 subdomains on 256 CUs: the third round holds
+// 128).  Here the launch has twice as many workgroups as subdomains; each
+// takes a ticket from a device counter when it starts.  Tickets below nsub
+// apply subdomain t; ticket nsub + k computes the product rows of subdomain
+// k, after the subdomains its rows read (the range dep[2k]..dep[2k+1]) have
+// finished.  All apply tickets are handed out before any product ticket, so
+// a product workgroup only waits for workgroups that are already running
+// and never wait themselves: every wait ends.  Each wait is still bounded;
+// one that exhausts its bound sets the solve's state word to kWaitFailed
+// (the solve returns an error) and releases the other waits.
+//
+// The price: every workgroup of the launch reserves the apply's LDS, so the
+// product rows run at one workgroup per CU instead of the stand-alone SpMV's
+// occupancy; at 160^3 (640 subdomains of 6400 rows) that loses more than the
+// idle tail gives back (2.40 against 2.21 ms per BiCGSTAB iteration), which
+// is why the solve uses it only on request.
+//
+// Visibility across the chip's L2 caches (one per XCD): an apply workgroup's
+// wavefronts wait for their z stores to be acknowledged, meet at a barrier,
+// and one lane publishes the subdomain's flag with a release store at agent
+// scope (which writes the L2 back first).  A product workgroup's first
+// wavefront polls the flags with relaxed agent-scope loads and then issues
+// one agent-scope acquire fence (which invalidates the stale L1/L2 lines)
+// before the barrier after which its rows read z.
+struct FuseArgs {
+    const int32_t *aptr, *acol;       // full reordered matrix
+    const double *aval;
+    double *y;                        // y = A z
+    const double *w;                  // dot partner: r0 (mode 0) or s (mode 1)
+    double *part;                     // partial sums [NV][part_stride], one per tile
+    int32_t part_stride;
+    int32_t nsub;
+    const int32_t *dep;               // [2 nsub] lowest and highest subdomain a tile reads
+    uint32_t *flag;                   // [nsub] epoch of the launch that last finished the subdomain
+    unsigned long long *ticket;       // workgroup counter (zeroed at the start of each solve)
+    unsigned long long ticket0;       // tickets handed out by the solve's earlier launches
+    uint32_t epoch;                   // this launch's number within the solve (from 1)
+    int32_t *state;                   // the solve's state word
+};
+
+constexpr int kWaitMax = 1 << 18;     // polls per flag (each at least 256 cycles apart)
+
+template <int BS, typename TS, typename TC, int NT, int MB, int PD, bool LIC, int MODE>
+__global__ __launch_bounds__(NT) void k_dd_apply_slots_spmv(
+    const double *__restrict__ r, double *__restrict__ z, int S, const int32_t *__restrict__ Loff,
+    const int32_t *__restrict__ Llp, const uint64_t *__restrict__ Ldesc, const TS *__restrict__ Lval,
+    const int32_t *__restrict__ Uoff, const int32_t *__restrict__ Ulp, const uint64_t *__restrict__ Udesc,
+    const TS *__restrict__ Uval, LicArgs la, FuseArgs f) {
+    constexpr int NV = MODE == 0 ? 1 : 2;
+    __shared__ int ticket;
+    __shared__ double red[NV][16];
+    extern __shared__ unsigned char dd_smem[];
+    if (threadIdx.x == 0) ticket = (int)(atomicAdd(f.ticket, 1ull) - f.ticket0);
+    __syncthreads();
+    const int t = ticket;
+    const int nsub = f.nsub;
+    // every workgroup has taken its ticket before this test, so the counter
+    // advances by the grid size whether or not the solve is still running
+    if (*f.state != 0) return;
+    if ((unsigned)t >= 2u * (unsigned)nsub) {  // counter out of step with the host: fail the solve
+        if (threadIdx.x == 0) __hip_atomic_store(f.state, kWaitFailed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    if (t < nsub) {
+        apply_slots_sub<BS, TS, TC, MB, PD, LIC>(reinterpret_cast<TC *>(dd_smem), t, r, z, S, Loff, Llp, Ldesc,
+                                                 Lval, Uoff, Ulp, Udesc, Uval, la);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (tid == 0) __hip_atomic_store(f.flag + t, f.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    const int k = t - nsub;  // < nsub by the test above
+    if (wave == 0) {
+        const int lo = f.dep[2 * k], hi = f.dep[2 * k + 1];
+        bool ok = true;
+        for (int d = lo + lane; d <= hi && ok; d += kWave) {
+            int polls = 0;
+            while (__hip_atomic_load(f.flag + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != f.epoch) {
+                if ((++polls & 63) == 0 &&
+                    (polls > kWaitMax ||
+                     __hip_atomic_load(f.state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+                    ok = false;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(4);
+            }
+        }
+        // the fence comes before the divergent store, so that the whole
+        // wavefront executes it
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (!ok) __hip_atomic_store(f.state, kWaitFailed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    // rows of subdomain k, BS lanes per row as in the stand-alone SpMV
+    constexpr int RPW = kWave / BS;
+    const int c = lane % BS, rl = lane / BS;
+    const int nw = blockDim.x / kWave;
+    double acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+    if (rl < RPW) {
+        const int64_t row0 = (int64_t)k * S;
+        for (int q = wave * RPW + rl; q < S; q += nw * RPW) {
+            const int64_t row = row0 + q;
+            const int64_t e = row * BS + c;
+            const double tv = bsr_row<BS>(f.aptr, f.acol, f.aval, z, row, c);
+            f.y[e] = tv;
+            if constexpr (MODE == 0) {
+                acc[0] += f.w[e] * tv;
+            } else {
+                acc[0] += tv * f.w[e];
+                acc[1] += tv * tv;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        const double sum = wave_sum(acc[q]);
+        if (lane == 0) red[q][wave] = sum;
+    }
+    __syncthreads();
+    if (tid == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double sum = 0.0;
+            for (int i = 0; i < nw; ++i) sum += red[q][i];
+            f.part[q * f.part_stride + k] = sum;
+        }
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -1139,6 +1287,113 @@ static hipError_t launch_slots_mb(dd_ctx *h, const double *r, double *z, const i
         case 2: return launch_slots<BS, TS, TC, NT, 2, LIC>(h, r, z, state, st, lv, uv);
         default: return launch_slots<BS, TS, TC, NT, 3, LIC>(h, r, z, state, st, lv, uv);
     }
+}
+
+// ------------------------------------------------------- apply + SpMV launch
+constexpr int kFusedStaticLds = 512;  // the kernel's ticket and partial sums (bound)
+
+int fused_unsupported(const dd_ctx *h) {
+    constexpr int kMaxNT = 1024;
+    const int rpp = (kWave / h->bs) * (kMaxNT / kWave);
+    if (h->pc_kind != 0 || h->profile) return 1;
+    if (!(h->variant == 0 || h->variant == 3) || !h->slots || h->max_level_width > rpp) return 2;
+    if (h->nsub > h->spmv_part_stride) return 3;
+    if (apply_lds_bytes(h, h->precision) > 163840 - kFusedStaticLds) return 4;
+    return 0;
+}
+
+template <int BS, typename TS, typename TC, int MB, bool LIC, int MODE>
+static hipError_t launch_fused_k(dd_ctx *h, const double *r, double *z, const FuseArgs &f, hipStream_t st) {
+    constexpr int PD = sizeof(TS) == 8 ? DDILU_PD64 : DDILU_PD32;
+    auto kern = k_dd_apply_slots_spmv<BS, TS, TC, 1024, MB, PD, LIC, MODE>;
+    static bool done = false;
+    if (!done) {
+        hipFuncAttributes a{};
+        hipError_t e = hipFuncGetAttributes(&a, reinterpret_cast<const void *>(kern));
+        if (e != hipSuccess) return e;
+        if (a.sharedSizeBytes > (size_t)kFusedStaticLds) return hipErrorInvalidValue;
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                163840 - kFusedStaticLds);
+        if (e != hipSuccess) return e;
+        done = true;
+    }
+    const TS *lv, *uv, *dv;
+    factor_ptrs<TS>(h, true, &lv, &uv, &dv);
+    const int lds = h->S * BS * (int)sizeof(TC);
+    constexpr int RPW = kWave / BS;
+    const int nt = std::max(kWave, std::min(1024, (h->max_level_width + RPW - 1) / RPW * kWave));
+    kern<<<2 * h->nsub, nt, lds, st>>>(r, z, h->S, h->lev[0].off, h->lev[0].ptr, h->sw[0].desc, lv, h->lev[1].off,
+                                       h->lev[1].ptr, h->sw[1].desc, uv, lic_args(h), f);
+    return hipGetLastError();
+}
+
+template <int BS, typename TS, typename TC, bool LIC>
+static hipError_t fused_mb(dd_ctx *h, int mode, const double *r, double *z, const FuseArgs &f, hipStream_t st) {
+    switch (h->slots * 2 + (mode != 0)) {
+        case 2: return launch_fused_k<BS, TS, TC, 1, LIC, 0>(h, r, z, f, st);
+        case 3: return launch_fused_k<BS, TS, TC, 1, LIC, 1>(h, r, z, f, st);
+        case 4: return launch_fused_k<BS, TS, TC, 2, LIC, 0>(h, r, z, f, st);
+        case 5: return launch_fused_k<BS, TS, TC, 2, LIC, 1>(h, r, z, f, st);
+        case 6: return launch_fused_k<BS, TS, TC, 3, LIC, 0>(h, r, z, f, st);
+        default: return launch_fused_k<BS, TS, TC, 3, LIC, 1>(h, r, z, f, st);
+    }
+}
+
+template <int BS, typename TS, typename TC>
+static hipError_t fused_lic(dd_ctx *h, int mode, const double *r, double *z, const FuseArgs &f, hipStream_t st) {
+    if constexpr (BS == 3)
+        if (h->lic.active) return fused_mb<BS, TS, TC, true>(h, mode, r, z, f, st);
+    return fused_mb<BS, TS, TC, false>(h, mode, r, z, f, st);
+}
+
+template <int BS>
+static hipError_t fused_bs(dd_ctx *h, int mode, const double *r, double *z, const FuseArgs &f, hipStream_t st) {
+    switch (h->precision) {
+        case DD_FP32: return fused_lic<BS, float, float>(h, mode, r, z, f, st);
+        case DD_MIXED: return fused_lic<BS, float, double>(h, mode, r, z, f, st);
+        default: return fused_lic<BS, double, double>(h, mode, r, z, f, st);
+    }
+}
+
+hipError_t launch_apply_spmv(dd_ctx *h, int mode, const double *r, double *z, double *y, const double *w,
+                             double *part, int part_stride, uint32_t epoch, unsigned long long ticket0,
+                             int32_t *state, hipStream_t st) {
+    if (fused_unsupported(h) || !h->fdep) return hipErrorInvalidValue;
+    const FuseArgs f{h->aptr, h->acol,  h->aval,   y,     w,       part,   part_stride,
+                     h->nsub, h->fdep,  h->fflag,  h->fticket,     ticket0, epoch, state};
+    return h->bs == 3 ? fused_bs<3>(h, mode, r, z, f, st) : fused_bs<1>(h, mode, r, z, f, st);
+}
+
+__global__ __launch_bounds__(256) void k_dep_range(int S, const int32_t *__restrict__ ptr,
+                                                   const int32_t *__restrict__ col, int32_t *__restrict__ dep) {
+    __shared__ int lo, hi;
+    const int k = blockIdx.x;
+    if (threadIdx.x == 0) {
+        lo = INT32_MAX;
+        hi = -1;
+    }
+    __syncthreads();
+    int l = INT32_MAX, u = -1;
+    for (int q = threadIdx.x; q < S; q += blockDim.x) {
+        const int64_t row = (int64_t)k * S + q;
+        for (int32_t b = ptr[row]; b < ptr[row + 1]; ++b) {
+            const int d = col[b] / S;
+            l = min(l, d);
+            u = max(u, d);
+        }
+    }
+    atomicMin(&lo, l);
+    atomicMax(&hi, u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        dep[2 * k] = lo <= hi ? lo : k;
+        dep[2 * k + 1] = lo <= hi ? hi : k;
+    }
+}
+
+hipError_t launch_dep_range(dd_ctx *h, hipStream_t st) {
+    k_dep_range<<<h->nsub, 256, 0, st>>>(h->S, h->aptr, h->acol, h->fdep);
+    return hipGetLastError();
 }
 
 // Ablation variants 4-8 (FP64; the API rejects other precisions and the

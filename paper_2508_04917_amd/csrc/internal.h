@@ -131,6 +131,10 @@ struct dd_ctx {
     double *kv = nullptr;       // 9 vectors of n*bs
     double *partials = nullptr; // [8 * spmv_part_stride] per-workgroup partial sums
     int32_t spmv_part_stride = 0;
+    int32_t fuse = 0;                    // apply + SpMV as one launch inside bicgstab_solve (opt-in)
+    int32_t *fdep = nullptr;             // [2 nsub] dependency ranges of the SpMV tiles
+    uint32_t *fflag = nullptr;           // [nsub] per-subdomain completion epochs
+    unsigned long long *fticket = nullptr;  // workgroup ticket counter
     ddilu::KrylovScalars *ks = nullptr;
     ddilu::KrylovScalars *ks_host = nullptr;  // pinned
     std::vector<void *> allocs;
@@ -221,4 +225,14 @@ hipError_t launch_adam(int np, float *P, const float *G, float *M, float *V, int
 hipError_t launch_apply_adjoint(dd_ctx *h, const double *g, double *a, hipStream_t st);
 // the preconditioner bicgstab_solve uses (DD apply, or the global ILU0 apply)
 hipError_t launch_precond(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st);
+constexpr int32_t kWaitFailed = -64;  // solve state word after a dependency wait hit its bound
+// BiCGSTAB's apply and the SpMV behind it as one launch (mode 0: y = A z with
+// the dot w.y; mode 1: the dots y.w and y.y), partials one per subdomain.
+// Nonzero when the handle's shape or settings need the separate launches.
+int fused_unsupported(const dd_ctx *h);
+hipError_t launch_apply_spmv(dd_ctx *h, int mode, const double *r, double *z, double *y, const double *w,
+                             double *part, int part_stride, uint32_t epoch, unsigned long long ticket0,
+                             int32_t *state, hipStream_t st);
+// dep[2k], dep[2k+1]: lowest and highest subdomain read by subdomain k's rows of A
+hipError_t launch_dep_range(dd_ctx *h, hipStream_t st);
 }  // namespace ddilu

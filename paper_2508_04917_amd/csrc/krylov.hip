@@ -13,6 +13,7 @@
 // returns at once when the solve has finished, so the host enqueues a batch
 // of iterations and only synchronises once per batch.
 #include "internal.h"
+#include "spmv.h"
 
 namespace ddilu {
 
@@ -21,12 +22,6 @@ constexpr int kMaxGrid = 2048;    // workgroups of grid-stride vector kernels
 constexpr int kStride = 8;        // partial-sum slots per reduction (2048 each)
 
 enum : int32_t { ST_RUN = 0, ST_CONV = 1, ST_HALF = 2 };
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
-    return v;
-}
 
 // Sums NV values over the workgroup in a fixed order and writes them to
 // out[k*stride + blockIdx.x].
@@ -48,63 +43,6 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double *out, int
             out[k * stride + blockIdx.x] = t;
         }
     }
-}
-
-// --------------------------------------------------------------- SpMV
-// BS lanes of one wavefront per block row, lane c computes component c.
-// The first kUnroll blocks of a row (a 7-point stencil row has at most 7)
-// are fetched branch-free: column indices and block rows for all of them are
-// issued together, positions past the row end re-read the row's last block
-// (a valid address, same cache line) and are discarded by a select, so a row
-// costs two memory round trips (A and col, then x) rather than one per block.
-// Longer rows finish in a loop.
-constexpr int kUnroll = 7;
-
-template <int BS>
-__device__ __forceinline__ double bsr_row(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
-                                          const double *__restrict__ val, const double *__restrict__ x,
-                                          int64_t row, int c) {
-    constexpr int BB = BS * BS;
-    const int32_t b0 = ptr[row], b1 = ptr[row + 1];
-    const int nb = b1 - b0;
-    int32_t idx[kUnroll];
-#pragma unroll
-    for (int k = 0; k < kUnroll; ++k) idx[k] = max(min(b0 + k, b1 - 1), 0);  // nnzb >= 1
-    int32_t J[kUnroll];
-    double v[kUnroll][BS];
-#pragma unroll
-    for (int k = 0; k < kUnroll; ++k) J[k] = col[idx[k]];
-#pragma unroll
-    for (int k = 0; k < kUnroll; ++k) {
-        const double *blk = val + (int64_t)idx[k] * BB + c * BS;
-#pragma unroll
-        for (int d = 0; d < BS; ++d) v[k][d] = blk[d];
-    }
-    // keep the scheduler from sinking these loads next to their uses
-    __builtin_amdgcn_sched_barrier(0);
-    double xv[kUnroll][BS];
-#pragma unroll
-    for (int k = 0; k < kUnroll; ++k) {
-        const double *xb = x + (int64_t)J[k] * BS;
-#pragma unroll
-        for (int d = 0; d < BS; ++d) xv[k][d] = xb[d];
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    double acc = 0.0;
-#pragma unroll
-    for (int k = 0; k < kUnroll; ++k) {
-        double t = 0.0;
-#pragma unroll
-        for (int d = 0; d < BS; ++d) t += v[k][d] * xv[k][d];
-        acc += k < nb ? t : 0.0;
-    }
-    for (int32_t b = b0 + kUnroll; b < b1; ++b) {
-        const int64_t Jb = col[b];
-        const double *blk = val + (int64_t)b * BB + c * BS;
-#pragma unroll
-        for (int d = 0; d < BS; ++d) acc += blk[d] * x[Jb * BS + d];
-    }
-    return acc;
 }
 
 template <int BS>
@@ -190,6 +128,14 @@ __global__ __launch_bounds__(kRedT) void k_axpy_s(int64_t m, const double *__res
         acc[0] += t * t;
     }
     block_partials<1>(acc, part, kMaxGrid);
+}
+
+// Zero the completion flags and the ticket counter of the apply + SpMV launch.
+__global__ __launch_bounds__(256) void k_fuse_reset(int nsub, uint32_t *__restrict__ flag,
+                                                   unsigned long long *__restrict__ ticket) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nsub) flag[i] = 0u;
+    if (i == 0) *ticket = 0ull;
 }
 
 // x += alpha p^ when the half step converged
@@ -409,6 +355,12 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
     const int gsp = (int)((n + rpb - 1) / rpb);  // one partial per SpMV workgroup
     const int gvec = (int)std::min<int64_t>((m + kRedT - 1) / kRedT, kMaxGrid);
     const int sps = h->spmv_part_stride;
+    // apply + SpMV in one launch (partials one per subdomain) where the
+    // handle allows it; the flags and the ticket counter start at zero
+    const bool fused = h->fuse && !fused_unsupported(h);
+    const int gpart = fused ? h->nsub : gsp;
+    uint32_t fepoch = 0;
+    unsigned long long ftick = 0;
 
     hipEvent_t e0, e1;
     KCHK(hipEventCreate(&e0));
@@ -421,6 +373,7 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
     init.state = ST_RUN;
     *h->ks_host = init;
     KCHK(hipMemcpyAsync(ks, h->ks_host, sizeof(KrylovScalars), hipMemcpyHostToDevice, st));
+    if (fused) k_fuse_reset<<<(h->nsub + 255) / 256, 256, 0, st>>>(h->nsub, h->fflag, h->fticket);
     KCHK(launch_permute(n, BS, h->new2old, b, bp, st));
     KCHK(launch_permute(n, BS, h->new2old, x, xp, st));
     // r = b - A x0, r0 = p = r; rho = r0.r
@@ -465,21 +418,31 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
             chunk_todo = todo;
             for (int k = 0; k < todo; ++k) {
                 ++it;
-                if (h->profile) KCHK(hipEventRecord(h->events[4 * k], st));
-                KCHK(launch_precond(h, p, ph, state, st));                       // p^ = M^{-1} p
-                if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 1], st));
-                k_spmv_dots<BS, 0><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, ph, v, r0, nullptr,
-                                                          nullptr, nullptr, part, sps, state);  // v = A p^, r0.v
-                k_scalars<<<1, kScalT, 0, st>>>(SC_ALPHA, it, part, gsp, sps, ks, h->hist, h->hist_len);
+                if (fused) {  // p^ = M^{-1} p and v = A p^, r0.v in one launch
+                    KCHK(launch_apply_spmv(h, 0, p, ph, v, r0, part, sps, ++fepoch, ftick, &ks->state, st));
+                    ftick += 2ull * h->nsub;
+                } else {
+                    if (h->profile) KCHK(hipEventRecord(h->events[4 * k], st));
+                    KCHK(launch_precond(h, p, ph, state, st));  // p^ = M^{-1} p
+                    if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 1], st));
+                    k_spmv_dots<BS, 0><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, ph, v, r0, nullptr,
+                                                              nullptr, nullptr, part, sps, state);  // v = A p^, r0.v
+                }
+                k_scalars<<<1, kScalT, 0, st>>>(SC_ALPHA, it, part, gpart, sps, ks, h->hist, h->hist_len);
                 k_axpy_s<<<gvec, kRedT, 0, st>>>(m, r, v, s, ks, part);        // s = r - alpha v
                 k_scalars<<<1, kScalT, 0, st>>>(SC_S, it, part, gvec, kMaxGrid, ks, h->hist, h->hist_len);
                 k_half<<<gvec, kRedT, 0, st>>>(m, xp, ph, ks);
-                if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 2], st));
-                KCHK(launch_precond(h, s, shat, state, st));                     // s^ = M^{-1} s
-                if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 3], st));
-                k_spmv_dots<BS, 1><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, shat, t, s, nullptr,
-                                                          nullptr, nullptr, part, sps, state);  // t = A s^, t.s, t.t
-                k_scalars<<<1, kScalT, 0, st>>>(SC_OMEGA, it, part, gsp, sps, ks, h->hist, h->hist_len);
+                if (fused) {  // s^ = M^{-1} s and t = A s^, t.s, t.t in one launch
+                    KCHK(launch_apply_spmv(h, 1, s, shat, t, s, part, sps, ++fepoch, ftick, &ks->state, st));
+                    ftick += 2ull * h->nsub;
+                } else {
+                    if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 2], st));
+                    KCHK(launch_precond(h, s, shat, state, st));  // s^ = M^{-1} s
+                    if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 3], st));
+                    k_spmv_dots<BS, 1><<<gsp, kRedT, 0, st>>>(n, h->aptr, h->acol, h->aval, shat, t, s, nullptr,
+                                                              nullptr, nullptr, part, sps, state);  // t = A s^, t.s, t.t
+                }
+                k_scalars<<<1, kScalT, 0, st>>>(SC_OMEGA, it, part, gpart, sps, ks, h->hist, h->hist_len);
                 k_update<<<gvec, kRedT, 0, st>>>(m, xp, ph, shat, r, s, t, r0, ks, part);
                 k_scalars<<<1, kScalT, 0, st>>>(SC_BETA, it, part, gvec, kMaxGrid, ks, h->hist, h->hist_len);
                 k_pupdate<<<gvec, kRedT, 0, st>>>(m, p, r, v, ks);
@@ -518,6 +481,8 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
     (void)hipEventDestroy(e1);
     const KrylovScalars &hk = *h->ks_host;
     int status = DD_OK;
+    if (hk.state == kWaitFailed)
+        return h->fail(DD_EHIP, "bicgstab_solve: a wait of the apply + SpMV launch exhausted its bound");
     if (hk.state == ST_CONV) status = hk.snorm > 2.0 * hk.tol ? DD_ENOCONV : DD_OK;  // restarts exhausted
     else if (hk.state == DD_EBREAKDOWN) status = DD_EBREAKDOWN;
     else status = DD_ENOCONV;
@@ -530,6 +495,7 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
         info->applies = applies;
         info->restarts = restarts;
         info->apply_seconds = apply_ms * 1e-3;
+        info->fused = fused ? 1 : 0;
     }
     if (status == DD_EBREAKDOWN) return h->fail(DD_EBREAKDOWN, "BiCGSTAB breakdown at iteration %d", hk.iters);
     if (status == DD_ENOCONV && hk.state == ST_CONV)
@@ -554,6 +520,14 @@ int bicgstab_run(dd_ctx *h, const double *b, double *x, double rtol, int32_t max
         if (rc) return rc;
         hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&h->ks_host), sizeof(KrylovScalars));
         if (e != hipSuccess) return h->fail(DD_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+    }
+    if (h->fuse && !h->fdep && !fused_unsupported(h)) {
+        int rc = h->alloc(&h->fdep, 2 * (int64_t)h->nsub);
+        if (!rc) rc = h->alloc(&h->fflag, h->nsub);
+        if (!rc) rc = h->alloc(&h->fticket, 1);
+        if (rc) return rc;
+        hipError_t e = launch_dep_range(h, st);
+        if (e != hipSuccess) return h->fail(DD_EHIP, "dependency ranges: %s", hipGetErrorString(e));
     }
     return h->bs == 3 ? run_typed<3>(h, b, x, rtol, maxit, st, info) : run_typed<1>(h, b, x, rtol, maxit, st, info);
 }
