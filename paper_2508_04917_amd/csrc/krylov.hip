@@ -178,11 +178,12 @@ __global__ __launch_bounds__(kRedT) void k_pupdate(int64_t m, double *__restrict
 // Fixed-order sum of nblk partials of slot k.
 // Scalar step: one workgroup of kScalT threads sums the partials of one or
 // two dot products.  Thread t adds entries t + (j*kScalU + u)*kScalT into
-// accumulator u (kScalU independent loads in flight per thread), then the
+// accumulator u (kScalU x kScalB independent loads in flight per thread), then the
 // accumulators, the wavefront and the wavefronts are combined in a fixed
 // order, so the result does not depend on timing.
 constexpr int kScalT = 1024;
 constexpr int kScalU = 4;
+constexpr int kScalB = 4;
 
 template <int NS>
 __device__ void reduce_slots(const double *part, int nblk, int stride, double (&out)[NS]) {
@@ -192,14 +193,25 @@ __device__ void reduce_slots(const double *part, int nblk, int stride, double (&
     for (int k = 0; k < NS; ++k)
 #pragma unroll
         for (int u = 0; u < kScalU; ++u) acc[k][u] = 0.0;
-    for (int i0 = threadIdx.x; i0 < nblk; i0 += kScalT * kScalU) {
+    // kScalB passes of that loop have their loads issued together (the
+    // additions keep the same order, so the sums do not change)
+    for (int i0 = threadIdx.x; i0 < nblk; i0 += kScalT * kScalU * kScalB) {
+        double v[kScalB][kScalU][NS];
 #pragma unroll
-        for (int u = 0; u < kScalU; ++u) {
-            const int i = i0 + u * kScalT;
-            if (i < nblk)
+        for (int b = 0; b < kScalB; ++b)
 #pragma unroll
-                for (int k = 0; k < NS; ++k) acc[k][u] += part[(int64_t)k * stride + i];
-        }
+            for (int u = 0; u < kScalU; ++u) {
+                const int i = i0 + (b * kScalU + u) * kScalT;
+#pragma unroll
+                for (int k = 0; k < NS; ++k) v[b][u][k] = i < nblk ? part[(int64_t)k * stride + i] : 0.0;
+            }
+#pragma unroll
+        for (int b = 0; b < kScalB; ++b)
+#pragma unroll
+            for (int u = 0; u < kScalU; ++u)
+                if (i0 + (b * kScalU + u) * kScalT < nblk)
+#pragma unroll
+                    for (int k = 0; k < NS; ++k) acc[k][u] += v[b][u][k];
     }
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
