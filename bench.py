@@ -410,6 +410,15 @@ def main():
     cev[1].record()
     torch.cuda.synchronize()
     copy_gbs = 2 * csrc.numel() * 8 * 5 / (cev[0].elapsed_time(cev[1]) * 1e-3) / 1e9
+    # and a plain read of the same 1 GiB (a sum): the apply reads 24 bytes
+    # for every byte it writes, so this is the closer ceiling
+    csrc.sum()
+    cev[0].record()
+    for _ in range(5):
+        csrc.sum()
+    cev[1].record()
+    torch.cuda.synchronize()
+    read_gbs = csrc.numel() * 8 * 5 / (cev[0].elapsed_time(cev[1]) * 1e-3) / 1e9
     del csrc, cdst
 
     for w in range(args.warmup):
@@ -493,7 +502,8 @@ def main():
                      "frac": round(gbs64 / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "k_dd_apply_slots<3, double, double, 1024, 3, 2, false>",
                      "bytes_per_launch": bytes64, "copy_GBs": round(copy_gbs, 1),
-                     "frac_of_copy": round(gbs64 / copy_gbs, 4)},
+                     "frac_of_copy": round(gbs64 / copy_gbs, 4), "read_GBs": round(read_gbs, 1),
+                     "frac_of_read": round(gbs64 / read_gbs, 4)},
         "cpu_baseline": None,
     }
 
