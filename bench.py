@@ -410,16 +410,19 @@ def main():
     cev[1].record()
     torch.cuda.synchronize()
     copy_gbs = 2 * csrc.numel() * 8 * 5 / (cev[0].elapsed_time(cev[1]) * 1e-3) / 1e9
-    # and a plain read of the same 1 GiB (a sum): the apply reads 24 bytes
-    # for every byte it writes, so this is the closer ceiling
-    csrc.sum()
+    del csrc, cdst
+    # and a plain read of 2 GiB (a sum): the apply reads 24 bytes for every
+    # byte it writes, so this is the closer ceiling
+    rsrc = torch.ones(1 << 28, dtype=torch.float64, device=dev)
+    for _ in range(2):
+        rsrc.sum()
     cev[0].record()
-    for _ in range(5):
-        csrc.sum()
+    for _ in range(10):
+        rsrc.sum()
     cev[1].record()
     torch.cuda.synchronize()
-    read_gbs = csrc.numel() * 8 * 5 / (cev[0].elapsed_time(cev[1]) * 1e-3) / 1e9
-    del csrc, cdst
+    read_gbs = rsrc.numel() * 8 * 10 / (cev[0].elapsed_time(cev[1]) * 1e-3) / 1e9
+    del rsrc
 
     for w in range(args.warmup):
         log(f"warmup step {w + 1}/{args.warmup}")

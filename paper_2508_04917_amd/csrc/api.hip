@@ -268,6 +268,7 @@ static int build_handle(dd_ctx *h, const int32_t *brow_ptr, const int32_t *bcol,
         PCHK(launch_partition(h, st));
     }
     PCHK(launch_row_len(h, brow_ptr, len, st));
+    PCHK(launch_max_count(n, len, h->status + 6, st));  // longest row (selects the SpMV layout)
     PCHK(exclusive_scan(len, h->aptr, n, h->scan_tmp, st));
     int32_t total = 0, status[8];
     PCHK(hipMemcpyAsync(&total, h->aptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -281,6 +282,7 @@ static int build_handle(dd_ctx *h, const int32_t *brow_ptr, const int32_t *bcol,
         h->fail(DD_EINVAL, "brow_ptr describes %d blocks, nnzb says %lld", total, (long long)nnzb);
         return bail(DD_EINVAL);
     }
+    h->max_row_a = status[6];
     PCHK(launch_reorder_fill(h, brow_ptr, bcol, val, src, st));
     PCHK(hipStreamSynchronize(st));
     release(h, len);

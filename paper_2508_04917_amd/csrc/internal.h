@@ -131,6 +131,10 @@ struct dd_ctx {
     double *kv = nullptr;       // 9 vectors of n*bs
     double *partials = nullptr; // [8 * spmv_part_stride] per-workgroup partial sums
     int32_t spmv_part_stride = 0;
+    int32_t max_row_a = 0;               // most blocks in a row of the full matrix
+    int32_t ell_state = 0;               // sliced-ELL copy for the SpMV: 0 not built, 1 ready, -1 not used
+    int32_t *ell_col = nullptr;          // [groups][kUnroll][rows per wavefront]
+    double *ell_val = nullptr;           // the same slots, bs*bs values each
     int32_t fuse = 0;                    // apply + SpMV as one launch inside bicgstab_solve (opt-in)
     int32_t *fdep = nullptr;             // [2 nsub] dependency ranges of the SpMV tiles
     uint32_t *fflag = nullptr;           // [nsub] per-subdomain completion epochs

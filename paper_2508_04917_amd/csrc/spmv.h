@@ -69,4 +69,43 @@ __device__ __forceinline__ double bsr_row(const int32_t *__restrict__ ptr, const
     return acc;
 }
 
+// The same row product on the sliced ELL copy: slot (g, k, r) holds the k-th
+// block of row g*RPW + r (column -1 and a zero block past the row's end), so
+// the lanes of a wavefront read the k-th blocks of its RPW rows as one
+// contiguous run.  Blocks are taken in the row's CSR order and an empty slot
+// adds 0 exactly as in bsr_row, so both give the same bits.
+template <int BS>
+__device__ __forceinline__ double ell_row(const int32_t *__restrict__ ecol, const double *__restrict__ eval,
+                                          const double *__restrict__ x, int64_t g, int r, int c) {
+    constexpr int RPW = 64 / BS, BB = BS * BS;
+    int32_t J[kUnroll];
+    double v[kUnroll][BS];
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) J[k] = ecol[(g * kUnroll + k) * RPW + r];
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) {
+        const double *blk = eval + ((g * kUnroll + k) * RPW + r) * BB + c * BS;
+#pragma unroll
+        for (int d = 0; d < BS; ++d) v[k][d] = blk[d];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    double xv[kUnroll][BS];
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) {
+        const double *xb = x + (int64_t)max(J[k], 0) * BS;
+#pragma unroll
+        for (int d = 0; d < BS; ++d) xv[k][d] = xb[d];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) {
+        double t = 0.0;
+#pragma unroll
+        for (int d = 0; d < BS; ++d) t += v[k][d] * xv[k][d];
+        acc += J[k] >= 0 ? t : 0.0;
+    }
+    return acc;
+}
+
 }  // namespace ddilu
