@@ -109,6 +109,14 @@ typedef struct {
                                   int32 row pointers of L and Uhat, FP64 r
                                   in and z out)                           */
     int64_t lds_bytes;         /* LDS per workgroup used by the apply     */
+    int32_t max_row_blocks;    /* most blocks in a row of A               */
+    int32_t spmv_layout;       /* layout dd_spmv and bicgstab_solve read A
+                                  in: 0 = CSR arrays (before the first
+                                  SpMV or solve, and for rows of more than
+                                  7 blocks), 1 = a sliced ELL copy built
+                                  by the first SpMV or solve (the k-th
+                                  blocks of each wavefront's rows stored
+                                  together; one more copy of A's blocks)  */
 } dd_info;
 
 /* Result of bicgstab_solve. */

@@ -314,6 +314,8 @@ extern "C" int dd_get_info(dd_handle h, dd_info *info) {
     info->apply_bytes = (h->nlow + h->nupp) * (bb * wsz + 4) + h->n * bb * wsz + 2 * 4 * (h->n + 1) +
                         2 * h->n * h->bs * 8;
     info->lds_bytes = apply_lds_bytes(h, h->precision);
+    info->max_row_blocks = h->max_row_a;
+    info->spmv_layout = h->ell_state == 1 ? 1 : 0;
     return DD_OK;
 }
 

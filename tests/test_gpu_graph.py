@@ -46,6 +46,23 @@ def np_(t):
     return t.detach().cpu().numpy()
 
 
+@pytest.mark.parametrize("name", list(CASES))
+def test_spmv_layouts(name):
+    """SpMV against the oracle on graph-partitioned matrices: the sliced ELL
+    copy where rows hold at most 7 blocks, the CSR arrays where the k-nearest
+    neighbour pattern gives longer rows."""
+    p, s, st = case(name)
+    x = np.random.default_rng(6).standard_normal(st.n * st.bs)
+    y_o = st.spmv(x)
+    y_g = np_(s.spmv(torch.as_tensor(x, device="cuda")))
+    assert np.linalg.norm(y_g - y_o) / np.linalg.norm(y_o) < 1e-14
+    inf = dd.dd_get_info(s.h)
+    longest = int(np.diff(st.aptr).max())
+    print(f"[graph {name}] longest row {longest} blocks, layout {inf['spmv_layout']}", flush=True)
+    assert inf["max_row_blocks"] == longest
+    assert inf["spmv_layout"] == (1 if longest <= 7 else 0)
+
+
 def test_worked_example_matches_oracle():
     ptr, col = grid_graph(4, 4, 1)
     val = np.where(col == np.repeat(np.arange(16), np.diff(ptr)), 4.0, -1.0)

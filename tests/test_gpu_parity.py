@@ -209,11 +209,16 @@ def test_apply_reduced_precision(name, variant, precision):
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_spmv(name):
+    """The SpMV (on the sliced ELL copy: every case is a 7-point pattern)
+    against the oracle's CSR product."""
     p, s, st = case(name)
     x = np.random.default_rng(5).standard_normal(st.n * st.bs)
     y_o = st.spmv(x)
     y_g = np_(s.spmv(torch.as_tensor(x, device="cuda")))
     assert np.linalg.norm(y_g - y_o) / np.linalg.norm(y_o) < 1e-14
+    inf = P.ddilu.dd_get_info(s.h)
+    assert inf["max_row_blocks"] == int(np.diff(st.aptr).max())
+    assert inf["spmv_layout"] == 1
 
 
 def test_apply_deterministic():
