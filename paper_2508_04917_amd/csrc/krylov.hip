@@ -98,7 +98,9 @@ static void ensure_ell(dd_ctx *h, hipStream_t st) {
         k_ell_fill<3><<<g, 256, 0, st>>>(h->n, h->aptr, h->acol, h->aval, h->ell_col, h->ell_val, nslots);
     else
         k_ell_fill<1><<<g, 256, 0, st>>>(h->n, h->aptr, h->acol, h->aval, h->ell_col, h->ell_val, nslots);
-    if (hipGetLastError() == hipSuccess) h->ell_state = 1;
+    // later SpMVs may run on other streams: the copy is complete before any
+    // of them is enqueued
+    if (hipGetLastError() == hipSuccess && hipStreamSynchronize(st) == hipSuccess) h->ell_state = 1;
 }
 
 // one row product, CSR or sliced ELL
