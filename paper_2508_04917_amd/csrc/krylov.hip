@@ -262,8 +262,16 @@ __global__ __launch_bounds__(kRedT) void k_update(int64_t m, double *__restrict_
 
 // p = r + beta (p - omega v)
 __global__ __launch_bounds__(kRedT) void k_pupdate(int64_t m, double *__restrict__ p, const double *__restrict__ r,
-                                                  const double *__restrict__ v, const KrylovScalars *__restrict__ ks) {
-    if (ks->state != ST_RUN) return;
+                                                  const double *__restrict__ v, KrylovScalars *__restrict__ ks) {
+    const int32_t st0 = ks->state;
+    if (st0 != ST_RUN) {
+        // The half step converged in this iteration and k_half has added
+        // alpha p^ to x: mark the solve converged (every workgroup returns
+        // whichever of the two values it reads), so that the batch's later
+        // iterations leave x alone.
+        if (st0 == ST_HALF && blockIdx.x == 0 && threadIdx.x == 0) ks->state = ST_CONV;
+        return;
+    }
     const double beta = ks->beta, omega = ks->omega;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = r[i] + beta * (p[i] - omega * v[i]);
@@ -420,10 +428,6 @@ __global__ __launch_bounds__(kScalT) void k_scalars(int stage, int it, const dou
     }
 }
 
-__global__ void k_half_to_conv(KrylovScalars *ks) {
-    if (ks->state == ST_HALF) ks->state = ST_CONV;
-}
-
 // out[i] = in[map[i]] per block row
 __global__ void k_permute(int64_t n, int bs, const int32_t *map, const double *in, double *out) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -552,7 +556,6 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
                 k_update<<<gvec, kRedT, 0, st>>>(m, xp, ph, shat, r, s, t, r0, ks, part);
                 k_scalars<<<1, kScalT, 0, st>>>(SC_BETA, it, part, gvec, kMaxGrid, ks, h->hist, h->hist_len);
                 k_pupdate<<<gvec, kRedT, 0, st>>>(m, p, r, v, ks);
-                k_half_to_conv<<<1, 1, 0, st>>>(ks);
                 KCHK(hipGetLastError());
             }
         }
