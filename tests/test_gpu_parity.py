@@ -36,6 +36,8 @@ CASES = {
     "rand_jacobi": (lambda: random_blocks(6, 5, 4, seed=9), (1, 1, 1)),
     "rand_lines": (lambda: random_blocks(20, 4, 3, seed=10), (20, 1, 1)),
     "lap_one_sub": (lambda: laplacian_scalar(12, 10, 8, seed=3), (12, 10, 8)),
+    # scalar rows not a multiple of one wavefront's 64 (ragged last SpMV group)
+    "lap_ragged": (lambda: laplacian_scalar(10, 9, 7, seed=4), (5, 9, 7)),
 }
 
 _cache = {}
