@@ -190,11 +190,11 @@ def drop(n, bs, S, ptr, col, val=None):
     """Section 3.2: keep block (I,J) iff I and J lie in the same S-row window."""
     ptr, col = _i32(ptr), _i32(col)
     if val is not None:
-        val = _f64(val)
+        val = _f64(val).reshape(-1, bs, bs)  # blocks row-major, whatever shape they came in
     m = lib().o_drop(n, bs, S, _p(ptr), _p(col), None, None, None, None)
     tptr = np.empty(n + 1, dtype=np.int32)
     tcol = np.empty(m, dtype=np.int32)
-    tval = None if val is None else np.empty((m,) + val.shape[1:], dtype=np.float64)
+    tval = None if val is None else np.empty((m, bs, bs), dtype=np.float64)
     lib().o_drop(n, bs, S, _p(ptr), _p(col), _p(val), _p(tptr), _p(tcol), _p(tval))
     return tptr, tcol, tval
 

@@ -127,6 +127,54 @@ def test_bicgstab(name):
     assert abs(info["iters"] - ref.iters) <= max(3, ref.iters // 7)
 
 
+def chain_with_hub(n, extra, bs=3, seed=21):
+    """A chain of n block rows (tridiagonal pattern) whose row 10 is also
+    coupled, both ways, to `extra` far rows: row 10 then holds 3 + extra
+    blocks, the largest in the matrix."""
+    rng = np.random.default_rng(seed)
+    far = [20, 30, 40, 50, 60][:extra]
+    nb = [{i} | {j for j in (i - 1, i + 1) if 0 <= j < n} for i in range(n)]
+    for j in far:
+        nb[10].add(j)
+        nb[j].add(10)
+    ptr = np.zeros(n + 1, dtype=np.int32)
+    cols = []
+    for i in range(n):
+        c = sorted(nb[i])
+        cols += c
+        ptr[i + 1] = ptr[i] + len(c)
+    col = np.array(cols, dtype=np.int32)
+    val = rng.standard_normal((col.size, bs, bs))
+    for i in range(n):
+        k = ptr[i] + list(col[ptr[i]:ptr[i + 1]]).index(i)
+        val[k] += 8.0 * np.eye(bs)
+    from problems.generators import Problem
+    return Problem(name="chain_hub", nx=n, ny=1, nz=1, bs=bs, brow_ptr=ptr, bcol=col, val=val.reshape(-1),
+                   b=rng.standard_normal(n * bs), seed=seed)
+
+
+@pytest.mark.parametrize("extra,layout", [(4, 1), (5, 0)])
+def test_spmv_layout_threshold(extra, layout):
+    """A longest row of 7 blocks takes the sliced ELL copy, 8 blocks the CSR
+    arrays; both agree with the oracle's product on the reordered matrix."""
+    p = chain_with_hub(64, extra)
+    S = 16
+    s = DDSolver(p.n, 1, 1, p.bs, p.brow_ptr, p.bcol, p.val, graph_part_rows=S)
+    try:
+        st = O.setup_graph(p, S)
+        x = np.random.default_rng(3).standard_normal(p.n * p.bs)
+        y_o = st.spmv(x)
+        y_g = np_(s.spmv(torch.as_tensor(x, device="cuda")))
+        assert np.linalg.norm(y_g - y_o) / np.linalg.norm(y_o) < 1e-14
+        inf = dd.dd_get_info(s.h)
+        assert inf["max_row_blocks"] == 3 + extra
+        assert inf["spmv_layout"] == layout
+        xs, info = s.solve(torch.as_tensor(p.b, device="cuda"), rtol=1e-10)
+        assert info["status"] == 0 and info["rel_res_true"] <= 2e-10
+    finally:
+        s.close()
+
+
 def test_isolated_vertices_match_oracle():
     n, S = 48, 4
     ptr = np.arange(n + 1, dtype=np.int32)

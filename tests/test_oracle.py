@@ -14,6 +14,7 @@ import scipy.sparse.linalg as spla
 
 import oracle as O
 from problems import (laplacian_scalar, lognormal_problem, random_blocks, stencil_pattern)
+from problems.generators import Problem
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -504,3 +505,15 @@ def test_bicgstab_maxit_and_breakdown():
     b[0] = np.nan
     res = st.bicgstab(b, rtol=1e-8, maxit=10)
     assert res.status == O.O_EBREAKDOWN
+
+
+def test_block_values_in_any_shape():
+    """The oracle takes a matrix's blocks as (nnzb, bs, bs) or flat; both give
+    the same dropped pattern and factors (a flat array once made the drop
+    allocate one value per block instead of bs*bs)."""
+    p = random_blocks(6, 5, 4, seed=31)
+    flat = Problem(**{**p.__dict__, "val": p.val.reshape(-1)})
+    a, b = O.setup(p, (3, 5, 2)), O.setup(flat, (3, 5, 2))
+    assert np.array_equal(a.tptr, b.tptr) and np.array_equal(a.tcol, b.tcol)
+    assert np.array_equal(a.tval.reshape(-1), b.tval.reshape(-1))
+    assert np.array_equal(a.f.reshape(-1), b.f.reshape(-1))
