@@ -111,12 +111,12 @@ typedef struct {
     int64_t lds_bytes;         /* LDS per workgroup used by the apply     */
     int32_t max_row_blocks;    /* most blocks in a row of A               */
     int32_t spmv_layout;       /* layout dd_spmv and bicgstab_solve read A
-                                  in: 0 = CSR arrays (before the first
-                                  SpMV or solve, and for rows of more than
-                                  7 blocks), 1 = a sliced ELL copy built
-                                  by the first SpMV or solve (the k-th
-                                  blocks of each wavefront's rows stored
-                                  together; one more copy of A's blocks)  */
+                                  in: 1 = a sliced ELL copy built by the
+                                  partition step (the k-th blocks of each
+                                  wavefront's rows stored together; one
+                                  more copy of A's blocks), 0 = the CSR
+                                  arrays (rows of more than 7 blocks, or
+                                  no memory for the copy)                 */
 } dd_info;
 
 /* Result of bicgstab_solve. */
@@ -158,7 +158,9 @@ int dd_device_caps(int32_t *n_cu, int64_t *lds_per_workgroup);
  * with its subdomain, renumber cells subdomain by subdomain (stable in the
  * old index, i.e. local lexicographic order inside each box), and build the
  * reordered matrix P A P^T with each row's blocks sorted by column.  The
- * full reordered matrix is kept for SpMV (Section 3.2).
+ * full reordered matrix is kept for SpMV (Section 3.2); when no row holds
+ * more than 7 blocks, a second, sliced ELL copy of it is built for the SpMV
+ * (dd_info.spmv_layout), so a handle holds A's blocks twice.
  * brow_ptr, bcol, val: device, the matrix in grid order, nnzb blocks,
  * at most 64 blocks per row.  The library copies what it needs; the caller
  * may free them after the call returns.

@@ -287,6 +287,7 @@ static int build_handle(dd_ctx *h, const int32_t *brow_ptr, const int32_t *bcol,
     PCHK(hipStreamSynchronize(st));
     release(h, len);
     release(h, src);
+    build_spmv_layout(h, st);
     *out = h;
     return DD_OK;
 }

@@ -208,6 +208,8 @@ const char *variant_unsupported(const dd_ctx *h, int v);
 
 // Krylov
 hipError_t launch_spmv(dd_ctx *h, const double *x, double *y, hipStream_t st);
+// the sliced ELL copy of A for the SpMV (once per handle; synchronises st)
+void build_spmv_layout(dd_ctx *h, hipStream_t st);
 hipError_t launch_permute(int64_t n, int bs, const int32_t *map, const double *in, double *out,
                           hipStream_t st);
 int bicgstab_run(dd_ctx *h, const double *b, double *x, double rtol, int32_t maxit,

