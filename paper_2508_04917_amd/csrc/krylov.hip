@@ -52,8 +52,8 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double *out, int
 // end).  In the CSR layout the k-th blocks of a wavefront's rows lie one row
 // length apart, so each load instruction touches RPW separate pieces; here
 // it reads one contiguous run (measured at 160^3: 441 -> 408 us per SpMV,
-// same bits).  One more copy of A's blocks (plus kUnroll/row length of
-// padding); the CSR arrays stay for everything else.
+// same bits).  One more copy of A's blocks (plus a zero block for each
+// position a row leaves empty); the CSR arrays stay for everything else.
 template <int BS>
 __global__ __launch_bounds__(256) void k_ell_fill(int64_t n, const int32_t *__restrict__ ptr,
                                                  const int32_t *__restrict__ col, const double *__restrict__ val,
