@@ -64,8 +64,9 @@ def measured_traffic(workload, sub):
 
 def kernels_only(args, p, sub, ptr_d, col_d, val_d, dd, torch):
     """A plain device copy of known size (the reference for scaling hardware
-    byte counters), then bursts of applies in each precision, each burst
-    timed with events on the stream the library launches on."""
+    byte counters), then bursts of applies in each precision and of the
+    SpMV, each burst timed with events on the stream the library launches
+    on."""
     copy_elems = 1 << 28  # 2 GiB of FP64 read + 2 GiB written
     src = torch.ones(copy_elems, dtype=torch.float64, device="cuda:0")
     dst = torch.empty_like(src)
@@ -97,6 +98,21 @@ def kernels_only(args, p, sub, ptr_d, col_d, val_d, dd, torch):
         nbytes = dd.dd_get_info(h)["apply_bytes"]
         out[name] = {"us_per_apply": round(us, 2), "bytes_per_apply": nbytes, "GB/s": round(nbytes / us / 1e3, 1)}
         log(f"{name}: {us:.1f} us per apply, {nbytes / us / 1e3:.1f} GB/s")
+    # SpMV bursts on the layout the handle uses; bytes as the BSR count
+    # (FP64 blocks, int32 columns and row pointers, x once, y)
+    info = dd.dd_get_info(h)
+    dd.dd_spmv(h, r, z)
+    ev[0].record()
+    for _ in range(args.applies):
+        dd.dd_spmv(h, r, z)
+    ev[1].record()
+    torch.cuda.synchronize()
+    us = 1e3 * ev[0].elapsed_time(ev[1]) / args.applies
+    bb = info["bs"] * info["bs"]
+    nbytes = info["nnzb"] * (bb * 8 + 4) + (info["n"] + 1) * 4 + 2 * info["n"] * info["bs"] * 8
+    out["spmv"] = {"us_per_call": round(us, 2), "layout": "sliced ELL" if info["spmv_layout"] else "CSR",
+                   "bytes_per_call": nbytes, "GB/s": round(nbytes / us / 1e3, 1)}
+    log(f"spmv: {us:.1f} us per call, {nbytes / us / 1e3:.1f} GB/s")
     h.close()
     print(json.dumps(out), flush=True)
 
@@ -290,7 +306,7 @@ def main():
     ap.add_argument("--cpu-applies", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="full", choices=["full", "kernels", "ablation", "rocsparse", "graph"],
-                    help="kernels: only a copy kernel of known size and bursts of applies "
+                    help="kernels: only a copy kernel of known size and bursts of applies and SpMVs "
                          "(the short program the rocprofv3 counter runs profile); "
                          "ablation: the FP64 apply kernel variants, timed on the same factors; "
                          "rocsparse: rocSPARSE's block ILU0 apply on the decomposed and the full matrix; "

@@ -54,21 +54,26 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double *out, int
 // it reads one contiguous run (measured at 160^3: 441 -> 408 us per SpMV,
 // same bits).  One more copy of A's blocks (plus a zero block for each
 // position a row leaves empty); the CSR arrays stay for everything else.
+// One thread per value of the copy, so that consecutive threads write
+// consecutive words (the column of a slot is written by its first value's
+// thread).
 template <int BS>
 __global__ __launch_bounds__(256) void k_ell_fill(int64_t n, const int32_t *__restrict__ ptr,
                                                  const int32_t *__restrict__ col, const double *__restrict__ val,
                                                  int32_t *__restrict__ ecol, double *__restrict__ eval,
                                                  int64_t nslots) {
     constexpr int RPW = kWave / BS, BB = BS * BS;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nslots) return;
-    const int64_t r = i % RPW, gk = i / RPW, k = gk % kUnroll, g = gk / kUnroll;
-    const int64_t row = g * RPW + r;
-    int64_t b = -1;
-    if (row < n && ptr[row] + k < ptr[row + 1]) b = ptr[row] + k;
-    ecol[i] = b >= 0 ? col[b] : -1;
-#pragma unroll
-    for (int e = 0; e < BB; ++e) eval[i * BB + e] = b >= 0 ? val[b * BB + e] : 0.0;
+    const int64_t total = nslots * BB;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / BB, e = t % BB;
+        const int64_t r = i % RPW, gk = i / RPW, k = gk % kUnroll, g = gk / kUnroll;
+        const int64_t row = g * RPW + r;
+        int64_t b = -1;
+        if (row < n && ptr[row] + k < ptr[row + 1]) b = ptr[row] + k;
+        if (e == 0) ecol[i] = b >= 0 ? col[b] : -1;
+        eval[t] = b >= 0 ? val[b * BB + e] : 0.0;
+    }
 }
 
 // Build the sliced ELL copy once per handle when the rows are short enough
@@ -95,7 +100,7 @@ void build_spmv_layout(dd_ctx *h, hipStream_t st) {
     h->allocs.push_back(v);
     h->ell_col = static_cast<int32_t *>(c);
     h->ell_val = static_cast<double *>(v);
-    const unsigned g = (unsigned)((nslots + 255) / 256);
+    const unsigned g = (unsigned)std::min<int64_t>((nslots * bb + 255) / 256, 1 << 20);  // grid-stride beyond
     if (h->bs == 3)
         k_ell_fill<3><<<g, 256, 0, st>>>(h->n, h->aptr, h->acol, h->aval, h->ell_col, h->ell_val, nslots);
     else
