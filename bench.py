@@ -167,7 +167,7 @@ def ablation(args, p, sub, ptr_d, col_d, val_d, dd, torch):
 
 
 def rocsparse_cmp(args, p, sub, ptr_d, col_d, val_d, dd, torch):
-    """The paper's headline comparison (Section 5.3, Table 4) restated on this
+    """The paper's headline comparison (Section 5.2, Table 4) restated on this
     GPU: rocSPARSE's block ILU0 apply (two block triangular solves) as a black
     box, on the decomposed matrix (the same preconditioner as the DD apply)
     and on the full matrix (global ILU0, against this library's
@@ -294,6 +294,149 @@ def graph_mode(args, p, ptr_d, col_d, val_d, dd, torch):
     print(json.dumps(out), flush=True)
 
 
+def host_cpu():
+    """(model name, threads available to this process)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(args, p, sub, bytes64, np):
+    """The oracle timed on this host's CPU cores, on the same matrix: the
+    DD-ILU0 apply single-threaded (the oracle's own whole-matrix call) and
+    subdomain-parallel on every available core (one oracle call per
+    subdomain's rows of the dropped matrix, which share no coupling; the
+    calls release the GIL), bytes counted as for the GPU apply; plus the
+    oracle's BiCGSTAB (setup and solve, single-threaded) on the 16^3 scalar
+    Laplacian and the 64^3 random-block operator."""
+    import concurrent.futures as cf
+
+    import oracle as O
+    from problems import make_workload
+    model, threads = host_cpu()
+    log(f"cpu baseline: oracle setup on {p.nx}x{p.ny}x{p.nz} ({threads} threads of {model})")
+    t = time.perf_counter()
+    st = O.setup(p, tuple(sub))
+    setup_s = time.perf_counter() - t
+    r = np.random.default_rng(0).standard_normal(p.n * p.bs)
+    st.apply(r)
+    t = time.perf_counter()
+    for _ in range(args.cpu_applies):
+        st.apply(r)
+    dt1 = (time.perf_counter() - t) / args.cpu_applies
+    # per-subdomain slices of the dropped matrix and its factors (local columns)
+    S, bs, bb = st.S, st.bs, st.bs * st.bs
+    f = np.asarray(st.f).reshape(-1, bb)
+    parts = []
+    for k in range(st.nsub):
+        a, b = int(st.tptr[k * S]), int(st.tptr[(k + 1) * S])
+        ptr = (st.tptr[k * S:(k + 1) * S + 1] - a).astype(np.int32)
+        col = (st.tcol[a:b] - k * S).astype(np.int32)
+        parts.append((ptr, col, np.ascontiguousarray(f[a:b]), k * S * bs))
+    z = np.empty_like(r)
+
+    def one(part):
+        ptr, col, fk, off = part
+        z[off:off + S * bs] = O.apply(S, bs, ptr, col, fk, r[off:off + S * bs])
+
+    with cf.ThreadPoolExecutor(max_workers=threads) as pool:
+        list(pool.map(one, parts))
+        zref = st.apply(r)
+        assert np.array_equal(z, zref), "subdomain-parallel oracle apply differs from the whole-matrix call"
+        t = time.perf_counter()
+        for _ in range(args.cpu_applies):
+            list(pool.map(one, parts))
+        dtn = (time.perf_counter() - t) / args.cpu_applies
+    out = {"value": round(bytes64 / dtn / 1e9, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+           "sample": f"{args.cpu_applies} oracle DD-ILU0 applies (FP64) on the full {p.nx}x{p.ny}x{p.nz} matrix "
+                     f"on {threads} threads (one oracle call per subdomain), {dtn * 1e3:.1f} ms each; "
+                     f"single-threaded {dt1 * 1e3:.1f} ms each; bytes counted as for the GPU apply",
+           "cpu_model": model, "single_thread_GBs": round(bytes64 / dt1 / 1e9, 3),
+           "apply_ms": {"threads": round(dtn * 1e3, 2), "single": round(dt1 * 1e3, 2)},
+           "setup_s": round(setup_s, 3), "solves": {}}
+    log(f"cpu baseline apply: {dt1 * 1e3:.1f} ms single-threaded, {dtn * 1e3:.1f} ms on {threads} threads")
+    if args.cpu_solves:
+        for wname in ("laplacian16_scalar", "random64_bsr3"):
+            q = make_workload(wname)
+            qsub = WORKLOAD_SUB.get(wname)
+            t = time.perf_counter()
+            qs = O.setup(q, qsub)
+            t_setup = time.perf_counter() - t
+            t = time.perf_counter()
+            res = qs.bicgstab(q.b, rtol=args.rtol)
+            t_solve = time.perf_counter() - t
+            out["solves"][wname] = {"iters": res.iters, "status": res.status, "setup_s": round(t_setup, 3),
+                                    "solve_s": round(t_solve, 3), "subdomain": list(qsub), "threads": 1}
+            log(f"cpu baseline {wname}: oracle setup {t_setup:.2f} s, BiCGSTAB {res.iters} it {t_solve:.2f} s")
+    return out
+
+
+# subdomain extents of the oracle solves in the CPU baseline: those the GPU
+# library chooses for the workload on an MI355X (160 KB of LDS, 256 CUs)
+WORKLOAD_SUB = {"laplacian16_scalar": (8, 8, 8), "random64_bsr3": (8, 8, 16)}
+
+
+def compare_workload(args, wname, override, lic_params, dd, torch, np):
+    """One more workload, outside the timed steps: BiCGSTAB to rtol with plain
+    FP64 DD-ILU0, with FP32-stored factors (DD_MIXED), and with the learned
+    correction + FP32-stored factors; iterations, solve seconds, the
+    library's true residual and the residual of each solution recomputed by
+    the oracle's FP64 SpMV on the matrix as generated."""
+    import oracle as O
+    from problems import make_workload
+    log(f"extra workload {wname}: generating")
+    q = make_workload(wname, **override)
+    dev = "cuda:0"
+    ptr_d = torch.as_tensor(q.brow_ptr, device=dev)
+    col_d = torch.as_tensor(q.bcol, device=dev)
+    val_d = torch.as_tensor(q.val.reshape(-1), device=dev)
+    b_d = torch.as_tensor(q.b, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = dd.dd_partition(q.nx, q.ny, q.nz, q.bs, ptr_d, col_d, val_d)
+    dd.ilu0_factor(h, dd.DD_FP64)
+    torch.cuda.synchronize()
+    inf = dd.dd_get_info(h)
+    rec = {"grid": [q.nx, q.ny, q.nz], "seed": q.seed, "subdomain": [inf["sx"], inf["sy"], inf["sz"]],
+           "n_subdomains": inf["nsub"], "setup_s": round(time.perf_counter() - t0, 4)}
+    bn = float(np.linalg.norm(q.b))
+
+    def solve(label):
+        x, info = dd.bicgstab_solve(h, b_d, rtol=args.rtol, maxit=args.maxit)
+        xs = x.cpu().numpy()
+        res_o = float(np.linalg.norm(O.spmv(q.n, q.bs, q.brow_ptr, q.bcol, q.val, xs) - q.b) / bn)
+        rec[label] = {"iters": info["iters"], "status": info["status"], "solve_s": round(info["solve_seconds"], 4),
+                      "rel_res_true": info["rel_res_true"], "oracle_rel_res": res_o,
+                      "restarts": info["restarts"], "fallback": info["fallback"]}
+        log(f"  {wname} {label}: {info['iters']} it, {info['solve_seconds']:.3f} s, "
+            f"oracle residual {res_o:.2e}")
+        return x
+
+    solve("plain_fp64")
+    dd.dd_set_precision(h, dd.DD_MIXED)
+    solve("mixed_fp32_factors")
+    if lic_params is not None and q.bs == 3:
+        t = time.perf_counter()
+        dd.lic_setup(h)
+        dd.lic_set_params(h, lic_params)
+        torch.cuda.synchronize()
+        rec["lic_setup_s"] = round(time.perf_counter() - t, 4)
+        solve("learned_mixed")
+        dd.lic_set_params(h, None)
+    h.close()
+    p64, pl = rec["plain_fp64"], rec.get("learned_mixed")
+    if pl:
+        rec["learned_mixed_speedup_vs_plain_fp64"] = round(p64["solve_s"] / pl["solve_s"], 3)
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -303,8 +446,14 @@ def main():
     ap.add_argument("--sub", default="auto", help="sx,sy,sz or auto")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=5000)
-    ap.add_argument("--cpu-applies", type=int, default=8)
+    ap.add_argument("--cpu-applies", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-solves", type=int, default=1,
+                    help="1: the CPU baseline also times the oracle's BiCGSTAB on the 16^3 scalar "
+                         "and 64^3 random-block workloads")
+    ap.add_argument("--extra", type=int, default=1,
+                    help="1: after the timed steps, compare plain FP64, FP32-factor and learned solves on "
+                         "the anisotropic 160^3 and the 128^3 evaluation workloads")
     ap.add_argument("--mode", default="full", choices=["full", "kernels", "ablation", "rocsparse", "graph"],
                     help="kernels: only a copy kernel of known size and bursts of applies and SpMVs "
                          "(the short program the rocprofv3 counter runs profile); "
@@ -400,13 +549,11 @@ def main():
             torch.cuda.synchronize()
             rec["lic_setup_s"] = time.perf_counter() - t2
             dd.dd_set_precision(h, dd.DD_MIXED)
+            # a failed learned solve is repeated with plain DD-ILU0 inside the
+            # library (dd_set_lic_fallback, on by default); info reports it
             xl, il = dd.bicgstab_solve(h, b_d, rtol=args.rtol, maxit=args.maxit)
-            if il["status"] != 0:  # fallback: plain DD-ILU0
-                log(f"learned solve status {il['status']}: falling back to the plain preconditioner")
-                dd.lic_set_params(h, None)
-                xl, il2 = dd.bicgstab_solve(h, b_d, rtol=args.rtol, maxit=args.maxit)
-                il2["fallback_from"] = il
-                il = il2
+            if il["fallback"]:
+                log("learned solve failed: the result is the plain DD-ILU0 rerun")
             rec["learned"] = il
             rec["x_rel_diff_learned"] = float(torch.linalg.norm(xl - x64) / nx64)
         h.close()
@@ -515,7 +662,7 @@ def main():
                 "lic_setup_s": round(med([r["lic_setup_s"] for r in recs]), 4),
                 "rel_res_true": recs[0]["learned"]["rel_res_true"],
                 "x_rel_diff_vs_fp64": recs[0]["x_rel_diff_learned"],
-                "fallback": "fallback_from" in recs[0]["learned"]},
+                "fallback": bool(recs[0]["learned"]["fallback"])},
         },
         "roofline": {"bound": "hbm", "achieved": round(gbs64, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs64 / HBM_PEAK_GBS, 4),
@@ -526,20 +673,13 @@ def main():
         "cpu_baseline": None,
     }
 
+    if args.extra:
+        out["workloads"] = {}
+        for wname, override in (("aniso160_bsr3", {}), ("lognormal128_eval", {})):
+            out["workloads"][wname] = compare_workload(args, wname, override, lic_params, dd, torch, np)
+
     if not args.no_cpu_baseline:
-        import oracle as O
-        log("cpu baseline: oracle setup + applies on the same matrix")
-        st = O.setup(p, tuple(subd))
-        r = np.random.default_rng(0).standard_normal(p.n * p.bs)
-        st.apply(r)
-        t = time.perf_counter()
-        for _ in range(args.cpu_applies):
-            st.apply(r)
-        dt = (time.perf_counter() - t) / args.cpu_applies
-        out["cpu_baseline"] = {
-            "value": round(bytes64 / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{args.cpu_applies} single-thread oracle DD-ILU0 applies (FP64) on the full "
-                      f"{p.nx}x{p.ny}x{p.nz} matrix, {dt * 1e3:.1f} ms each, bytes counted as for the GPU apply"}
+        out["cpu_baseline"] = cpu_baseline(args, p, tuple(subd), bytes64, np)
     print(json.dumps(out), flush=True)
 
 

@@ -75,7 +75,7 @@ typedef struct {
 } dd_partition_desc;
 
 /* A matrix graph without geometry (Section 3: labels from a graph
- * partitioner; Section 5.4: parts balanced to one size). */
+ * partitioner; Section 5.3: parts balanced to one size). */
 typedef struct {
     int64_t n;                 /* block rows (graph vertices)             */
     int32_t bs;                /* 1 or 3                                  */
@@ -137,7 +137,13 @@ typedef struct {
                                   was switched on with dd_set_profiling)  */
     int32_t fused;             /* 1 when each apply ran in one launch with
                                   the SpMV after it (dd_set_fusion)       */
-    int32_t reserved;
+    int32_t fallback;          /* 1 when a solve with the learned
+                                  correction broke down or missed maxit and
+                                  the result comes from the rerun with plain
+                                  DD-ILU0 (dd_set_lic_fallback): iters,
+                                  rel_res, rel_res_true and status are the
+                                  rerun's, solve_seconds, applies and
+                                  apply_seconds cover both runs           */
 } dd_solve_info;
 
 /* Automatic subdomain extents (host only, no device access).
@@ -301,6 +307,15 @@ int dd_set_profiling(dd_handle h, int32_t on);
  * one workgroup per CU, and at 160^3 (640 subdomains) a fused iteration
  * measured 8% slower than two launches. */
 int dd_set_fusion(dd_handle h, int32_t on);
+
+/* Fallback of a learned solve (on = 1, the default; 0 = off).  When the
+ * learned interface correction is on (lic_set_params / lic_set_coeffs) and
+ * bicgstab_solve with it ends in DD_EBREAKDOWN or DD_ENOCONV, the solve is
+ * repeated from the caller's initial guess with the correction off (plain
+ * DD-ILU0, which the correction is meant to improve on), and
+ * dd_solve_info.fallback is set.  The correction stays on for later calls.
+ * The initial guess is kept in the handle's Krylov workspace meanwhile. */
+int dd_set_lic_fallback(dd_handle h, int32_t on);
 
 /* Record the residual history of later bicgstab_solve calls on h: entry j
  * of hist (device double[len]) receives ||r_j||/||b|| after iteration j

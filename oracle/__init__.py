@@ -341,7 +341,7 @@ class OracleSetup:
         return apply(self.n, self.bs, self.tptr, self.tcol, self.f, r)
 
     def apply_fp32_factors(self, r, round_input=True):
-        """FP32-factor variants (task addition, not in the paper): the FP64
+        """FP32-factor variants (an addition to the method; not in the paper): the FP64
         apply run with L, inv_D and Uhat rounded to FP32 (round to nearest
         even) and, when round_input, with r rounded to FP32 as well."""
         f32 = np.asarray(self.f, dtype=np.float64).astype(np.float32).astype(np.float64)

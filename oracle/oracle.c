@@ -129,7 +129,7 @@ int o_partition(int nx, int ny, int nz, int sx, int sy, int sz, int32_t *part_id
 }
 
 /* ------------------------------------------------------------------ */
-/* Section 3 (graph-based labels) and Section 5.4 (uniform part sizes): */
+/* Section 3 (graph-based labels) and Section 5.3 (uniform part sizes): */
 /* partition a matrix graph without geometry into parts of exactly S    */
 /* vertices.  The paper uses METIS and then balances the parts to one   */
 /* size by hand; METIS is not available, so this is a stated reading:   */

@@ -566,8 +566,42 @@ extern "C" int bicgstab_solve(dd_handle h, const double *b, double *x, double rt
     if (!h->factored) return h->fail(DD_ESTATE, "bicgstab_solve before ilu0_factor");
     if (!b || !x || b == x) return h->fail(DD_EINVAL, "bicgstab_solve: b and x must be distinct device buffers");
     if (!(rtol > 0.0) || maxit < 0) return h->fail(DD_EINVAL, "bicgstab_solve: bad rtol or maxit");
-    if (h->pc_kind == 0) RCHK(prepare_variant(h, "bicgstab_solve", as_stream(hip_stream)));
-    return bicgstab_run(h, b, x, rtol, maxit, as_stream(hip_stream), info);
+    hipStream_t st = as_stream(hip_stream);
+    if (h->pc_kind == 0) RCHK(prepare_variant(h, "bicgstab_solve", st));
+    const bool learned = h->pc_kind == 0 && h->lic.active;
+    if (!learned || !h->lic_fallback) return bicgstab_run(h, b, x, rtol, maxit, st, info);
+    // A learned solve that breaks down or misses maxit is repeated with plain
+    // DD-ILU0 from the caller's initial guess, kept in the workspace's last
+    // vector (the solve overwrites x with its last iterate).
+    RCHK(krylov_workspace(h));
+    const int64_t m = h->n * h->bs;
+    double *x0 = h->kv + (int64_t)(kKrylovVectors - 1) * m;
+    HCHK(hipMemcpyAsync(x0, x, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+    dd_solve_info first{};
+    const int rc = bicgstab_run(h, b, x, rtol, maxit, st, &first);
+    if (rc != DD_EBREAKDOWN && rc != DD_ENOCONV) {
+        if (info) *info = first;
+        return rc;
+    }
+    HCHK(hipMemcpyAsync(x, x0, m * sizeof(double), hipMemcpyDeviceToDevice, st));
+    h->lic.active = 0;
+    dd_solve_info second{};
+    const int rc2 = bicgstab_run(h, b, x, rtol, maxit, st, &second);
+    h->lic.active = 1;
+    if (info) {
+        *info = second;
+        info->fallback = 1;
+        info->solve_seconds += first.solve_seconds;
+        info->applies += first.applies;
+        info->apply_seconds += first.apply_seconds;
+    }
+    return rc2;
+}
+
+extern "C" int dd_set_lic_fallback(dd_handle h, int32_t on) {
+    if (!h) return set_global_error(DD_EINVAL, "dd_set_lic_fallback: null handle");
+    h->lic_fallback = on ? 1 : 0;
+    return DD_OK;
 }
 
 extern "C" int dd_set_apply_variant(dd_handle h, int32_t variant) {

@@ -1,5 +1,5 @@
 // Partition labels for a matrix graph without geometry (Section 3: labels
-// from a graph partitioner; Section 5.4: parts balanced to one size), as a
+// from a graph partitioner; Section 5.3: parts balanced to one size), as a
 // stand-in for METIS: recursive BFS bisection into parts of exactly S
 // vertices.  A segment of k parts (k*S vertices, all labelled with its first
 // part number b) splits, if k > 1, by a BFS inside the segment from its

@@ -128,13 +128,14 @@ struct dd_ctx {
     int32_t *scan_tmp = nullptr;
     int64_t scan_tmp_len = 0;
     // Krylov workspace (allocated on first solve)
-    double *kv = nullptr;       // 9 vectors of n*bs
+    double *kv = nullptr;       // kKrylovVectors vectors of n*bs
     double *partials = nullptr; // [8 * spmv_part_stride] per-workgroup partial sums
     int32_t spmv_part_stride = 0;
     int32_t max_row_a = 0;               // most blocks in a row of the full matrix
     int32_t ell_state = 0;               // sliced-ELL copy for the SpMV: 0 not built, 1 ready, -1 not used
     int32_t *ell_col = nullptr;          // [groups][kUnroll][rows per wavefront]
     double *ell_val = nullptr;           // the same slots, bs*bs values each
+    int32_t lic_fallback = 1;            // rerun a failed learned solve with plain DD-ILU0
     int32_t fuse = 0;                    // apply + SpMV as one launch inside bicgstab_solve (opt-in)
     int32_t *fdep = nullptr;             // [2 nsub] dependency ranges of the SpMV tiles
     uint32_t *fflag = nullptr;           // [nsub] per-subdomain completion epochs
@@ -214,6 +215,11 @@ hipError_t launch_permute(int64_t n, int bs, const int32_t *map, const double *i
                           hipStream_t st);
 int bicgstab_run(dd_ctx *h, const double *b, double *x, double rtol, int32_t maxit,
                  hipStream_t st, dd_solve_info *info);
+// vectors of n*bs in the Krylov workspace: ten for the recurrence, one to
+// keep the initial guess while a learned solve may still fall back
+constexpr int kKrylovVectors = 11;
+// the Krylov workspace of bicgstab_run (allocated once per handle)
+int krylov_workspace(dd_ctx *h);
 
 // global ILU0
 int global_factor(dd_ctx *h, hipStream_t st);

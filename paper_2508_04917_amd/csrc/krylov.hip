@@ -610,6 +610,7 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
         info->restarts = restarts;
         info->apply_seconds = apply_ms * 1e-3;
         info->fused = fused ? 1 : 0;
+        info->fallback = 0;
     }
     if (status == DD_EBREAKDOWN) return h->fail(DD_EBREAKDOWN, "BiCGSTAB breakdown at iteration %d", hk.iters);
     if (status == DD_ENOCONV && hk.state == ST_CONV)
@@ -621,20 +622,25 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
     return DD_OK;
 }
 
+int krylov_workspace(dd_ctx *h) {
+    if (h->kv) return DD_OK;
+    int rc = h->alloc(&h->kv, kKrylovVectors * h->n * h->bs);
+    if (rc) return rc;
+    const int rpb = (kWave / h->bs) * (kRedT / kWave);
+    h->spmv_part_stride = (int)std::max<int64_t>((h->n + rpb - 1) / rpb, kMaxGrid);
+    rc = h->alloc(&h->partials, (int64_t)kStride * h->spmv_part_stride);
+    if (rc) return rc;
+    rc = h->alloc(&h->ks, 1);
+    if (rc) return rc;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&h->ks_host), sizeof(KrylovScalars));
+    if (e != hipSuccess) return h->fail(DD_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+    return DD_OK;
+}
+
 int bicgstab_run(dd_ctx *h, const double *b, double *x, double rtol, int32_t maxit, hipStream_t st,
                  dd_solve_info *info) {
-    if (!h->kv) {
-        int rc = h->alloc(&h->kv, 10 * h->n * h->bs);
-        if (rc) return rc;
-        const int rpb = (kWave / h->bs) * (kRedT / kWave);
-        h->spmv_part_stride = (int)std::max<int64_t>((h->n + rpb - 1) / rpb, kMaxGrid);
-        rc = h->alloc(&h->partials, (int64_t)kStride * h->spmv_part_stride);
-        if (rc) return rc;
-        rc = h->alloc(&h->ks, 1);
-        if (rc) return rc;
-        hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&h->ks_host), sizeof(KrylovScalars));
-        if (e != hipSuccess) return h->fail(DD_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
-    }
+    int rc0 = krylov_workspace(h);
+    if (rc0) return rc0;
     build_spmv_layout(h, st);
     if (h->fuse && !h->fdep && !fused_unsupported(h)) {
         int rc = h->alloc(&h->fdep, 2 * (int64_t)h->nsub);

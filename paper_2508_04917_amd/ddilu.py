@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "DD_OK", -1: "DD_EINVAL", -2: "DD_ENOTDIV", -3: "DD_ELDS", -4
 # every symbol include/ddilu.h declares
 EXPORTS = ("dd_auto_subdims", "dd_device_caps", "dd_partition", "dd_partition_graph", "dd_get_info", "dd_get_partition",
            "dd_get_reordered", "ilu0_factor", "dd_set_precision", "dd_get_levels", "dd_get_factors",
-           "dd_trsv_apply", "dd_spmv", "bicgstab_solve", "dd_set_apply_variant", "dd_set_fusion", "dd_set_profiling",
+           "dd_trsv_apply", "dd_spmv", "bicgstab_solve", "dd_set_apply_variant", "dd_set_fusion", "dd_set_lic_fallback",
+           "dd_set_profiling",
            "dd_set_residual_history", "dd_global_factor", "dd_global_apply", "dd_set_preconditioner",
            "lic_setup", "lic_get_faces", "lic_set_params", "lic_set_coeffs", "lic_get_coeffs",
            "dd_apply_adjoint", "lic_targets", "lic_loss_grad", "lic_adam", "lic_train",
@@ -62,7 +63,7 @@ class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("rel_res", C.c_double),
                 ("rel_res_true", C.c_double), ("solve_seconds", C.c_double),
                 ("applies", C.c_int32), ("restarts", C.c_int32), ("apply_seconds", C.c_double),
-                ("fused", C.c_int32), ("reserved", C.c_int32)]
+                ("fused", C.c_int32), ("fallback", C.c_int32)]
 
 
 _lib = None
@@ -93,6 +94,7 @@ def lib():
             "bicgstab_solve": (C.c_int, [vp, vp, vp, C.c_double, i32, vp, C.POINTER(SolveInfo)]),
             "dd_set_apply_variant": (C.c_int, [vp, i32]),
             "dd_set_fusion": (C.c_int, [vp, i32]),
+            "dd_set_lic_fallback": (C.c_int, [vp, i32]),
             "dd_set_profiling": (C.c_int, [vp, i32]),
             "dd_set_residual_history": (C.c_int, [vp, vp, i32]),
             "dd_global_factor": (C.c_int, [vp, vp]),
@@ -305,6 +307,10 @@ def dd_set_apply_variant(h: Handle, variant: int):
 
 def dd_set_fusion(h: Handle, on: bool):
     _check(lib().dd_set_fusion(h.ptr, 1 if on else 0), h)
+
+
+def dd_set_lic_fallback(h: Handle, on: bool):
+    _check(lib().dd_set_lic_fallback(h.ptr, 1 if on else 0), h)
 
 
 def dd_set_profiling(h: Handle, on: bool):

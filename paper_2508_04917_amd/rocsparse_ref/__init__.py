@@ -1,7 +1,7 @@
 """ctypes binding of the rocSPARSE baseline (``librocsparse_ref.so``, built
 by ``paper_2508_04917_amd.build``): rocSPARSE's block ILU0 and its two block
 triangular solves on a BSR matrix already on the device, as the vendor
-reference the paper compares its apply against (Section 5.3).  Used by
+reference the paper compares its apply against (Section 5.2, Table 4).  Used by
 ``bench.py --mode rocsparse`` and its parity test only."""
 
 import ctypes as C

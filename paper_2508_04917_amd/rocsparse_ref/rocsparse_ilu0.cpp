@@ -1,4 +1,4 @@
-// Vendor-library baseline for the apply comparison of Section 5.3: rocSPARSE's
+// Vendor-library baseline for the apply comparison of Section 5.2 (Table 4): rocSPARSE's
 // block ILU0 (bsrilu0) and its two block triangular solves (bsrsv, lower with
 // unit diagonal, then upper), called as a black box on a BSR matrix already
 // on the device.  Built as its own library so that the DD-ILU0 library does

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from parity import check_close, check_layers
 from problems import lic_init_params, lognormal_problem, probe_vectors
 
 torch = pytest.importorskip("torch")
@@ -58,7 +59,7 @@ def test_global_apply_parity(prob):
     Z = np_(dd.dd_global_apply(s.h, cu(R.reshape(-1)), nrhs=2)).reshape(2, -1)
     for q in range(2):
         zo = L.apply_global(R[q])
-        assert np.linalg.norm(Z[q] - zo) / np.linalg.norm(zo) < 1e-12
+        check_close(Z[q], zo, 3, 1e-12, what=f"global apply probe {q}")
 
 
 def test_global_preconditioned_bicgstab(prob):
@@ -78,7 +79,7 @@ def test_adjoint_apply_parity(prob):
     g = np.random.default_rng(4).standard_normal(st.n * 3)
     a = np_(dd.dd_apply_adjoint(s.h, cu(g)))
     ao = O.apply_transpose(st.n, 3, st.tptr, st.tcol, st.f, g)
-    assert np.linalg.norm(a - ao) / np.linalg.norm(ao) < 1e-12
+    check_close(a, ao, 3, 1e-12, what="adjoint apply")
 
 
 def test_zero_output_is_plain_apply(prob):
@@ -102,7 +103,7 @@ def test_mlp_coefficients(prob):
     finally:
         dd.lic_set_params(s.h, None)
     Co = L.coeffs(P)
-    assert np.linalg.norm(Cg - Co) / np.linalg.norm(Co) < 1e-5
+    check_close(Cg, Co, 9, 1e-5, what="MLP coefficients per face")
 
 
 @pytest.mark.parametrize("variant", [1, 3])
@@ -118,7 +119,7 @@ def test_corrected_apply_parity(prob, variant):
         dd.lic_set_coeffs(s.h, None)
         dd.dd_set_apply_variant(s.h, 0)
     zo = L.apply(Co.astype(np.float64), r)
-    assert np.linalg.norm(zg - zo) / np.linalg.norm(zo) < 1e-12
+    check_close(zg, zo, 3, 1e-12, what=f"corrected apply v{variant}")
 
 
 def test_targets_loss_and_gradient(prob):
@@ -130,7 +131,7 @@ def test_targets_loss_and_gradient(prob):
     Zs_g, den_g = dd.lic_targets(s.h, cu(R))
     Zs_o = np.stack([L.apply_global(r) for r in R])
     den_o = np.array([((st.apply(r) - z) ** 2).sum() for r, z in zip(R, Zs_o)])
-    assert np.linalg.norm(np_(Zs_g) - Zs_o) / np.linalg.norm(Zs_o) < 1e-12
+    check_close(np_(Zs_g), Zs_o, 3, 1e-12, what="global ILU0 targets")
     assert np.allclose(np_(den_g), den_o, rtol=1e-10)
     P = trained_like_params()
     loss_g, grad_g = dd.lic_loss_grad(s.h, cu(P, torch.float32), cu(R), Zs_g, den_g)
@@ -139,6 +140,7 @@ def test_targets_loss_and_gradient(prob):
     assert abs(float(loss_g.item()) - loss_o) / loss_o < 1e-5
     gg = np_(grad_g).astype(np.float64)
     assert np.linalg.norm(gg - grad_o) / np.linalg.norm(grad_o) < 1e-3
+    check_layers(gg, grad_o, 1e-3, what="gradient")
 
 
 def test_adam_step():
@@ -167,3 +169,51 @@ def test_training_reduces_loss(prob):
     hist = dd.lic_train([s.h], [R], [Zs], [den], params, m, v, 30, order, lr=1e-3)
     assert abs(hist[0] - 1.0) < 1e-6  # untrained correction is zero: loss 1
     assert hist[-1] < hist[0]
+
+
+@pytest.fixture(scope="module")
+def prob16():
+    """The training shape: 16^3 subdomains (here 32x32x16 cells, two by two
+    by one subdomains), where lic_train runs."""
+    print("[lic] problem 32x32x16, subdomains 16x16x16", flush=True)
+    p = lognormal_problem(32, 32, 16, seed=43, sigma=2.0, corr_len=4.0)
+    s = DDSolver.from_problem(p, sub=(16, 16, 16))
+    st = O.setup(p, (16, 16, 16))
+    L = O.LicOracle(st)
+    dd.lic_setup(s.h)
+    dd.dd_global_factor(s.h)
+    return p, s, st, L
+
+
+def test_adjoint_apply_parity_training_shape(prob16):
+    p, s, st, L = prob16
+    for seed in (4, 5):
+        g = np.random.default_rng(seed).standard_normal(st.n * 3)
+        a = np_(dd.dd_apply_adjoint(s.h, cu(g)))
+        ao = O.apply_transpose(st.n, 3, st.tptr, st.tcol, st.f, g)
+        check_close(a, ao, 3, 1e-12, what=f"adjoint apply 16^3 seed {seed}")
+
+
+def test_loss_and_gradient_training_shape(prob16):
+    """lic_loss_grad at the shape lic_train runs on, against the oracle:
+    targets per block row to 1e-12, loss to 1e-5, gradient to 1e-3 in norm
+    and per layer."""
+    p, s, st, L = prob16
+    Q = 4
+    R = probe_vectors(43, Q, st.n * 3)
+    Zs_g, den_g = dd.lic_targets(s.h, cu(R))
+    Zs_o = np.stack([L.apply_global(r) for r in R])
+    den_o = np.array([((st.apply(r) - z) ** 2).sum() for r, z in zip(R, Zs_o)])
+    check_close(np_(Zs_g), Zs_o, 3, 1e-12, what="16^3 targets")
+    assert np.allclose(np_(den_g), den_o, rtol=1e-10)
+    P = trained_like_params(11)
+    loss_g, grad_g = dd.lic_loss_grad(s.h, cu(P, torch.float32), cu(R), Zs_g, den_g)
+    P32 = P.astype(np.float32).astype(np.float64)
+    loss_o, grad_o = L.loss_and_grad(P32, R, Zs_o, den_o)
+    lerr = abs(float(loss_g.item()) - loss_o) / loss_o
+    gg = np_(grad_g).astype(np.float64)
+    gerr = np.linalg.norm(gg - grad_o) / np.linalg.norm(grad_o)
+    print(f"[lic 16^3] loss {loss_o:.6f} rel err {lerr:.2e}, gradient rel err {gerr:.2e}", flush=True)
+    assert lerr < 1e-5
+    assert gerr < 1e-3
+    check_layers(gg, grad_o, 1e-3, what="16^3 gradient")

@@ -5,14 +5,20 @@ vectors to relative 1e-12.  BiCGSTAB iteration counts are only defined up to
 rounding: the GPU sums its dot products in a different (fixed) order than the
 oracle, and on these nonsymmetric, erratically converging problems a
 perturbation of b at unit roundoff already moves the oracle's own exit by
-several iterations (Section 5.4 likewise reports about +-10% from summation
+several iterations (Section 5.3 likewise reports about +-10% from summation
 order alone).  So the GPU count must lie in the band the oracle spans over
-such perturbed right-hand sides, widened by 2."""
+such perturbed right-hand sides, widened by 2, and the first iterations'
+residual history must match the oracle's to 1e-8 (a recurrence error shows
+there at once).  Floating-point results are compared per block row (or
+block, face) as well as in norm (tests/parity.py)."""
+
+import os
 
 import numpy as np
 import pytest
 
 import oracle as O
+from parity import check_close, check_spmv
 from problems import laplacian_scalar, lognormal_problem, random_blocks
 
 torch = pytest.importorskip("torch")
@@ -90,9 +96,7 @@ def test_factors_fp64(name):
     ptr, col, f = P.dd_get_factors(s.h)
     assert np.array_equal(np_(ptr), st.tptr)
     assert np.array_equal(np_(col), st.tcol)
-    fo = st.f.reshape(-1)
-    fg = np_(f)
-    assert np.linalg.norm(fg - fo) / np.linalg.norm(fo) < RTOL_FP64
+    check_close(np_(f), st.f, st.bs * st.bs, RTOL_FP64, what=f"{name} factor blocks")
 
 
 # apply kernels: 1 plain level loop, 2 workgroup-pass chunks with the next
@@ -112,8 +116,7 @@ def test_apply_fp64(name, variant):
             r = rng.standard_normal(st.n * st.bs)
             z_o = st.apply(r)
             z_g = np_(s.apply(torch.as_tensor(r, device="cuda")))
-            err = np.linalg.norm(z_g - z_o) / np.linalg.norm(z_o)
-            assert err < RTOL_FP64, f"{name}: rel err {err:.3e}"
+            check_close(z_g, z_o, st.bs, RTOL_FP64, what=f"{name} apply v{variant}")
     finally:
         P.ddilu.dd_set_apply_variant(s.h, 0)
 
@@ -138,9 +141,7 @@ def test_apply_ablation_fp64(name, variant):
             r = rng.standard_normal(st.n * st.bs)
             z_o = st.apply(r)
             z_g = np_(s.apply(torch.as_tensor(r, device="cuda")))
-            assert np.isfinite(z_g).all(), f"{name}: non-finite output"
-            err = np.linalg.norm(z_g - z_o) / np.linalg.norm(z_o)
-            assert err < RTOL_FP64, f"{name}: rel err {err:.3e}"
+            check_close(z_g, z_o, st.bs, RTOL_FP64, what=f"{name} ablation v{variant}")
     finally:
         P.ddilu.dd_set_apply_variant(s.h, 0)
 
@@ -175,16 +176,22 @@ def test_bicgstab_with_ablation(variant):
     assert abs(i1["iters"] - i0["iters"]) <= max(3, i0["iters"] // 10), (i0["iters"], i1["iters"])
 
 
-# FP32 factors (task addition (1), not in the paper).
+# FP32 factors (an addition to the method; not in the paper).
 # DD_FP32: the GPU computes in FP32 throughout the apply; the oracle applies
 # FP32-rounded factors to the FP32-rounded input in FP64.  The difference is
 # FP32 arithmetic rounding, bounded by (levels) x u32 x growth; 2e-5 relative
-# holds with margin for these problems (measured values are printed).
+# in norm holds with margin for these problems (measured values are
+# printed).  Per block row the bound is 2e-4 with a floor of 1e-3 of the
+# largest row: rows whose entries cancel carry FP32 errors up to 1e-4 of
+# their own size (an FP32 emulation of the sweeps on the CPU measured 1.2e-5
+# at that floor on these shapes).
 # DD_MIXED: FP32-stored factors, FP64 arithmetic; the oracle applies the
 # FP32-rounded factors to the FP64 input.  Only FP64 rounding and the rare
 # factor entry whose FP32 rounding differs by one unit (the GPU rounds its
-# own FP64 factors, equal to the oracle's to ~1e-15) separate them: 1e-10.
+# own FP64 factors, equal to the oracle's to ~1e-15) separate them: 1e-10,
+# in norm and per block row.
 RTOL_FP32 = 2e-5
+ROW_TOL_FP32, ROW_FLOOR_FP32 = 2e-4, 1e-3
 RTOL_MIXED = 1e-10
 
 
@@ -200,10 +207,13 @@ def test_apply_reduced_precision(name, variant, precision):
         zo = st.apply_fp32_factors(r, round_input=(precision == "fp32"))
         z64o = st.apply(r)
         zg = np_(s.apply(torch.as_tensor(r, device="cuda")))
-        err = np.linalg.norm(zg - zo) / np.linalg.norm(zo)
         err64 = np.linalg.norm(zg - z64o) / np.linalg.norm(z64o)
-        print(f"[{name} v{variant} {precision}] vs FP32-factor oracle {err:.2e}, vs FP64 oracle {err64:.2e}")
-        assert err < (RTOL_FP32 if precision == "fp32" else RTOL_MIXED)
+        print(f"[{name} v{variant} {precision}] vs FP64 oracle {err64:.2e}")
+        if precision == "fp32":
+            check_close(zg, zo, st.bs, ROW_TOL_FP32, floor=ROW_FLOOR_FP32, norm_tol=RTOL_FP32,
+                        what=f"{name} v{variant} fp32 apply")
+        else:
+            check_close(zg, zo, st.bs, RTOL_MIXED, what=f"{name} v{variant} mixed apply")
     finally:
         s.set_precision(P.DD_FP64)
         P.ddilu.dd_set_apply_variant(s.h, 0)
@@ -217,7 +227,7 @@ def test_spmv(name):
     x = np.random.default_rng(5).standard_normal(st.n * st.bs)
     y_o = st.spmv(x)
     y_g = np_(s.spmv(torch.as_tensor(x, device="cuda")))
-    assert np.linalg.norm(y_g - y_o) / np.linalg.norm(y_o) < 1e-14
+    check_spmv(st, x, y_g, y_o, name)
     inf = P.ddilu.dd_get_info(s.h)
     assert inf["max_row_blocks"] == int(np.diff(st.aptr).max())
     assert inf["spmv_layout"] == 1
@@ -231,29 +241,64 @@ def test_apply_deterministic():
         assert torch.equal(s.apply(r), z1)
 
 
-def oracle_iteration_band(st, b, k=4, seed=99):
-    """Oracle iteration counts for b and for k copies of b perturbed at 1e-15."""
-    its = [st.bicgstab(b, rtol=1e-8).iters]
-    rng = np.random.default_rng(seed)
-    for _ in range(k):
-        its.append(st.bicgstab(b * (1 + 1e-15 * rng.standard_normal(b.size)), rtol=1e-8).iters)
-    return min(its), max(its)
+GOLDEN_BANDS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "bicgstab_bands.txt")
 
 
-@pytest.mark.parametrize("name", ["lap16_8cube", "rand_ragged", "logn_24_32_40"])
+def oracle_band(name):
+    """(sub, iterations for b, min, max) of the oracle over b and 8 copies of
+    b perturbed at 1e-15, written by golden/make_bicgstab_bands.py."""
+    with open(GOLDEN_BANDS) as f:
+        for line in f:
+            w = line.split()
+            if w and w[0] == name:
+                return tuple(int(v) for v in w[1:4]), int(w[4]), int(w[5]), int(w[6])
+    raise KeyError(name)
+
+
+# Residual history over the first HIST_K iterations: the recurrence is the
+# same on both sides up to rounding (factors to ~1e-16, dot products summed
+# in another order), so the relative residuals agree far below 1e-8 early on
+# (the oracle's own histories under 1e-15 perturbations of b differ by at
+# most 1e-12 over the first 10 entries on these cases), while a wrong
+# coefficient or sign anywhere in Algorithm 1 changes them at O(1) within
+# the first two iterations.
+HIST_K = 10
+HIST_RTOL = 1e-8
+
+
+@pytest.mark.parametrize("name", ["lap16_8cube", "rand_ragged", "logn_24_32_40", "rand64_auto"])
 def test_bicgstab_parity(name):
     p, s, st = case(name)
+    sub, it_b, lo, hi = oracle_band(name)
+    assert (s.info["sx"], s.info["sy"], s.info["sz"]) == sub
+    print(f"[bicgstab {name}] oracle solve", flush=True)
     ref = st.bicgstab(p.b, rtol=1e-8)
     assert ref.status == 0
-    lo, hi = oracle_iteration_band(st, p.b)
+    assert ref.iters == it_b, "stale golden band: regenerate it with golden/make_bicgstab_bands.py"
     b = torch.as_tensor(p.b, device="cuda")
-    x, info = s.solve(b, rtol=1e-8)
+    hist = torch.full((20001,), float("nan"), dtype=torch.float64, device="cuda")
+    P.ddilu.dd_set_residual_history(s.h, hist)
+    try:
+        x, info = s.solve(b, rtol=1e-8)
+    finally:
+        P.ddilu.dd_set_residual_history(s.h, None)
+    print(f"[bicgstab {name}] GPU {info['iters']} it, oracle {ref.iters} (band {lo}..{hi})", flush=True)
     assert info["status"] == 0
+    hg = np_(hist)[: info["iters"] + 1]
+    k = min(HIST_K + 1, len(hg), len(ref.history))
+    hrel = np.abs(hg[:k] / ref.history[:k] - 1.0)
+    print(f"[bicgstab {name}] history rel diff over {k} entries: max {hrel.max():.2e}", flush=True)
+    assert hrel.max() <= HIST_RTOL, (hg[:k], ref.history[:k])
     assert lo - 2 <= info["iters"] <= hi + 2, (info["iters"], lo, hi)
     assert info["rel_res"] <= 1e-8
     assert info["rel_res_true"] <= 2e-8
     xg = np_(x)
-    assert np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x) < 1e-5
+    # the GPU solution's residual recomputed by the oracle's FP64 SpMV
+    res_o = np.linalg.norm(st.unpermute(st.spmv(st.permute(xg))) - p.b) / np.linalg.norm(p.b)
+    xerr = np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x)
+    print(f"[bicgstab {name}] oracle residual of the GPU x {res_o:.2e}, x vs oracle x {xerr:.2e}", flush=True)
+    assert res_o <= 2e-8
+    assert xerr < 1e-5
     # same solve again: bit-identical (deterministic reductions)
     x2, info2 = s.solve(b, rtol=1e-8)
     assert info2["iters"] == info["iters"] and torch.equal(x2, x)

@@ -4,12 +4,17 @@ are scale invariant, forward/backward/Adam agree with independent library
 implementations, the analytic gradient agrees with central differences, and
 the free per-face least-squares fit bounds what any network can reach."""
 
+import os
+from fractions import Fraction
+
 import numpy as np
 import pytest
 import torch
 
 import oracle as O
-from problems import lic_init_params, lognormal_problem, probe_vectors
+from problems import Problem, lic_init_params, lognormal_problem, probe_vectors
+
+GOLDEN_FEATURES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "lic_features_3cell.txt")
 
 
 @pytest.fixture(scope="module")
@@ -48,6 +53,49 @@ def test_features_scale_invariant(small):
     assert np.allclose(X2, L.X, rtol=1e-14, atol=1e-15)
     # the diagonal blocks of an interior cell: trace part 3, coupling about -1/6 each
     assert np.all(np.abs(L.X[:, 0] + L.X[:, 4] + L.X[:, 8]) > 0)
+
+
+def _golden_features():
+    blocks, faces = {}, []
+    with open(GOLDEN_FEATURES) as f:
+        for line in f:
+            w = line.split()
+            if not w or w[0].startswith("#"):
+                continue
+            if w[0] == "block":
+                blocks[(int(w[1]), int(w[2]))] = np.array([float(v) for v in w[3:12]]).reshape(3, 3)
+            elif w[0] == "face":
+                faces.append((int(w[1]), int(w[2]), int(w[3]), [float(Fraction(v)) for v in w[4:]]))
+    return blocks, faces
+
+
+def test_features_hand_worked():
+    """Faces and features of a three-cell chain cut into single cells,
+    against values worked by hand (golden/lic_features_3cell.txt).  Every
+    sigma is an exact integer (sqrt(324)/3, sqrt(81)/3), so each feature is
+    one correctly rounded division and must equal the fraction exactly."""
+    blocks, faces = _golden_features()
+    n = 3
+    ptr = [0]
+    col, val = [], []
+    for I in range(n):
+        for J in range(n):
+            if (I, J) in blocks:
+                col.append(J)
+                val.append(blocks[(I, J)])
+        ptr.append(len(col))
+    p = Problem(name="chain3", nx=3, ny=1, nz=1, bs=3, brow_ptr=np.array(ptr, dtype=np.int32),
+                bcol=np.array(col, dtype=np.int32), val=np.array(val).reshape(-1), b=np.zeros(9), seed=0)
+    st = O.setup(p, (1, 1, 1))
+    L = O.LicOracle(st)
+    fI, fJ, fq = L.faces
+    assert list(zip(fI.tolist(), fJ.tolist())) == [(f[0], f[1]) for f in faces]
+    assert np.array_equal(st.acol[fq], fJ)
+    for k, (I, J, sigma, x) in enumerate(faces):
+        assert np.array_equal(L.X[k], np.array(x)), (I, J, L.X[k], x)
+    # the same features through the plain wrapper on the unreordered matrix
+    X = O.lic_features(p.brow_ptr, p.bcol, p.val, L.faces)
+    assert np.array_equal(X, L.X)
 
 
 def test_mlp_forward_backward_against_torch(small):

@@ -55,10 +55,22 @@ MUTATIONS = [
      "for (int d = 0; d < bs; ++d) s += f[p * bb + d * bs + c] * a[K * bs + d];",
      "for (int d = 0; d < bs; ++d) s += f[p * bb + c * bs + d] * a[K * bs + d];",
      ["test_apply_transpose_adjoint", "test_least_squares_bound"]),
+    ("features_diagonal_blocks_swapped",
+     "x[e] = Aii[e] / sigma;", "x[e] = Ajj[e] / sigma;",
+     ["test_features_hand_worked"]),
+    ("features_reverse_coupling",
+     "*Aij = val + (int64_t)fq[f] * 9,", "*Aij = val + find_col(ptr, col, fJ[f], fI[f]) * 9,",
+     ["test_features_hand_worked"]),
+    ("features_coupling_transposed",
+     "x[9 + e] = Aij[e] / sigma;", "x[9 + e] = Aij[(e % 3) * 3 + e / 3] / sigma;",
+     ["test_features_hand_worked"]),
+    ("features_sigma_over_nine",
+     "sqrt(fabs(ti) * fabs(tj)) / 3.0;", "sqrt(fabs(ti) * fabs(tj)) / 9.0;",
+     ["test_features_hand_worked"]),
 ]
 
 LIC_PINS = ("test_mlp_forward_backward_against_torch", "test_loss_gradient_central_differences",
-            "test_least_squares_bound")
+            "test_least_squares_bound", "test_features_hand_worked")
 
 
 @pytest.mark.parametrize("name,old,new,pins", MUTATIONS, ids=[m[0] for m in MUTATIONS])
