@@ -42,24 +42,65 @@ def unit_ratio(got, ref, unit, floor=FLOOR):
     return float((d / scale).max())
 
 
-def check_close(got, ref, unit, tol, floor=FLOOR, what="", norm_tol=None):
+def check_close(got, ref, unit, tol, floor=FLOOR, what="", norm_tol=None, scale=None):
     """Assert per-unit and norm agreement; print the measured values.
 
     unit: entries per unit (bs for a vector's block rows, bs*bs for factor
     blocks, 27 for a face's features, 9 for a face's coefficients).
-    norm_tol: bound on ||got - ref|| / ||ref|| (default tol).  Returns
-    (norm error, worst unit ratio)."""
+    norm_tol: bound on ||got - ref|| / ||ref|| (default tol).
+    scale: per-unit magnitudes to measure the error against instead of
+    ||ref_u|| + floor * max ||ref_v|| (see apply_scale).  Returns (norm
+    error, worst unit ratio)."""
     g = np.asarray(got, dtype=np.float64).reshape(-1)
     r = np.asarray(ref, dtype=np.float64).reshape(-1)
     assert np.isfinite(g).all(), f"{what}: non-finite entries"
     rn = np.linalg.norm(r)
     nerr = float(np.linalg.norm(g - r) / rn) if rn > 0 else float(np.linalg.norm(g))
-    uerr = unit_ratio(g, r, unit, floor)
+    if scale is None:
+        uerr = unit_ratio(g, r, unit, floor)
+        how = f"floor {floor:g}"
+    else:
+        d = np.linalg.norm((g - r).reshape(-1, unit), axis=1)
+        sc = np.asarray(scale, dtype=np.float64)
+        assert sc.shape == d.shape and (sc > 0).all()
+        uerr = float((d / sc).max()) if d.size else 0.0
+        how = "against the magnitude recursion"
     print(f"[parity] {what}: norm {nerr:.2e}, worst unit {uerr:.2e} "
-          f"(tol {tol:g}, floor {floor:g})", flush=True)
+          f"(tol {tol:g}, {how})", flush=True)
     assert nerr <= (tol if norm_tol is None else norm_tol), f"{what}: norm error {nerr:.3e}"
     assert uerr <= tol, f"{what}: worst unit error {uerr:.3e}"
     return nerr, uerr
+
+
+def magnitude_factors(ptr, col, f, bs):
+    """ILDU0 factors with every off-diagonal block replaced by -|block| and
+    every diagonal (inv_D) block by |block| (entrywise): the oracle's apply,
+    which subtracts the off-diagonal products, then runs the magnitude
+    recursion  y'_I = |r_I| + sum_J |L_IJ| y'_J,
+    z'_I = |inv_D_I| y'_I + sum_K |Uhat_IK| z'_K  on |r|."""
+    n = len(ptr) - 1
+    rowid = np.repeat(np.arange(n), np.diff(ptr))
+    F = np.abs(np.asarray(f, dtype=np.float64).reshape(-1, bs * bs)).copy()
+    F[np.asarray(col) != rowid] *= -1.0
+    return F
+
+
+def apply_scale(n, bs, ptr, col, f, r, transpose=False):
+    """Per block row, ||z'_I|| of the magnitude recursion for z = M^{-1} r
+    (or M^{-T} r).  Rounding-error analysis of substitution bounds the
+    forward error of each computed row by a small multiple of the unit
+    roundoff (depth of the recursion times terms per row) times this
+    magnitude: rows whose value cancels to near zero are measured against
+    the size of the terms that cancelled, not against their own value."""
+    F = magnitude_factors(ptr, col, f, bs)
+    ra = np.abs(np.asarray(r, dtype=np.float64))
+    za = (O.apply_transpose if transpose else O.apply)(n, bs, ptr, col, F, ra)
+    return np.linalg.norm(za.reshape(-1, bs), axis=1)
+
+
+def dd_scale(st, r):
+    """apply_scale of the DD-ILU0 apply of an oracle setup."""
+    return apply_scale(st.n, st.bs, st.tptr, st.tcol, st.f, r)
 
 
 # Layer boundaries of the 27 -> 64 -> 64 -> 9 network's flat parameter

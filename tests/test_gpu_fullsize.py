@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from parity import check_close, check_spmv
+from parity import check_close, check_spmv, dd_scale
 from problems import make_workload
 
 torch = pytest.importorskip("torch")
@@ -54,7 +54,7 @@ def test_fullsize_apply_fp64(full):
     r = np.random.default_rng(31).standard_normal(st.n * 3)
     zo = st.apply(r)
     zg = np_(s.apply(torch.as_tensor(r, device="cuda")))
-    check_close(zg, zo, 3, 1e-12, what="fullsize apply")
+    check_close(zg, zo, 3, 1e-12, what="fullsize apply", scale=dd_scale(st, r))
     # per-subdomain check: no subdomain is off (a wrong workgroup would hide in the norm)
     e_sub = np.linalg.norm((zg - zo).reshape(st.nsub, -1), axis=1) / np.linalg.norm(zo.reshape(st.nsub, -1), axis=1)
     assert e_sub.max() < 1e-11
@@ -132,7 +132,9 @@ def test_fullsize_learned_correction(full):
         dd.lic_set_coeffs(s.h, Cg)
         r = np.random.default_rng(34).standard_normal(st.n * 3)
         zg = np_(s.apply(torch.as_tensor(r, device="cuda")))
-        zo = L.apply(np_(Cg).astype(np.float64), r)
-        check_close(zg, zo, 3, 1e-12, what="fullsize corrected apply")
+        C64 = np_(Cg).astype(np.float64)
+        zo = L.apply(C64, r)
+        sc = dd_scale(st, O.lic_correct(st.n, L.faces, np.abs(C64), np.abs(r)))
+        check_close(zg, zo, 3, 1e-12, what="fullsize corrected apply", scale=sc)
     finally:
         dd.lic_set_params(s.h, None)

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from parity import check_close, check_spmv
+from parity import check_close, check_spmv, dd_scale
 from problems import grid_graph, laplacian_scalar, unstructured_problem
 
 torch = pytest.importorskip("torch")
@@ -120,7 +120,7 @@ def test_apply(name, variant):
         r = np.random.default_rng(7).standard_normal(p.n * p.bs)
         z_o = st.apply(r)
         z_g = np_(s.apply(torch.as_tensor(r, device="cuda")))
-        check_close(z_g, z_o, p.bs, 1e-12, what=f"graph {name} apply v{variant}")
+        check_close(z_g, z_o, p.bs, 1e-12, what=f"graph {name} apply v{variant}", scale=dd_scale(st, r))
     finally:
         dd.dd_set_apply_variant(s.h, 0)
 
@@ -260,7 +260,8 @@ def test_learned_correction_on_graph_partition():
         dd.lic_set_coeffs(s.h, None)
         s.close()
     zo = L.apply(Co.astype(np.float64), r)
-    check_close(zg, zo, 3, 1e-12, what="graph corrected apply")
+    sc = dd_scale(st, O.lic_correct(st.n, L.faces, np.abs(Co.astype(np.float64)), np.abs(r)))
+    check_close(zg, zo, 3, 1e-12, what="graph corrected apply", scale=sc)
 
 
 def test_automatic_part_size():

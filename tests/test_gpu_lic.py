@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from parity import check_close, check_layers
+from parity import apply_scale, check_close, check_layers, dd_scale
 from problems import lic_init_params, lognormal_problem, probe_vectors
 
 torch = pytest.importorskip("torch")
@@ -59,7 +59,8 @@ def test_global_apply_parity(prob):
     Z = np_(dd.dd_global_apply(s.h, cu(R.reshape(-1)), nrhs=2)).reshape(2, -1)
     for q in range(2):
         zo = L.apply_global(R[q])
-        check_close(Z[q], zo, 3, 1e-12, what=f"global apply probe {q}")
+        sc = apply_scale(st.n, 3, st.aptr, st.acol, L.global_factors(), R[q])
+        check_close(Z[q], zo, 3, 1e-12, what=f"global apply probe {q}", scale=sc)
 
 
 def test_global_preconditioned_bicgstab(prob):
@@ -79,7 +80,8 @@ def test_adjoint_apply_parity(prob):
     g = np.random.default_rng(4).standard_normal(st.n * 3)
     a = np_(dd.dd_apply_adjoint(s.h, cu(g)))
     ao = O.apply_transpose(st.n, 3, st.tptr, st.tcol, st.f, g)
-    check_close(a, ao, 3, 1e-12, what="adjoint apply")
+    sc = apply_scale(st.n, 3, st.tptr, st.tcol, st.f, g, transpose=True)
+    check_close(a, ao, 3, 1e-12, what="adjoint apply", scale=sc)
 
 
 def test_zero_output_is_plain_apply(prob):
@@ -119,7 +121,8 @@ def test_corrected_apply_parity(prob, variant):
         dd.lic_set_coeffs(s.h, None)
         dd.dd_set_apply_variant(s.h, 0)
     zo = L.apply(Co.astype(np.float64), r)
-    check_close(zg, zo, 3, 1e-12, what=f"corrected apply v{variant}")
+    sc = dd_scale(st, O.lic_correct(st.n, L.faces, np.abs(Co.astype(np.float64)), np.abs(r)))
+    check_close(zg, zo, 3, 1e-12, what=f"corrected apply v{variant}", scale=sc)
 
 
 def test_targets_loss_and_gradient(prob):
@@ -131,7 +134,8 @@ def test_targets_loss_and_gradient(prob):
     Zs_g, den_g = dd.lic_targets(s.h, cu(R))
     Zs_o = np.stack([L.apply_global(r) for r in R])
     den_o = np.array([((st.apply(r) - z) ** 2).sum() for r, z in zip(R, Zs_o)])
-    check_close(np_(Zs_g), Zs_o, 3, 1e-12, what="global ILU0 targets")
+    sc = np.concatenate([apply_scale(st.n, 3, st.aptr, st.acol, L.global_factors(), r) for r in R])
+    check_close(np_(Zs_g), Zs_o, 3, 1e-12, what="global ILU0 targets", scale=sc)
     assert np.allclose(np_(den_g), den_o, rtol=1e-10)
     P = trained_like_params()
     loss_g, grad_g = dd.lic_loss_grad(s.h, cu(P, torch.float32), cu(R), Zs_g, den_g)
@@ -191,7 +195,8 @@ def test_adjoint_apply_parity_training_shape(prob16):
         g = np.random.default_rng(seed).standard_normal(st.n * 3)
         a = np_(dd.dd_apply_adjoint(s.h, cu(g)))
         ao = O.apply_transpose(st.n, 3, st.tptr, st.tcol, st.f, g)
-        check_close(a, ao, 3, 1e-12, what=f"adjoint apply 16^3 seed {seed}")
+        sc = apply_scale(st.n, 3, st.tptr, st.tcol, st.f, g, transpose=True)
+        check_close(a, ao, 3, 1e-12, what=f"adjoint apply 16^3 seed {seed}", scale=sc)
 
 
 def test_loss_and_gradient_training_shape(prob16):
@@ -204,7 +209,8 @@ def test_loss_and_gradient_training_shape(prob16):
     Zs_g, den_g = dd.lic_targets(s.h, cu(R))
     Zs_o = np.stack([L.apply_global(r) for r in R])
     den_o = np.array([((st.apply(r) - z) ** 2).sum() for r, z in zip(R, Zs_o)])
-    check_close(np_(Zs_g), Zs_o, 3, 1e-12, what="16^3 targets")
+    sc = np.concatenate([apply_scale(st.n, 3, st.aptr, st.acol, L.global_factors(), r) for r in R])
+    check_close(np_(Zs_g), Zs_o, 3, 1e-12, what="16^3 targets", scale=sc)
     assert np.allclose(np_(den_g), den_o, rtol=1e-10)
     P = trained_like_params(11)
     loss_g, grad_g = dd.lic_loss_grad(s.h, cu(P, torch.float32), cu(R), Zs_g, den_g)

@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from parity import check_close, check_spmv
+from parity import check_close, check_spmv, dd_scale
 from problems import laplacian_scalar, lognormal_problem, random_blocks
 
 torch = pytest.importorskip("torch")
@@ -116,7 +116,7 @@ def test_apply_fp64(name, variant):
             r = rng.standard_normal(st.n * st.bs)
             z_o = st.apply(r)
             z_g = np_(s.apply(torch.as_tensor(r, device="cuda")))
-            check_close(z_g, z_o, st.bs, RTOL_FP64, what=f"{name} apply v{variant}")
+            check_close(z_g, z_o, st.bs, RTOL_FP64, what=f"{name} apply v{variant}", scale=dd_scale(st, r))
     finally:
         P.ddilu.dd_set_apply_variant(s.h, 0)
 
@@ -141,7 +141,7 @@ def test_apply_ablation_fp64(name, variant):
             r = rng.standard_normal(st.n * st.bs)
             z_o = st.apply(r)
             z_g = np_(s.apply(torch.as_tensor(r, device="cuda")))
-            check_close(z_g, z_o, st.bs, RTOL_FP64, what=f"{name} ablation v{variant}")
+            check_close(z_g, z_o, st.bs, RTOL_FP64, what=f"{name} ablation v{variant}", scale=dd_scale(st, r))
     finally:
         P.ddilu.dd_set_apply_variant(s.h, 0)
 
