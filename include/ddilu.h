@@ -263,6 +263,28 @@ int dd_spmv(dd_handle h, const double *x, double *y, void *hip_stream);
 int bicgstab_solve(dd_handle h, const double *b, double *x, double rtol,
                    int32_t maxit, void *hip_stream, dd_solve_info *info);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): bicgstab_solve with the same arguments,
+ * kernels and results, whose Krylov workspace (the vectors, the partial
+ * sums of the dot products and the device scalars) lives in a fixed array
+ * of the library instead of buffers the handle allocates.  The array holds
+ * 128 MiB on each device the library is loaded on, until the process ends;
+ * it fits 11 * n * bs FP64 values plus the partial sums, about 1.5 million
+ * values of n * bs (a 64^3 grid of 3x3 blocks uses 69 MB), and a larger
+ * problem returns DD_EINVAL without running.  The call allocates nothing:
+ * the handle must already hold what the solve reads (partition, factors in
+ * the chosen precision, learned coefficients; apply variant 7 additionally
+ * needs one earlier dd_trsv_apply or bicgstab_solve, else DD_ESTATE).
+ * Differences from bicgstab_solve: the apply + SpMV fusion (dd_set_fusion)
+ * and per-apply profiling are not used (applies and apply_seconds report
+ * 0), and solve_seconds is host wall time from the moment the stream is
+ * idle to the end of the call.  Every call on one device shares that
+ * device's array (its contents are rewritten by each call before they are
+ * read): calls that overlap on one device, from several threads or
+ * streams, race and give wrong results; serialise them. */
+int bicgstab_solve_noalloc(dd_handle h, const double *b, double *x, double rtol,
+                           int32_t maxit, void *hip_stream, dd_solve_info *info);
+
 /* Choose the kernel dd_trsv_apply (and bicgstab_solve) uses; all compute the
  * same z up to rounding order.  0 = automatic (3 where the handle's shape
  * allows it, else 1), 1 = plain level loop (a row's blocks loaded four at a

@@ -560,25 +560,26 @@ extern "C" int dd_spmv(dd_handle h, const double *x, double *y, void *hip_stream
     return DD_OK;
 }
 
-extern "C" int bicgstab_solve(dd_handle h, const double *b, double *x, double rtol, int32_t maxit, void *hip_stream,
-                              dd_solve_info *info) {
-    if (!h) return set_global_error(DD_EINVAL, "bicgstab_solve: null handle");
-    if (!h->factored) return h->fail(DD_ESTATE, "bicgstab_solve before ilu0_factor");
-    if (!b || !x || b == x) return h->fail(DD_EINVAL, "bicgstab_solve: b and x must be distinct device buffers");
-    if (!(rtol > 0.0) || maxit < 0) return h->fail(DD_EINVAL, "bicgstab_solve: bad rtol or maxit");
-    hipStream_t st = as_stream(hip_stream);
-    if (h->pc_kind == 0) RCHK(prepare_variant(h, "bicgstab_solve", st));
+static int check_solve_args(dd_ctx *h, const char *who, const double *b, double *x, double rtol, int32_t maxit) {
+    if (!h->factored) return h->fail(DD_ESTATE, "%s before ilu0_factor", who);
+    if (!b || !x || b == x) return h->fail(DD_EINVAL, "%s: b and x must be distinct device buffers", who);
+    if (!(rtol > 0.0) || maxit < 0) return h->fail(DD_EINVAL, "%s: bad rtol or maxit", who);
+    return DD_OK;
+}
+
+// One solve in workspace w.  A learned solve that breaks down or misses
+// maxit is repeated with plain DD-ILU0 from the caller's initial guess, kept
+// in the workspace's last vector (the solve overwrites x with its last
+// iterate).
+static int solve_in(dd_ctx *h, const KrylovWork &w, const double *b, double *x, double rtol, int32_t maxit,
+                    hipStream_t st, dd_solve_info *info) {
     const bool learned = h->pc_kind == 0 && h->lic.active;
-    if (!learned || !h->lic_fallback) return bicgstab_run(h, b, x, rtol, maxit, st, info);
-    // A learned solve that breaks down or misses maxit is repeated with plain
-    // DD-ILU0 from the caller's initial guess, kept in the workspace's last
-    // vector (the solve overwrites x with its last iterate).
-    RCHK(krylov_workspace(h));
+    if (!learned || !h->lic_fallback) return bicgstab_run(h, w, b, x, rtol, maxit, st, info);
     const int64_t m = h->n * h->bs;
-    double *x0 = h->kv + (int64_t)(kKrylovVectors - 1) * m;
+    double *x0 = w.kv + (int64_t)(kKrylovVectors - 1) * m;
     HCHK(hipMemcpyAsync(x0, x, m * sizeof(double), hipMemcpyDeviceToDevice, st));
     dd_solve_info first{};
-    const int rc = bicgstab_run(h, b, x, rtol, maxit, st, &first);
+    const int rc = bicgstab_run(h, w, b, x, rtol, maxit, st, &first);
     if (rc != DD_EBREAKDOWN && rc != DD_ENOCONV) {
         if (info) *info = first;
         return rc;
@@ -586,7 +587,7 @@ extern "C" int bicgstab_solve(dd_handle h, const double *b, double *x, double rt
     HCHK(hipMemcpyAsync(x, x0, m * sizeof(double), hipMemcpyDeviceToDevice, st));
     h->lic.active = 0;
     dd_solve_info second{};
-    const int rc2 = bicgstab_run(h, b, x, rtol, maxit, st, &second);
+    const int rc2 = bicgstab_run(h, w, b, x, rtol, maxit, st, &second);
     h->lic.active = 1;
     if (info) {
         *info = second;
@@ -596,6 +597,35 @@ extern "C" int bicgstab_solve(dd_handle h, const double *b, double *x, double rt
         info->apply_seconds += first.apply_seconds;
     }
     return rc2;
+}
+
+extern "C" int bicgstab_solve(dd_handle h, const double *b, double *x, double rtol, int32_t maxit, void *hip_stream,
+                              dd_solve_info *info) {
+    if (!h) return set_global_error(DD_EINVAL, "bicgstab_solve: null handle");
+    RCHK(check_solve_args(h, "bicgstab_solve", b, x, rtol, maxit));
+    hipStream_t st = as_stream(hip_stream);
+    if (h->pc_kind == 0) RCHK(prepare_variant(h, "bicgstab_solve", st));
+    KrylovWork w;
+    RCHK(krylov_workspace(h, &w));
+    return solve_in(h, w, b, x, rtol, maxit, st, info);
+}
+
+extern "C" int bicgstab_solve_noalloc(dd_handle h, const double *b, double *x, double rtol, int32_t maxit,
+                                      void *hip_stream, dd_solve_info *info) {
+    if (!h) return set_global_error(DD_EINVAL, "bicgstab_solve_noalloc: null handle");
+    RCHK(check_solve_args(h, "bicgstab_solve_noalloc", b, x, rtol, maxit));
+    if (h->pc_kind == 0) {
+        if (const char *why = variant_unsupported(h, h->variant))
+            return h->fail(DD_EINVAL, "bicgstab_solve_noalloc: %s", why);
+        if (h->variant == 7 && !h->sw[1].uraw)
+            return h->fail(DD_ESTATE,
+                           "bicgstab_solve_noalloc: apply variant 7 needs its unscaled factors, which the first "
+                           "dd_trsv_apply or bicgstab_solve with that variant allocates");
+    }
+    KrylovScalars host{};
+    KrylovWork w;
+    RCHK(noalloc_workspace(h, &w, &host));
+    return solve_in(h, w, b, x, rtol, maxit, as_stream(hip_stream), info);
 }
 
 extern "C" int dd_set_lic_fallback(dd_handle h, int32_t on) {

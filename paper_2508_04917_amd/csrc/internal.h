@@ -213,13 +213,33 @@ hipError_t launch_spmv(dd_ctx *h, const double *x, double *y, hipStream_t st);
 void build_spmv_layout(dd_ctx *h, hipStream_t st);
 hipError_t launch_permute(int64_t n, int bs, const int32_t *map, const double *in, double *out,
                           hipStream_t st);
-int bicgstab_run(dd_ctx *h, const double *b, double *x, double rtol, int32_t maxit,
-                 hipStream_t st, dd_solve_info *info);
 // vectors of n*bs in the Krylov workspace: ten for the recurrence, one to
 // keep the initial guess while a learned solve may still fall back
 constexpr int kKrylovVectors = 11;
-// the Krylov workspace of bicgstab_run (allocated once per handle)
-int krylov_workspace(dd_ctx *h);
+// Device workspace of one solve: the Krylov vectors, the per-workgroup
+// partial sums and the device scalars, plus a host copy of the scalars.
+// Either the handle's own buffers (allocated on its first solve) or the
+// library's fixed array (bicgstab_solve_noalloc).
+struct KrylovWork {
+    double *kv = nullptr;              // kKrylovVectors vectors of n*bs
+    double *partials = nullptr;        // [8 * part_stride] per-workgroup partial sums
+    int32_t part_stride = 0;
+    KrylovScalars *ks = nullptr;       // device
+    KrylovScalars *ks_host = nullptr;  // host (pinned for the handle's workspace)
+    // false: create no HIP events (the solve is timed on the host, per-apply
+    // profiling is off) and use no buffer outside this workspace (the fused
+    // apply + SpMV launch, whose flags the handle allocates, is not used)
+    bool handle_owned = true;
+};
+int bicgstab_run(dd_ctx *h, const KrylovWork &w, const double *b, double *x, double rtol, int32_t maxit,
+                 hipStream_t st, dd_solve_info *info);
+// the handle's Krylov workspace (allocated on the first call)
+int krylov_workspace(dd_ctx *h, KrylovWork *w);
+// the workspace in the library's fixed device array: no allocation;
+// DD_EINVAL when the problem needs more than that array holds
+int noalloc_workspace(dd_ctx *h, KrylovWork *w, KrylovScalars *host);
+// bytes of the fixed array (per device)
+constexpr int64_t kNoallocBytes = int64_t(128) << 20;
 
 // global ILU0
 int global_factor(dd_ctx *h, hipStream_t st);

@@ -12,6 +12,9 @@
 // device.  Every kernel of an iteration first reads the state word and
 // returns at once when the solve has finished, so the host enqueues a batch
 // of iterations and only synchronises once per batch.
+#include <chrono>
+#include <mutex>
+
 #include "internal.h"
 #include "spmv.h"
 
@@ -457,39 +460,50 @@ hipError_t launch_permute(int64_t n, int bs, const int32_t *map, const double *i
     } while (0)
 
 template <int BS>
-static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t maxit, hipStream_t st,
-                     dd_solve_info *info) {
+static int run_typed(dd_ctx *h, const KrylovWork &W, const double *b, double *x, double rtol, int32_t maxit,
+                     hipStream_t st, dd_solve_info *info) {
     const int64_t n = h->n;
     const int64_t m = n * BS;
-    double *V = h->kv;
+    double *V = W.kv;
     double *bp = V + 0 * m, *xp = V + 1 * m, *r = V + 2 * m, *r0 = V + 3 * m, *p = V + 4 * m;
     double *ph = V + 5 * m, *v = V + 6 * m, *s = V + 7 * m, *shat = V + 8 * m, *t = V + 9 * m;
-    double *part = h->partials;
-    KrylovScalars *ks = h->ks;
+    double *part = W.partials;
+    KrylovScalars *ks = W.ks;
+    KrylovScalars *ks_host = W.ks_host;
     const int32_t *state = &ks->state;
+    // events (solve timing, per-apply profiling) and the fused launch only
+    // with the handle's own workspace
+    const bool own = W.handle_owned;
+    const bool profile = own && h->profile;
 
     const int rpb = (kWave / BS) * (kRedT / kWave);
     const int gsp = (int)((n + rpb - 1) / rpb);  // one partial per SpMV workgroup
     const int gvec = (int)std::min<int64_t>((m + kRedT - 1) / kRedT, kMaxGrid);
-    const int sps = h->spmv_part_stride;
+    const int sps = W.part_stride;
     // apply + SpMV in one launch (partials one per subdomain) where the
     // handle allows it; the flags and the ticket counter start at zero
-    const bool fused = h->fuse && !fused_unsupported(h);
+    const bool fused = own && h->fuse && !fused_unsupported(h);
     const int gpart = fused ? h->nsub : gsp;
     uint32_t fepoch = 0;
     unsigned long long ftick = 0;
 
-    hipEvent_t e0, e1;
-    KCHK(hipEventCreate(&e0));
-    KCHK(hipEventCreate(&e1));
-    KCHK(hipEventRecord(e0, st));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::chrono::steady_clock::time_point h0;
+    if (own) {
+        KCHK(hipEventCreate(&e0));
+        KCHK(hipEventCreate(&e1));
+        KCHK(hipEventRecord(e0, st));
+    } else {  // host clock from an idle stream to the final synchronisation
+        KCHK(hipStreamSynchronize(st));
+        h0 = std::chrono::steady_clock::now();
+    }
 
     KrylovScalars init{};
     init.tol = rtol;
     init.maxit = maxit;
     init.state = ST_RUN;
-    *h->ks_host = init;
-    KCHK(hipMemcpyAsync(ks, h->ks_host, sizeof(KrylovScalars), hipMemcpyHostToDevice, st));
+    *ks_host = init;
+    KCHK(hipMemcpyAsync(ks, ks_host, sizeof(KrylovScalars), hipMemcpyHostToDevice, st));
     if (fused) k_fuse_reset<<<(h->nsub + 255) / 256, 256, 0, st>>>(h->nsub, h->fflag, h->fticket);
     KCHK(launch_permute(n, BS, h->new2old, b, bp, st));
     KCHK(launch_permute(n, BS, h->new2old, x, xp, st));
@@ -499,7 +513,7 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
     KCHK(hipGetLastError());
 
     const int chunk = 8;
-    if (h->profile && (int)h->events.size() < 4 * chunk) {
+    if (profile && (int)h->events.size() < 4 * chunk) {
         while ((int)h->events.size() < 4 * chunk) {
             hipEvent_t ev;
             KCHK(hipEventCreate(&ev));
@@ -512,11 +526,11 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
     for (;;) {  // restarts
         chunk_todo = 0;
         while (true) {
-            KCHK(hipMemcpyAsync(h->ks_host, ks, sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
+            KCHK(hipMemcpyAsync(ks_host, ks, sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
             KCHK(hipStreamSynchronize(st));
-            final_state = h->ks_host->state;
-            if (h->profile) {  // applies of the finished chunk that did work
-                const KrylovScalars &hk = *h->ks_host;
+            final_state = ks_host->state;
+            if (profile) {  // applies of the finished chunk that did work
+                const KrylovScalars &hk = *ks_host;
                 for (int k = 0; k < chunk_todo; ++k) {
                     const int itk = chunk_first + k;
                     if (itk > hk.iters) break;
@@ -539,9 +553,9 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
                     KCHK(launch_apply_spmv(h, 0, p, ph, v, r0, part, sps, ++fepoch, ftick, &ks->state, st));
                     ftick += 2ull * h->nsub;
                 } else {
-                    if (h->profile) KCHK(hipEventRecord(h->events[4 * k], st));
+                    if (profile) KCHK(hipEventRecord(h->events[4 * k], st));
                     KCHK(launch_precond(h, p, ph, state, st));  // p^ = M^{-1} p
-                    if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 1], st));
+                    if (profile) KCHK(hipEventRecord(h->events[4 * k + 1], st));
                     spmv_dots<BS, 0>(h, gsp, ph, v, r0, nullptr, nullptr, nullptr, part, sps, state,
                                      st);  // v = A p^, r0.v
                 }
@@ -553,9 +567,9 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
                     KCHK(launch_apply_spmv(h, 1, s, shat, t, s, part, sps, ++fepoch, ftick, &ks->state, st));
                     ftick += 2ull * h->nsub;
                 } else {
-                    if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 2], st));
+                    if (profile) KCHK(hipEventRecord(h->events[4 * k + 2], st));
                     KCHK(launch_precond(h, s, shat, state, st));  // s^ = M^{-1} s
-                    if (h->profile) KCHK(hipEventRecord(h->events[4 * k + 3], st));
+                    if (profile) KCHK(hipEventRecord(h->events[4 * k + 3], st));
                     spmv_dots<BS, 1>(h, gsp, shat, t, s, nullptr, nullptr, nullptr, part, sps, state,
                                      st);  // t = A s^, t.s, t.t
                 }
@@ -569,13 +583,13 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
         // true residual ||b - A x|| / ||b||
         spmv_dots<BS, 3>(h, gsp, xp, t, bp, nullptr, nullptr, nullptr, part, sps, nullptr, st);
         k_scalars<<<1, kScalT, 0, st>>>(SC_TRUE, 0, part, gsp, sps, ks, h->hist, h->hist_len);
-        KCHK(hipMemcpyAsync(h->ks_host, ks, sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
+        KCHK(hipMemcpyAsync(ks_host, ks, sizeof(KrylovScalars), hipMemcpyDeviceToHost, st));
         KCHK(hipStreamSynchronize(st));
         // The recurrence met the tolerance but the true residual did not (an
         // FP32 trisolve makes the preconditioner slightly inconsistent from one
         // apply to the next): restart from the current iterate.
         {
-            const KrylovScalars &hk = *h->ks_host;
+            const KrylovScalars &hk = *ks_host;
             if (hk.state == ST_CONV && hk.snorm > 2.0 * hk.tol && restarts < kMaxRestarts && it < maxit) {
                 ++restarts;
                 spmv_dots<BS, 2>(h, gsp, xp, t, bp, r, r0, p, part, sps, nullptr, st);
@@ -586,14 +600,18 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
         }
         break;
     }  // restarts
-    KCHK(hipEventRecord(e1, st));
+    if (own) KCHK(hipEventRecord(e1, st));
     KCHK(launch_permute(n, BS, h->old2new, xp, x, st));
     KCHK(hipStreamSynchronize(st));
     float ms = 0.f;
-    KCHK(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    const KrylovScalars &hk = *h->ks_host;
+    if (own) {
+        KCHK(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    } else {
+        ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - h0).count();
+    }
+    const KrylovScalars &hk = *ks_host;
     int status = DD_OK;
     if (hk.state == kWaitFailed)
         return h->fail(DD_EHIP, "bicgstab_solve: a wait of the apply + SpMV launch exhausted its bound");
@@ -622,35 +640,102 @@ static int run_typed(dd_ctx *h, const double *b, double *x, double rtol, int32_t
     return DD_OK;
 }
 
-int krylov_workspace(dd_ctx *h) {
-    if (h->kv) return DD_OK;
-    int rc = h->alloc(&h->kv, kKrylovVectors * h->n * h->bs);
-    if (rc) return rc;
-    const int rpb = (kWave / h->bs) * (kRedT / kWave);
-    h->spmv_part_stride = (int)std::max<int64_t>((h->n + rpb - 1) / rpb, kMaxGrid);
-    rc = h->alloc(&h->partials, (int64_t)kStride * h->spmv_part_stride);
-    if (rc) return rc;
-    rc = h->alloc(&h->ks, 1);
-    if (rc) return rc;
-    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&h->ks_host), sizeof(KrylovScalars));
-    if (e != hipSuccess) return h->fail(DD_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+int krylov_workspace(dd_ctx *h, KrylovWork *w) {
+    if (!h->kv) {
+        int rc = h->alloc(&h->kv, kKrylovVectors * h->n * h->bs);
+        if (rc) return rc;
+        const int rpb = (kWave / h->bs) * (kRedT / kWave);
+        h->spmv_part_stride = (int)std::max<int64_t>((h->n + rpb - 1) / rpb, kMaxGrid);
+        rc = h->alloc(&h->partials, (int64_t)kStride * h->spmv_part_stride);
+        if (rc) return rc;
+        rc = h->alloc(&h->ks, 1);
+        if (rc) return rc;
+        hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&h->ks_host), sizeof(KrylovScalars));
+        if (e != hipSuccess) {
+            h->ks_host = nullptr;
+            h->kv = nullptr;  // the next call tries again (the buffers stay recorded for dd_destroy)
+            return h->fail(DD_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+        }
+    }
+    w->kv = h->kv;
+    w->partials = h->partials;
+    w->part_stride = h->spmv_part_stride;
+    w->ks = h->ks;
+    w->ks_host = h->ks_host;
+    w->handle_owned = true;
     return DD_OK;
 }
 
-int bicgstab_run(dd_ctx *h, const double *b, double *x, double rtol, int32_t maxit, hipStream_t st,
-                 dd_solve_info *info) {
-    int rc0 = krylov_workspace(h);
-    if (rc0) return rc0;
-    build_spmv_layout(h, st);
-    if (h->fuse && !h->fdep && !fused_unsupported(h)) {
-        int rc = h->alloc(&h->fdep, 2 * (int64_t)h->nsub);
-        if (!rc) rc = h->alloc(&h->fflag, h->nsub);
-        if (!rc) rc = h->alloc(&h->fticket, 1);
-        if (rc) return rc;
-        hipError_t e = launch_dep_range(h, st);
-        if (e != hipSuccess) return h->fail(DD_EHIP, "dependency ranges: %s", hipGetErrorString(e));
+// The fixed workspace of bicgstab_solve_noalloc: one array per device (each
+// device that loads the library holds its own copy until the process ends).
+// Kernels never name it: the host takes each device's address of it once,
+// with that device current, and passes that address as it passes the
+// handle's own workspace.  Every call on a device shares its array, so calls
+// that overlap on one device race.
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+static void *g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static int64_t align256(int64_t b) { return (b + 255) & ~int64_t(255); }
+
+int noalloc_workspace(dd_ctx *h, KrylovWork *w, KrylovScalars *host) {
+    const int rpb = (kWave / h->bs) * (kRedT / kWave);
+    const int64_t stride = std::max<int64_t>((h->n + rpb - 1) / rpb, kMaxGrid);
+    const int64_t vec_bytes = align256((int64_t)kKrylovVectors * h->n * h->bs * (int64_t)sizeof(double));
+    const int64_t part_bytes = align256((int64_t)kStride * stride * (int64_t)sizeof(double));
+    const int64_t need = vec_bytes + part_bytes + align256(sizeof(KrylovScalars));
+    if (need > kNoallocBytes)
+        return h->fail(DD_EINVAL,
+                       "bicgstab_solve_noalloc: the problem needs %lld bytes of Krylov workspace, the fixed array "
+                       "holds %lld (at most about %lld values of n*bs)",
+                       (long long)need, (long long)kNoallocBytes,
+                       (long long)((kNoallocBytes - part_bytes - 256) / (kKrylovVectors * (int64_t)sizeof(double))));
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return h->fail(DD_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return h->fail(DD_EINVAL, "bicgstab_solve_noalloc: device %d", dev);
+    void *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void *p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || p == nullptr) {
+                (void)hipGetLastError();
+                return h->fail(DD_EHIP, "hipGetSymbolAddress of the fixed workspace on device %d: %s", dev,
+                               hipGetErrorString(e));
+            }
+            g_scratch_ptr[dev] = p;
+        }
+        base = g_scratch_ptr[dev];
     }
-    return h->bs == 3 ? run_typed<3>(h, b, x, rtol, maxit, st, info) : run_typed<1>(h, b, x, rtol, maxit, st, info);
+    unsigned char *b = static_cast<unsigned char *>(base);
+    w->kv = reinterpret_cast<double *>(b);
+    w->partials = reinterpret_cast<double *>(b + vec_bytes);
+    w->part_stride = (int32_t)stride;
+    w->ks = reinterpret_cast<KrylovScalars *>(b + vec_bytes + part_bytes);
+    w->ks_host = host;
+    w->handle_owned = false;
+    return DD_OK;
+}
+
+int bicgstab_run(dd_ctx *h, const KrylovWork &w, const double *b, double *x, double rtol, int32_t maxit,
+                 hipStream_t st, dd_solve_info *info) {
+    if (w.handle_owned) {
+        build_spmv_layout(h, st);
+        if (h->fuse && !h->fdep && !fused_unsupported(h)) {
+            int rc = h->alloc(&h->fdep, 2 * (int64_t)h->nsub);
+            if (!rc) rc = h->alloc(&h->fflag, h->nsub);
+            if (!rc) rc = h->alloc(&h->fticket, 1);
+            if (rc) return rc;
+            hipError_t e = launch_dep_range(h, st);
+            if (e != hipSuccess) return h->fail(DD_EHIP, "dependency ranges: %s", hipGetErrorString(e));
+        }
+    }
+    return h->bs == 3 ? run_typed<3>(h, w, b, x, rtol, maxit, st, info)
+                      : run_typed<1>(h, w, b, x, rtol, maxit, st, info);
 }
 
 }  // namespace ddilu

@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "DD_OK", -1: "DD_EINVAL", -2: "DD_ENOTDIV", -3: "DD_ELDS", -4
 # every symbol include/ddilu.h declares
 EXPORTS = ("dd_auto_subdims", "dd_device_caps", "dd_partition", "dd_partition_graph", "dd_get_info", "dd_get_partition",
            "dd_get_reordered", "ilu0_factor", "dd_set_precision", "dd_get_levels", "dd_get_factors",
-           "dd_trsv_apply", "dd_spmv", "bicgstab_solve", "dd_set_apply_variant", "dd_set_fusion", "dd_set_lic_fallback",
+           "dd_trsv_apply", "dd_spmv", "bicgstab_solve", "bicgstab_solve_noalloc", "dd_set_apply_variant", "dd_set_fusion", "dd_set_lic_fallback",
            "dd_set_profiling",
            "dd_set_residual_history", "dd_global_factor", "dd_global_apply", "dd_set_preconditioner",
            "lic_setup", "lic_get_faces", "lic_set_params", "lic_set_coeffs", "lic_get_coeffs",
@@ -92,6 +92,7 @@ def lib():
             "dd_trsv_apply": (C.c_int, [vp, vp, vp, vp]),
             "dd_spmv": (C.c_int, [vp, vp, vp, vp]),
             "bicgstab_solve": (C.c_int, [vp, vp, vp, C.c_double, i32, vp, C.POINTER(SolveInfo)]),
+            "bicgstab_solve_noalloc": (C.c_int, [vp, vp, vp, C.c_double, i32, vp, C.POINTER(SolveInfo)]),
             "dd_set_apply_variant": (C.c_int, [vp, i32]),
             "dd_set_fusion": (C.c_int, [vp, i32]),
             "dd_set_lic_fallback": (C.c_int, [vp, i32]),
@@ -147,6 +148,13 @@ def _dev_check(t, dtype, numel, name):
         raise ValueError(f"{name}: expected a contiguous {dtype} CUDA tensor of {numel} elements")
 
 
+def _vecs(h, count, **named):
+    """FP64 device vectors of count * n * bs values each (the library reads
+    and writes exactly that many through the raw pointers)."""
+    for name, t in named.items():
+        _dev_check(t, torch.float64, count * h.m, name)
+
+
 class Handle:
     """Owns a dd_handle; released by close() or garbage collection."""
 
@@ -167,6 +175,14 @@ class Handle:
     @property
     def info(self):
         return dd_get_info(self)
+
+    @property
+    def m(self) -> int:
+        """Length n*bs of the handle's vectors (cached)."""
+        if getattr(self, "_m", None) is None:
+            i = dd_get_info(self)
+            self._m = int(i["n"]) * int(i["bs"])
+        return self._m
 
 
 def dd_last_error(h=None) -> str:
@@ -275,7 +291,7 @@ def dd_get_factors(h: Handle, stream=None):
 def dd_trsv_apply(h: Handle, r, z=None, stream=None):
     if z is None:
         z = torch.empty_like(r)
-    _dev_check(r, torch.float64, z.numel(), "r")
+    _vecs(h, 1, r=r, z=z)
     _check(lib().dd_trsv_apply(h.ptr, _ptr(r), _ptr(z), _stream(stream)), h)
     return z
 
@@ -283,7 +299,7 @@ def dd_trsv_apply(h: Handle, r, z=None, stream=None):
 def dd_spmv(h: Handle, x, y=None, stream=None):
     if y is None:
         y = torch.empty_like(x)
-    _dev_check(x, torch.float64, y.numel(), "x")
+    _vecs(h, 1, x=x, y=y)
     _check(lib().dd_spmv(h.ptr, _ptr(x), _ptr(y), _stream(stream)), h)
     return y
 
@@ -293,9 +309,20 @@ def bicgstab_solve(h: Handle, b, x=None, rtol=1e-8, maxit=10000, stream=None):
     other failures raise."""
     if x is None:
         x = torch.zeros_like(b)
-    _dev_check(b, torch.float64, x.numel(), "b")
+    _vecs(h, 1, b=b, x=x)
     si = SolveInfo()
     rc = lib().bicgstab_solve(h.ptr, _ptr(b), _ptr(x), rtol, maxit, _stream(stream), C.byref(si))
+    if rc not in (DD_OK, DD_EBREAKDOWN, DD_ENOCONV):
+        raise DDError(rc, dd_last_error(h))
+    return x, {k: getattr(si, k) for k, _ in SolveInfo._fields_}
+
+
+def bicgstab_solve_noalloc(h: Handle, b, x, rtol=1e-8, maxit=10000, stream=None):
+    """bicgstab_solve with the library's fixed workspace (no device
+    allocation in the call; x must be given).  Returns (x, info)."""
+    _vecs(h, 1, b=b, x=x)
+    si = SolveInfo()
+    rc = lib().bicgstab_solve_noalloc(h.ptr, _ptr(b), _ptr(x), rtol, maxit, _stream(stream), C.byref(si))
     if rc not in (DD_OK, DD_EBREAKDOWN, DD_ENOCONV):
         raise DDError(rc, dd_last_error(h))
     return x, {k: getattr(si, k) for k, _ in SolveInfo._fields_}
@@ -338,7 +365,7 @@ def dd_global_factor(h: Handle, stream=None):
 def dd_global_apply(h: Handle, r, z=None, nrhs=1, stream=None):
     if z is None:
         z = torch.empty_like(r)
-    _dev_check(r, torch.float64, z.numel(), "r")
+    _vecs(h, nrhs, r=r, z=z)
     _check(lib().dd_global_apply(h.ptr, _ptr(r), _ptr(z), nrhs, _stream(stream)), h)
     return z
 
@@ -385,7 +412,7 @@ def lic_get_coeffs(h: Handle, nf: int, stream=None):
 def dd_apply_adjoint(h: Handle, g, a=None, stream=None):
     if a is None:
         a = torch.empty_like(g)
-    _dev_check(g, torch.float64, a.numel(), "g")
+    _vecs(h, 1, g=g, a=a)
     _check(lib().dd_apply_adjoint(h.ptr, _ptr(g), _ptr(a), _stream(stream)), h)
     return a
 
@@ -394,6 +421,7 @@ def lic_targets(h: Handle, R, stream=None):
     """R: CUDA float64 [nq, 3n] probes.  Returns (Zs, den): global ILU0 applies
     and den_q = ||M_DD^{-1} r_q - Zs_q||^2."""
     nq = R.shape[0]
+    _vecs(h, nq, R=R)
     Zs = torch.empty_like(R)
     den = torch.empty(nq, dtype=torch.float64, device="cuda")
     _check(lib().lic_targets(h.ptr, nq, _ptr(R), _ptr(Zs), _ptr(den), _stream(stream)), h)
@@ -405,6 +433,12 @@ def lic_loss_grad(h: Handle, params, R, Zs, den, loss=None, grad=None, accumulat
         loss = torch.zeros(1, dtype=torch.float64, device="cuda")
     if grad is None:
         grad = torch.zeros(LIC_NPARAM, dtype=torch.float32, device="cuda")
+    nq = R.shape[0]
+    _vecs(h, nq, R=R, Zs=Zs)
+    _dev_check(den, torch.float64, nq, "den")
+    _dev_check(params, torch.float32, LIC_NPARAM, "params")
+    _dev_check(grad, torch.float32, LIC_NPARAM, "grad")
+    _dev_check(loss, torch.float64, 1, "loss")
     _check(lib().lic_loss_grad(h.ptr, _ptr(params), R.shape[0], _ptr(R), _ptr(Zs), _ptr(den), _ptr(loss),
                                _ptr(grad), 1 if accumulate else 0, _stream(stream)), h)
     return loss, grad
