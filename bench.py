@@ -294,6 +294,62 @@ def graph_mode(args, p, ptr_d, col_d, val_d, dd, torch):
     print(json.dumps(out), flush=True)
 
 
+def precision_mode(args, p, sub, ptr_d, col_d, val_d, lic_params, dd, torch):
+    """What the reduced-precision applies do to the preconditioner on this
+    workload: each apply's error against the FP64 apply (in norm and per
+    block row), its departure from linearity (M(a+b) - Ma - Mb and
+    M(2a) - 2Ma, relative to the result; zero up to rounding for a linear
+    operator), the variation between two applies of the same vector
+    (repeatability), and BiCGSTAB with each precision, with and without
+    the learned correction."""
+    h = dd.dd_partition(p.nx, p.ny, p.nz, p.bs, ptr_d, col_d, val_d, sub=sub)
+    dd.ilu0_factor(h, dd.DD_FP64)
+    m = p.n * p.bs
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(11)
+    a = torch.randn(m, dtype=torch.float64, device="cuda:0", generator=g)
+    b = torch.randn(m, dtype=torch.float64, device="cuda:0", generator=g)
+    b_d = torch.as_tensor(p.b, device="cuda:0")
+    out = {"workload": args.workload, "subdomain": list(sub)}
+
+    def rel(x, y):
+        return float(torch.linalg.norm(x - y) / torch.linalg.norm(y))
+
+    def rowmax(x, y):  # largest per-block-row error relative to the row's norm in y
+        d = (x - y).view(-1, p.bs).norm(dim=1)
+        n = y.view(-1, p.bs).norm(dim=1)
+        return float((d / n.clamp_min(1e-300)).max())
+
+    if lic_params is not None:
+        dd.lic_setup(h)
+    dd.dd_set_precision(h, dd.DD_FP64)
+    z64 = dd.dd_trsv_apply(h, a)
+    for name, prec in (("fp64", dd.DD_FP64), ("mixed", dd.DD_MIXED), ("fp32", dd.DD_FP32)):
+        dd.dd_set_precision(h, prec)
+        za = dd.dd_trsv_apply(h, a)
+        za2 = dd.dd_trsv_apply(h, a)
+        zb = dd.dd_trsv_apply(h, b)
+        zab = dd.dd_trsv_apply(h, a + b)
+        z2a = dd.dd_trsv_apply(h, 2.0 * a)
+        zs = dd.dd_trsv_apply(h, 1e-3 * a)
+        rec = {"apply_rel_err_vs_fp64": rel(za, z64), "apply_max_row_rel_err_vs_fp64": rowmax(za, z64),
+               "additivity_defect": rel(zab, za + zb), "scaling_defect_x2": rel(z2a, 2.0 * za),
+               "scaling_defect_x1e-3": rel(zs, 1e-3 * za), "repeat_identical": bool(torch.equal(za, za2))}
+        for label, lic in (("plain", None), ("learned", lic_params)):
+            if lic is None and label == "learned":
+                continue
+            dd.lic_set_params(h, lic)
+            x, info = dd.bicgstab_solve(h, b_d, rtol=args.rtol, maxit=args.maxit)
+            rec[f"bicgstab_{label}"] = {"iters": info["iters"], "status": info["status"],
+                                        "solve_s": round(info["solve_seconds"], 4), "restarts": info["restarts"],
+                                        "rel_res_true": info["rel_res_true"], "fallback": info["fallback"]}
+            dd.lic_set_params(h, None)
+        out[name] = rec
+        log(f"{name}: {rec}")
+    h.close()
+    print(json.dumps(out), flush=True)
+
+
 def host_cpu():
     """(model name, threads available to this process)."""
     model = "unknown"
@@ -454,12 +510,14 @@ def main():
     ap.add_argument("--extra", type=int, default=1,
                     help="1: after the timed steps, compare plain FP64, FP32-factor and learned solves on "
                          "the anisotropic 160^3 and the 128^3 evaluation workloads")
-    ap.add_argument("--mode", default="full", choices=["full", "kernels", "ablation", "rocsparse", "graph"],
+    ap.add_argument("--mode", default="full",
+                    choices=["full", "kernels", "ablation", "rocsparse", "graph", "precision"],
                     help="kernels: only a copy kernel of known size and bursts of applies and SpMVs "
                          "(the short program the rocprofv3 counter runs profile); "
                          "ablation: the FP64 apply kernel variants, timed on the same factors; "
                          "rocsparse: rocSPARSE's block ILU0 apply on the decomposed and the full matrix; "
-                         "graph: graph partition, apply and solve of a workload without geometry")
+                         "graph: graph partition, apply and solve of a workload without geometry; "
+                         "precision: error, nonlinearity and solves of the FP32-factor applies")
     ap.add_argument("--applies", type=int, default=10)
     args = ap.parse_args()
 
@@ -503,6 +561,9 @@ def main():
         return
     if args.mode == "rocsparse":
         rocsparse_cmp(args, p, sub, ptr_d, col_d, val_d, dd, torch)
+        return
+    if args.mode == "precision":
+        precision_mode(args, p, sub, ptr_d, col_d, val_d, lic_params, dd, torch)
         return
 
     def step():
