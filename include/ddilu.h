@@ -216,6 +216,21 @@ int dd_get_reordered(dd_handle h, int32_t *ptr, int32_t *col, double *val,
  * number above 1e14 (the message names the block row). */
 int ilu0_factor(dd_handle h, int32_t precision, void *hip_stream);
 
+/* Numeric refactorisation on the handle's pattern (Section 5.3: the setup
+ * is amortised over solves on one sparsity pattern).  val: device
+ * double[nnzb*bs*bs], new values of the matrix given to dd_partition (or
+ * dd_partition_graph), in that call's block order and pattern.  Reuses the
+ * partition, the reorder, the dropped pattern and the level sets; recomputes
+ * the reordered values (and the SpMV's sliced ELL copy), block ILU0 and the
+ * ILDU0 streams (and their FP32 copies if they exist), giving the factors a
+ * fresh dd_partition + ilu0_factor on the new values gives.  The learned
+ * correction and the global ILU0 depend on the values: they are switched off
+ * and need lic_setup (+ lic_set_params) or dd_global_factor again.
+ * Synchronises the stream; DD_ESTATE before a successful ilu0_factor,
+ * DD_EZEROPIVOT as for ilu0_factor (the handle then stays unfactored until
+ * a later ilu0_refactor or ilu0_factor succeeds). */
+int ilu0_refactor(dd_handle h, const double *val, void *hip_stream);
+
 /* Choose the apply precision after factoring (DD_FP32 and DD_MIXED build
  * the FP32 factor copies on first use). */
 int dd_set_precision(dd_handle h, int32_t precision, void *hip_stream);

@@ -286,7 +286,7 @@ static int build_handle(dd_ctx *h, const int32_t *brow_ptr, const int32_t *bcol,
     PCHK(launch_reorder_fill(h, brow_ptr, bcol, val, src, st));
     PCHK(hipStreamSynchronize(st));
     release(h, len);
-    release(h, src);
+    h->asrc = src;  // kept for ilu0_refactor
     build_spmv_layout(h, st);
     *out = h;
     return DD_OK;
@@ -443,6 +443,8 @@ extern "C" int ilu0_factor(dd_handle h, int32_t precision, void *hip_stream) {
     hipStream_t st = as_stream(hip_stream);
     const int bb = h->bs * h->bs;
     h->factored = 0;
+    h->patterned = 0;
+    h->lic.adj_ready = 0;  // the adjoint apply's streams hold the old factors
     int32_t *tbeg = nullptr, *tlen = nullptr, *tsrc = nullptr;
     RCHK(h->alloc(&tbeg, h->n));
     RCHK(h->alloc(&tlen, h->n + 1));
@@ -467,6 +469,8 @@ extern "C" int ilu0_factor(dd_handle h, int32_t precision, void *hip_stream) {
     RCHK(h->alloc(&h->lu, (int64_t)total * bb));
     if (!h->tdiag) RCHK(h->alloc(&h->tdiag, h->n));
     if (!h->invd) RCHK(h->alloc(&h->invd, h->n * bb));
+    if (h->tsrc) release(h, h->tsrc);
+    h->tsrc = nullptr;
     RCHK(h->alloc(&tsrc, total));
     HCHK(launch_drop_rows(h, tbeg, tsrc, st));
     // level sets (Section 4.2.1) for both factors
@@ -477,8 +481,9 @@ extern "C" int ilu0_factor(dd_handle h, int32_t precision, void *hip_stream) {
     HCHK(launch_bilu0(h, st));
     HCHK(hipMemcpyAsync(status, h->status, sizeof(status), hipMemcpyDeviceToHost, st));
     HCHK(hipStreamSynchronize(st));
+    h->tsrc = tsrc;  // kept for ilu0_refactor
     if (status[2] != 0x7fffffff) {
-        release(h, tbeg); release(h, tlen); release(h, tsrc);
+        release(h, tbeg); release(h, tlen);
         return h->fail(DD_EZEROPIVOT, "singular or ill-conditioned pivot block at reordered block row %d", status[2]);
     }
     // ILDU0 post-pass folded into the packing of the two sweeps
@@ -492,7 +497,46 @@ extern "C" int ilu0_factor(dd_handle h, int32_t precision, void *hip_stream) {
     HCHK(hipStreamSynchronize(st));
     release(h, tbeg);
     release(h, tlen);
-    release(h, tsrc);
+    h->factored = 1;
+    h->patterned = 1;
+    return DD_OK;
+}
+
+extern "C" int ilu0_refactor(dd_handle h, const double *val, void *hip_stream) {
+    if (!h) return set_global_error(DD_EINVAL, "ilu0_refactor: null handle");
+    if (!val) return h->fail(DD_EINVAL, "ilu0_refactor: null values");
+    if (!h->patterned || !h->asrc || !h->tsrc) return h->fail(DD_ESTATE, "ilu0_refactor before ilu0_factor");
+    hipStream_t st = as_stream(hip_stream);
+    const int bb = h->bs * h->bs;
+    h->factored = 0;
+    // what depends on A's values and is rebuilt by its own call
+    h->lic.adj_ready = 0;
+    h->lic.active = 0;
+    h->lic.ready = 0;
+    h->gfactored = 0;
+    if (h->sw[1].uraw) { release(h, h->sw[1].uraw); h->sw[1].uraw = nullptr; }
+    // values of the reordered matrix, its sliced ELL copy and the dropped pattern
+    HCHK(launch_gather_blocks(h->nnzb, bb, h->asrc, val, h->aval, st));
+    HCHK(refresh_spmv_layout(h, st));
+    HCHK(launch_gather_blocks(h->nnzt, bb, h->tsrc, h->aval, h->lu, st));
+    // block ILU0 on the kept level sets
+    int32_t init_status[8] = {0, 0x7fffffff, 0x7fffffff, 0, 0, 0, 0, 0};
+    HCHK(hipMemcpyAsync(h->status, init_status, sizeof(init_status), hipMemcpyHostToDevice, st));
+    HCHK(launch_bilu0(h, st));
+    int32_t status[8];
+    HCHK(hipMemcpyAsync(status, h->status, sizeof(status), hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    if (status[2] != 0x7fffffff)
+        return h->fail(DD_EZEROPIVOT, "singular or ill-conditioned pivot block at reordered block row %d", status[2]);
+    // ILDU0 scaling and the streaming layouts, into the existing arrays
+    HCHK(launch_pack_fill(h, 0, st));
+    HCHK(launch_pack_fill(h, 1, st));
+    if (h->slots) {
+        HCHK(launch_pack_slots(h, 0, st));
+        HCHK(launch_pack_slots(h, 1, st));
+    }
+    if (h->sw[0].val32) HCHK(launch_cast32(h, st));
+    HCHK(hipStreamSynchronize(st));
     h->factored = 1;
     return DD_OK;
 }
@@ -723,6 +767,7 @@ extern "C" int lic_set_coeffs(dd_handle h, const float *C, void *hip_stream) {
     if (h->lic.nf)
         HCHK(hipMemcpyAsync(h->lic.C, C, (size_t)h->lic.nf * 9 * sizeof(float), hipMemcpyDeviceToDevice,
                             as_stream(hip_stream)));
+    RCHK(ddilu::lic_publish_coeffs(h, as_stream(hip_stream)));
     h->lic.active = 1;
     return DD_OK;
 }
@@ -740,7 +785,8 @@ extern "C" int dd_apply_adjoint(dd_handle h, const double *g, double *a, void *h
     if (!h) return set_global_error(DD_EINVAL, "dd_apply_adjoint: null handle");
     if (!h->lic.ready) return h->fail(DD_ESTATE, "dd_apply_adjoint before lic_setup");
     if (!g || !a || g == a) return h->fail(DD_EINVAL, "dd_apply_adjoint: bad arguments");
-    HCHK(launch_apply_adjoint(h, g, a, as_stream(hip_stream)));
+    RCHK(ddilu::lic_adjoint_streams(h, as_stream(hip_stream)));
+    HCHK(launch_apply_adjoint(h, g, a, 1, as_stream(hip_stream)));
     return DD_OK;
 }
 

@@ -38,83 +38,103 @@ namespace ddilu {
 
 // Learned interface correction inside the apply: once the subdomain's r is
 // in LDS, every row with cut faces adds sum_f C_f r_J (J in a neighbouring
-// subdomain, read from r in global memory; faces in CSR order).  One lane per
-// (row, component), so the update order is fixed.  Each lane handles two
-// rows per pass and fetches in three dependent steps (row record; column
-// and coefficients of up to kLicFaces faces; r_J), with positions past the
-// end clamped to valid ones and discarded by selects, so the loads of a step
-// are all in flight together.  Rows with more faces finish in a loop.
+// subdomain, read from r in global memory).  The work item is one
+// (face, component) pair, and a subdomain's faces are stored rank-major: the
+// first face of every row that has one (rank 0, rows ascending), then every
+// row's second face (rank 1), and so on, each face as {local row, J} and its
+// coefficient C_f, the copy of C in this order.  A lane takes up to
+// kLicItems items; it fetches their records and coefficient rows before the
+// subdomain's slice of r is loaded (lic_begin: nothing they read depends on
+// the apply), their r_J once the records are in, and adds rank by rank with
+// a barrier between ranks.  A row has at most one face of each rank, so no
+// two items of a rank touch the same LDS entry, and every row adds its faces
+// in CSR order (rank 0 first) whatever the number of passes: the item list
+// is rank-major, so a pass holds the rest of one rank and a prefix of later
+// ones.  One pass covers a subdomain of up to kLicItems * blockDim faces'
+// components (at 16x20x20, 1,840 faces on 13 wavefronts).
 struct LicArgs {
-    const int32_t *bsub;
-    const int4 *brow;  // {row, first face, face count, 0}
-    const int32_t *fJ;
-    const float *C;
+    const int32_t *fptr;    // [n+1] faces of each row (CSR order); fptr[s*S] = first face of subdomain s
+    const int32_t *rb;      // [nsub*9] rank boundaries: faces of ranks < k of subdomain s at rb[9s + k]
+    const int2 *lrec;       // [nf] rank-major faces {local row, J}
+    const float *Cr;        // [nf*9] their coefficients C_f (row-major)
 };
 
-constexpr int kLicFaces = 3;  // a 7-point row has at most 3 cut faces unless a subdomain is one cell thin
-constexpr int kLicRows = 2;  // rows per lane and pass (3 measures the same at 160^3)
+constexpr int kLicItems = 7;  // (face, component) items per lane and pass
 
-template <int BS, typename TC>
-__device__ __forceinline__ void lic_correct_lds(TC *__restrict__ y, const double *__restrict__ r, int64_t base, int s,
-                                                const LicArgs &la, int tid, int nt) {
-    const int32_t b0 = la.bsub[s], b1 = la.bsub[s + 1];
-    const int nitems = (b1 - b0) * BS;
-    for (int i0 = tid; i0 < nitems; i0 += kLicRows * nt) {
-        int item[kLicRows];
-        bool ok[kLicRows];
-        int4 ri[kLicRows];
+template <int BS>
+struct LicPass {
+    int2 rec[kLicItems];
+    float cf[kLicItems][BS];
+    int item[kLicItems];
+};
+
+struct LicState {
+    int32_t f0;   // first face of the subdomain
+    int nitems;   // faces * BS
+    int s;
+};
+
+// records and coefficient rows of items i0 + u*nt (positions past the end
+// read item 0's, which exists when nitems > 0, and are not added)
+template <int BS>
+__device__ __forceinline__ void lic_fetch(LicPass<BS> &P, const LicArgs &la, const LicState &L, int i0, int nt) {
 #pragma unroll
-        for (int u = 0; u < kLicRows; ++u) {
-            ok[u] = i0 + u * nt < nitems;
-            item[u] = ok[u] ? i0 + u * nt : i0;
-            ri[u] = la.brow[b0 + item[u] / BS];
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        int32_t J[kLicRows][kLicFaces];
-        float cf[kLicRows][kLicFaces][BS];
+    for (int u = 0; u < kLicItems; ++u) {
+        const int it = i0 + u * nt;
+        P.item[u] = it;
+        const int q = it < L.nitems ? it : 0;
+        const int64_t f = L.f0 + q / BS;
+        const int c = q % BS;
+        P.rec[u] = la.lrec[f];
 #pragma unroll
-        for (int u = 0; u < kLicRows; ++u) {
-            const int c = item[u] % BS;
-#pragma unroll
-            for (int k = 0; k < kLicFaces; ++k) {
-                const int32_t f = ri[u].y + min(k, ri[u].z - 1);
-                J[u][k] = la.fJ[f];
-                const float *Cf = la.C + (int64_t)f * BS * BS + c * BS;
-#pragma unroll
-                for (int d = 0; d < BS; ++d) cf[u][k][d] = Cf[d];
-            }
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        double rv[kLicRows][kLicFaces][BS];
-#pragma unroll
-        for (int u = 0; u < kLicRows; ++u)
-#pragma unroll
-            for (int k = 0; k < kLicFaces; ++k)
-#pragma unroll
-                for (int d = 0; d < BS; ++d) rv[u][k][d] = r[(int64_t)J[u][k] * BS + d];
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int u = 0; u < kLicRows; ++u) {
-            if (!ok[u]) continue;
-            const int c = item[u] % BS;
-            double acc = 0.0;
-#pragma unroll
-            for (int k = 0; k < kLicFaces; ++k) {
-                double t = acc;
-#pragma unroll
-                for (int d = 0; d < BS; ++d) t += (double)cf[u][k][d] * rv[u][k][d];
-                acc = k < ri[u].z ? t : acc;
-            }
-            for (int32_t f = ri[u].y + kLicFaces; f < ri[u].y + ri[u].z; ++f) {
-                const int64_t Jf = la.fJ[f];
-                const float *Cf = la.C + (int64_t)f * BS * BS + c * BS;
-#pragma unroll
-                for (int d = 0; d < BS; ++d) acc += (double)Cf[d] * r[Jf * BS + d];
-            }
-            y[(ri[u].x - base) * BS + c] += static_cast<TC>(acc);
-        }
+        for (int d = 0; d < BS; ++d) P.cf[u][d] = la.Cr[f * BS * BS + c * BS + d];
     }
-    __syncthreads();
+}
+
+template <int BS>
+__device__ __forceinline__ void lic_begin(LicState &L, LicPass<BS> &P, int64_t base, int S, int s, const LicArgs &la,
+                                          int tid, int nt) {
+    L.s = s;
+    L.f0 = la.fptr[base];
+    L.nitems = (la.fptr[base + S] - L.f0) * BS;
+    if (L.nitems > 0) lic_fetch<BS>(P, la, L, tid, nt);
+}
+
+// After the slice is in LDS and a barrier: r_J of the fetched items, the
+// rank-ordered updates, further passes if the items did not fit one; then a
+// barrier.
+template <int BS, typename TC>
+__device__ __forceinline__ void lic_finish(TC *__restrict__ y, const double *__restrict__ r, const LicState &L,
+                                           LicPass<BS> &P, const LicArgs &la, int tid, int nt) {
+    (void)tid;
+    if (L.nitems == 0) return;  // uniform over the workgroup
+    const int32_t *rb = la.rb + 9 * L.s;
+    const int nf = L.nitems / BS;
+    for (int p0 = 0;; p0 += kLicItems * nt) {  // passes: the same count for every lane
+        double rv[kLicItems][BS];
+#pragma unroll
+        for (int u = 0; u < kLicItems; ++u)
+#pragma unroll
+            for (int d = 0; d < BS; ++d) rv[u][d] = r[(int64_t)P.rec[u].y * BS + d];
+        // ranks present in this subdomain: k while rb[k] < nf (at most 8)
+        for (int k = 0; k < 8 && rb[k] < nf; ++k) {
+            const int lo = rb[k] * BS, hi = rb[k + 1] * BS;
+#pragma unroll
+            for (int u = 0; u < kLicItems; ++u) {
+                const int it = P.item[u];
+                if (it < L.nitems && it >= lo && it < hi) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int d = 0; d < BS; ++d) t += (double)P.cf[u][d] * rv[u][d];
+                    const int c = it % BS;
+                    y[P.rec[u].x * BS + c] += static_cast<TC>(t);
+                }
+            }
+            __syncthreads();
+        }
+        if (p0 + kLicItems * nt >= L.nitems) break;
+        lic_fetch<BS>(P, la, L, p0 + kLicItems * nt + tid, nt);
+    }
 }
 
 // The subdomain's slice of r into LDS: each thread issues kLoadU loads
@@ -313,9 +333,12 @@ __global__ __launch_bounds__(NT) void k_dd_apply(
     const int s = blockIdx.x;
     const int64_t base = (int64_t)s * S;
     const int tid = threadIdx.x;
+    LicState lst;
+    LicPass<BS> lpass;
+    if constexpr (LIC) lic_begin<BS>(lst, lpass, base, S, s, la, tid, NT);
     load_slice<TC>(y, r + base * BS, S * BS, tid, NT);
     __syncthreads();
-    if constexpr (LIC) lic_correct_lds<BS, TC>(y, r, base, s, la, tid, NT);
+    if constexpr (LIC) lic_finish<BS, TC>(y, r, lst, lpass, la, tid, NT);
     plain_lower<BS, TS, TC, NT, false>(y, base, s, Loff, Llp, Lrow, Lbp, Lcol, Lval);
     plain_upper<BS, TS, TC, NT, false, true>(y, base, s, Uoff, Ulp, Urow, Ubp, Ucol, Uval, Dval);
     store_slice<TC>(z + base * BS, y, S * BS, tid, NT);
@@ -795,9 +818,12 @@ __device__ __forceinline__ void apply_slots_sub(
     // wavefronts for the widest level, so no wavefront is idle at every level
     const int nt = blockDim.x;
     const double *rs = r + base * BS;
+    LicState lst;
+    LicPass<BS> lpass;
+    if constexpr (LIC) lic_begin<BS>(lst, lpass, base, S, s, la, tid, nt);
     load_slice<TC>(y, rs, S * BS, tid, nt);
     __syncthreads();
-    if constexpr (LIC) lic_correct_lds<BS, TC>(y, r, base, s, la, tid, nt);
+    if constexpr (LIC) lic_finish<BS, TC>(y, r, lst, lpass, la, tid, nt);
     const int wrow0 = __builtin_amdgcn_readfirstlane(wave) * RPW;  // first slot of this wavefront
     sweep_slots<BS, TS, TC, MB, PD, false>(y, base, S, s, Loff, Llp, Ldesc, Lval, slot, wrow0, lane_ok, c);
     sweep_slots<BS, TS, TC, MB, PD, true>(y, base, S, s, Uoff, Ulp, Udesc, Uval, slot, wrow0, lane_ok, c);
@@ -810,11 +836,13 @@ __global__ __launch_bounds__(NT) void k_dd_apply_slots(
     const double *__restrict__ r, double *__restrict__ z, int S, const int32_t *__restrict__ Loff,
     const int32_t *__restrict__ Llp, const uint64_t *__restrict__ Ldesc, const TS *__restrict__ Lval,
     const int32_t *__restrict__ Uoff, const int32_t *__restrict__ Ulp, const uint64_t *__restrict__ Udesc,
-    const TS *__restrict__ Uval, const int32_t *__restrict__ state, LicArgs la) {
+    const TS *__restrict__ Uval, const int32_t *__restrict__ state, LicArgs la, int64_t vstride) {
     if (state != nullptr && *state != 0) return;
     extern __shared__ unsigned char dd_smem[];
-    apply_slots_sub<BS, TS, TC, MB, PD, LIC>(reinterpret_cast<TC *>(dd_smem), blockIdx.x, r, z, S, Loff, Llp, Ldesc,
-                                             Lval, Uoff, Ulp, Udesc, Uval, la);
+    // right-hand side blockIdx.y of a batch stored one after another
+    const int64_t off = (int64_t)blockIdx.y * vstride;
+    apply_slots_sub<BS, TS, TC, MB, PD, LIC>(reinterpret_cast<TC *>(dd_smem), blockIdx.x, r + off, z + off, S, Loff,
+                                             Llp, Ldesc, Lval, Uoff, Ulp, Udesc, Uval, la);
 }
 
 // ------------------------------------------------------------------------
@@ -1259,12 +1287,12 @@ static void factor_ptrs(const dd_ctx *h, bool slots, const TS **lv, const TS **u
 }
 
 static LicArgs lic_args(const dd_ctx *h) {
-    return LicArgs{h->lic.bsub, h->lic.brow, h->lic.fJ, h->lic.C};
+    return LicArgs{h->lic.fptr, h->lic.rb, h->lic.lrec, h->lic.Cr};
 }
 
 template <int BS, typename TS, typename TC, int NT, int MB, bool LIC>
 static hipError_t launch_slots(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st,
-                               const TS *lv, const TS *uv) {
+                               const TS *lv, const TS *uv, int nrhs) {
     constexpr int PD = sizeof(TS) == 8 ? DDILU_PD64 : DDILU_PD32;
     auto kern = k_dd_apply_slots<BS, TS, TC, NT, MB, PD, LIC>;
     static bool done = false;
@@ -1274,18 +1302,19 @@ static hipError_t launch_slots(dd_ctx *h, const double *r, double *z, const int3
     // wavefronts for the widest level (at most NT / 64)
     constexpr int RPW = kWave / BS;
     const int nt = std::max(kWave, std::min(NT, (h->max_level_width + RPW - 1) / RPW * kWave));
-    kern<<<h->nsub, nt, lds, st>>>(r, z, h->S, h->lev[0].off, h->lev[0].ptr, h->sw[0].desc, lv, h->lev[1].off,
-                                   h->lev[1].ptr, h->sw[1].desc, uv, state, lic_args(h));
+    kern<<<dim3(h->nsub, nrhs), nt, lds, st>>>(r, z, h->S, h->lev[0].off, h->lev[0].ptr, h->sw[0].desc, lv,
+                                               h->lev[1].off, h->lev[1].ptr, h->sw[1].desc, uv, state, lic_args(h),
+                                               h->n * BS);
     return hipGetLastError();
 }
 
 template <int BS, typename TS, typename TC, int NT, bool LIC>
 static hipError_t launch_slots_mb(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st,
-                                  const TS *lv, const TS *uv) {
+                                  const TS *lv, const TS *uv, int nrhs = 1) {
     switch (h->slots) {
-        case 1: return launch_slots<BS, TS, TC, NT, 1, LIC>(h, r, z, state, st, lv, uv);
-        case 2: return launch_slots<BS, TS, TC, NT, 2, LIC>(h, r, z, state, st, lv, uv);
-        default: return launch_slots<BS, TS, TC, NT, 3, LIC>(h, r, z, state, st, lv, uv);
+        case 1: return launch_slots<BS, TS, TC, NT, 1, LIC>(h, r, z, state, st, lv, uv, nrhs);
+        case 2: return launch_slots<BS, TS, TC, NT, 2, LIC>(h, r, z, state, st, lv, uv, nrhs);
+        default: return launch_slots<BS, TS, TC, NT, 3, LIC>(h, r, z, state, st, lv, uv, nrhs);
     }
 }
 
@@ -1454,7 +1483,8 @@ static hipError_t launch_ablation(dd_ctx *h, int variant, const double *r, doubl
 }
 
 template <int BS, typename TS, typename TC, int NT>
-static hipError_t launch_typed(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st) {
+static hipError_t launch_typed(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st,
+                               int nrhs) {
     const Sweep &L = h->sw[0], &U = h->sw[1];
     const int lds = h->S * BS * (int)sizeof(TC);
     constexpr int RPP = (kWave / BS) * (NT / kWave);
@@ -1476,8 +1506,16 @@ static hipError_t launch_typed(dd_ctx *h, const double *r, double *z, const int3
         const TS *lv, *uv, *dv;
         factor_ptrs<TS>(h, true, &lv, &uv, &dv);
         if constexpr (BS == 3)
-            if (lic) return launch_slots_mb<BS, TS, TC, NT, true>(h, r, z, state, st, lv, uv);
-        return launch_slots_mb<BS, TS, TC, NT, false>(h, r, z, state, st, lv, uv);
+            if (lic) return launch_slots_mb<BS, TS, TC, NT, true>(h, r, z, state, st, lv, uv, nrhs);
+        return launch_slots_mb<BS, TS, TC, NT, false>(h, r, z, state, st, lv, uv, nrhs);
+    }
+    if (nrhs > 1) {  // the other kernels take one right-hand side per launch
+        const int64_t m = h->n * BS;
+        for (int q = 0; q < nrhs; ++q) {
+            hipError_t e = launch_typed<BS, TS, TC, NT>(h, r + q * m, z + q * m, state, st, 1);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
     }
     const TS *lv, *uv, *dv;
     factor_ptrs<TS>(h, false, &lv, &uv, &dv);
@@ -1520,47 +1558,52 @@ static int pick_threads(const dd_ctx *h) {
 }
 
 template <int BS, typename TS, typename TC>
-static hipError_t launch_nt(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st) {
+static hipError_t launch_nt(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st, int nrhs) {
     switch (pick_threads(h)) {
-        case 64: return launch_typed<BS, TS, TC, 64>(h, r, z, state, st);
-        case 128: return launch_typed<BS, TS, TC, 128>(h, r, z, state, st);
-        case 256: return launch_typed<BS, TS, TC, 256>(h, r, z, state, st);
-        case 512: return launch_typed<BS, TS, TC, 512>(h, r, z, state, st);
-        default: return launch_typed<BS, TS, TC, 1024>(h, r, z, state, st);
+        case 64: return launch_typed<BS, TS, TC, 64>(h, r, z, state, st, nrhs);
+        case 128: return launch_typed<BS, TS, TC, 128>(h, r, z, state, st, nrhs);
+        case 256: return launch_typed<BS, TS, TC, 256>(h, r, z, state, st, nrhs);
+        case 512: return launch_typed<BS, TS, TC, 512>(h, r, z, state, st, nrhs);
+        default: return launch_typed<BS, TS, TC, 1024>(h, r, z, state, st, nrhs);
     }
 }
 
 template <int BS>
-static hipError_t launch_bs(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st) {
+static hipError_t launch_bs(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st, int nrhs) {
     switch (h->precision) {
-        case DD_FP32: return launch_nt<BS, float, float>(h, r, z, state, st);
-        case DD_MIXED: return launch_nt<BS, float, double>(h, r, z, state, st);
-        default: return launch_nt<BS, double, double>(h, r, z, state, st);
+        case DD_FP32: return launch_nt<BS, float, float>(h, r, z, state, st, nrhs);
+        case DD_MIXED: return launch_nt<BS, float, double>(h, r, z, state, st, nrhs);
+        default: return launch_nt<BS, double, double>(h, r, z, state, st, nrhs);
     }
 }
 
 hipError_t launch_apply(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st) {
-    return h->bs == 3 ? launch_bs<3>(h, r, z, state, st) : launch_bs<1>(h, r, z, state, st);
+    return launch_apply_batch(h, r, z, 1, st, state);
+}
+
+hipError_t launch_apply_batch(dd_ctx *h, const double *r, double *z, int nrhs, hipStream_t st,
+                              const int32_t *state) {
+    return h->bs == 3 ? launch_bs<3>(h, r, z, state, st, nrhs) : launch_bs<1>(h, r, z, state, st, nrhs);
 }
 
 // a = M_DD^{-T} g: the slot kernel run on the transposed factor streams (FP64,
 // no correction); needs 3x3 blocks, the slot layout and one-pass levels.
 template <int NT>
-static hipError_t launch_adjoint_nt(dd_ctx *h, const double *g, double *a, hipStream_t st) {
+static hipError_t launch_adjoint_nt(dd_ctx *h, const double *g, double *a, int nrhs, hipStream_t st) {
     constexpr int RPP = (kWave / 3) * (NT / kWave);
     if (h->max_level_width > RPP) return hipErrorInvalidValue;
     const double *lv = h->lic.adj_val[0], *uv = h->lic.adj_val[1];
-    return launch_slots_mb<3, double, double, NT, false>(h, g, a, nullptr, st, lv, uv);
+    return launch_slots_mb<3, double, double, NT, false>(h, g, a, nullptr, st, lv, uv, nrhs);
 }
 
-hipError_t launch_apply_adjoint(dd_ctx *h, const double *g, double *a, hipStream_t st) {
-    if (h->bs != 3 || !h->slots || !h->lic.ready) return hipErrorInvalidValue;
+hipError_t launch_apply_adjoint(dd_ctx *h, const double *g, double *a, int nrhs, hipStream_t st) {
+    if (h->bs != 3 || !h->slots || !h->lic.ready || !h->lic.adj_val[1]) return hipErrorInvalidValue;
     switch (pick_threads(h)) {
-        case 64: return launch_adjoint_nt<64>(h, g, a, st);
-        case 128: return launch_adjoint_nt<128>(h, g, a, st);
-        case 256: return launch_adjoint_nt<256>(h, g, a, st);
-        case 512: return launch_adjoint_nt<512>(h, g, a, st);
-        default: return launch_adjoint_nt<1024>(h, g, a, st);
+        case 64: return launch_adjoint_nt<64>(h, g, a, nrhs, st);
+        case 128: return launch_adjoint_nt<128>(h, g, a, nrhs, st);
+        case 256: return launch_adjoint_nt<256>(h, g, a, nrhs, st);
+        case 512: return launch_adjoint_nt<512>(h, g, a, nrhs, st);
+        default: return launch_adjoint_nt<1024>(h, g, a, nrhs, st);
     }
 }
 

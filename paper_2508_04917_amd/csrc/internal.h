@@ -59,12 +59,16 @@ struct Levels {
 // the training workspace).
 struct Lic {
     int32_t ready = 0, active = 0;
-    int32_t nf = 0, nb = 0;       // faces; rows with at least one face
+    int32_t nf = 0;               // faces
     int32_t *fptr = nullptr;      // [n+1] faces of each row (CSR order)
     int32_t *fI = nullptr, *fJ = nullptr, *fq = nullptr;  // [nf] row, column, block position in A
     int32_t *diag = nullptr;      // [n] diagonal block position of each row of A
-    int4 *brow = nullptr;         // [nb] rows with faces, ascending: {row, first face, face count, 0}
-    int32_t *bsub = nullptr;      // [nsub+1] first entry of brow of each subdomain
+    // the apply's copy of the faces, rank-major per subdomain (first face of
+    // every row, then second faces, ...): records, CSR index, coefficients
+    int2 *lrec = nullptr;         // [nf] {local row, J}
+    int32_t *lperm = nullptr;     // [nf] CSR face index of each rank-major position
+    float *Cr = nullptr;          // [nf*9] C in rank-major order
+    int32_t *rb = nullptr;        // [nsub*9] faces of ranks < k of subdomain s at rb[9s + k]
     float *X = nullptr;           // [nf*27] features
     float *C = nullptr;           // [nf*9] coefficients
     float *H1 = nullptr, *H2 = nullptr, *G1 = nullptr, *G2 = nullptr, *dC = nullptr;
@@ -72,6 +76,7 @@ struct Lic {
     double *Z = nullptr, *G = nullptr, *A = nullptr;
     int32_t work_q = 0;
     double *adj_val[2] = {nullptr, nullptr};  // transposed slot streams (U^T lower, L^T + inv_D^T upper)
+    int32_t adj_ready = 0;                    // adj_val packed from the current factors
 };
 
 // Device scalars of one BiCGSTAB run (all FP64 except the control words).
@@ -96,6 +101,8 @@ struct dd_ctx {
     int32_t graph = 0;            // labels from the graph partitioner (no geometry: nx = n, sx = S)
     int64_t n = 0, nnzb = 0;
     int32_t *part_id = nullptr, *new2old = nullptr, *old2new = nullptr;
+    int32_t *asrc = nullptr;      // [nnzb] input block of each reordered block (for ilu0_refactor)
+    int32_t *tsrc = nullptr;      // [nnzt] block of A of each block of the dropped pattern
     // full reordered matrix
     int32_t *aptr = nullptr, *acol = nullptr;
     double *aval = nullptr;
@@ -107,6 +114,7 @@ struct dd_ctx {
     ddilu::Levels lev[2];
     ddilu::Sweep sw[2];
     int32_t factored = 0;
+    int32_t patterned = 0;        // drop, levels and streaming layouts built (ilu0_refactor may run)
     int32_t precision = DD_FP64;
     int32_t max_level_width = 0;  // widest level of any subdomain, L or U
     int32_t profile = 0;          // time every apply inside bicgstab_solve
@@ -198,9 +206,19 @@ hipError_t launch_cast32(dd_ctx *h, hipStream_t st);
 hipError_t launch_pack_slots(dd_ctx *h, int which, hipStream_t st);
 hipError_t launch_max_count(int64_t n, const int32_t *cnt, int32_t *out, hipStream_t st);
 hipError_t launch_export_factors(dd_ctx *h, double *f, hipStream_t st);
+// out[k] = val[src[k]] for nblk blocks of bb values
+hipError_t launch_gather_blocks(int64_t nblk, int bb, const int32_t *src, const double *val, double *out,
+                                hipStream_t st);
+// rewrite the sliced ELL copy's values after A's values changed
+hipError_t refresh_spmv_layout(dd_ctx *h, hipStream_t st);
 
 hipError_t launch_apply(dd_ctx *h, const double *r, double *z, const int32_t *state,
                         hipStream_t st);
+// nrhs applies of right-hand sides stored one after another (n*bs apart):
+// one launch (grid.y = right-hand side) where the slot kernel runs, else one
+// launch per right-hand side
+hipError_t launch_apply_batch(dd_ctx *h, const double *r, double *z, int nrhs, hipStream_t st,
+                              const int32_t *state = nullptr);
 int apply_lds_bytes(const dd_ctx *h, int precision);
 int spin_lds_bytes(const dd_ctx *h);
 // 0 if the handle's precision and correction allow apply variant v, else the
@@ -249,12 +267,18 @@ hipError_t launch_diag_positions(dd_ctx *h, int32_t *diag, hipStream_t st);
 // learned correction
 int lic_setup(dd_ctx *h, hipStream_t st);
 int lic_coeffs_from_params(dd_ctx *h, const float *params, bool keep_hidden, hipStream_t st);
+// refresh the apply's rank-major copy of C after C changed
+int lic_publish_coeffs(dd_ctx *h, hipStream_t st);
 int lic_loss_grad_run(dd_ctx *h, const float *params, int Q, const double *R, const double *Zs, const double *den,
                       double *loss, float *grad, int accumulate, hipStream_t st);
 int lic_targets_run(dd_ctx *h, int Q, const double *R, double *Zs, double *den, hipStream_t st);
 hipError_t launch_adam(int np, float *P, const float *G, float *M, float *V, int t, float lr, float b1, float b2,
                        float eps, hipStream_t st);
-hipError_t launch_apply_adjoint(dd_ctx *h, const double *g, double *a, hipStream_t st);
+// nrhs adjoint applies (right-hand sides n*3 apart) in one launch; the
+// transposed streams must have been packed (lic_adjoint_streams)
+hipError_t launch_apply_adjoint(dd_ctx *h, const double *g, double *a, int nrhs, hipStream_t st);
+// pack the transposed factor streams of the adjoint apply (once per factorisation)
+int lic_adjoint_streams(dd_ctx *h, hipStream_t st);
 // the preconditioner bicgstab_solve uses (DD apply, or the global ILU0 apply)
 hipError_t launch_precond(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st);
 constexpr int32_t kWaitFailed = -64;  // solve state word after a dependency wait hit its bound

@@ -113,6 +113,19 @@ void build_spmv_layout(dd_ctx *h, hipStream_t st) {
     if (hipGetLastError() == hipSuccess && hipStreamSynchronize(st) == hipSuccess) h->ell_state = 1;
 }
 
+// New values of A on the same pattern: rewrite the sliced ELL copy in place.
+hipError_t refresh_spmv_layout(dd_ctx *h, hipStream_t st) {
+    if (h->ell_state != 1) return hipSuccess;
+    const int rpw = kWave / h->bs, bb = h->bs * h->bs;
+    const int64_t nslots = (h->n + rpw - 1) / rpw * kUnroll * rpw;
+    const unsigned g = (unsigned)std::min<int64_t>((nslots * bb + 255) / 256, 1 << 20);
+    if (h->bs == 3)
+        k_ell_fill<3><<<g, 256, 0, st>>>(h->n, h->aptr, h->acol, h->aval, h->ell_col, h->ell_val, nslots);
+    else
+        k_ell_fill<1><<<g, 256, 0, st>>>(h->n, h->aptr, h->acol, h->aval, h->ell_col, h->ell_val, nslots);
+    return hipGetLastError();
+}
+
 // one row product, CSR or sliced ELL
 template <int BS, bool ELL>
 __device__ __forceinline__ double row_product(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,

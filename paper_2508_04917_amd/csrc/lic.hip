@@ -51,18 +51,44 @@ __global__ void k_face_fill(int64_t n, int S, const int32_t *__restrict__ ptr, c
         }
 }
 
-// rows with at least one face: flag for the boundary-row compaction
-__global__ void k_bflag(int64_t n, const int32_t *__restrict__ fptr, int32_t *flag) {
+// Rank-major faces (the apply's copy): faces of rank k (a row's k-th face)
+// of subdomain s occupy positions fptr[sS] + rb[9s + k] ... in row order.
+// One pass per rank present: flag the rows with more than k faces, scan, and
+// place their k-th faces; rb[9s + k + 1] = rb[9s + k] + rows of s flagged.
+__global__ void k_rank_flag(int64_t n, int k, const int32_t *__restrict__ fptr, int32_t *flag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) flag[i] = fptr[i + 1] > fptr[i];
+    if (i < n) flag[i] = fptr[i + 1] - fptr[i] > k;
 }
 
-__global__ void k_bfill(int64_t n, int S, const int32_t *__restrict__ fptr, const int32_t *__restrict__ bpos,
-                        int4 *brow, int32_t *bsub) {
+__global__ void k_rank_place(int64_t n, int S, int k, const int32_t *__restrict__ fptr, const int32_t *__restrict__ fJ,
+                             const int32_t *__restrict__ pre, const int32_t *__restrict__ rb, int2 *lrec,
+                             int32_t *lperm) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (fptr[i + 1] > fptr[i]) brow[bpos[i]] = make_int4((int32_t)i, fptr[i], fptr[i + 1] - fptr[i], 0);
-    if (i % S == 0) bsub[i / S] = bpos[i];  // first boundary row of the subdomain
+    if (i >= n || fptr[i + 1] - fptr[i] <= k) return;
+    const int64_t s = i / S, b = s * S;
+    const int32_t pos = fptr[b] + rb[9 * s + k] + (pre[i] - pre[b]);
+    const int32_t f = fptr[i] + k;
+    lrec[pos] = make_int2((int32_t)(i - b), fJ[f]);
+    lperm[pos] = f;
+}
+
+__global__ void k_rank_count(int nsub, int S, int k, const int32_t *__restrict__ pre, int32_t *rb) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < nsub) rb[9 * s + k + 1] = rb[9 * s + k] + (pre[(int64_t)(s + 1) * S] - pre[(int64_t)s * S]);
+}
+
+// the apply's copy of C: Cr[p] = C[lperm[p]]
+__global__ void k_rank_coeffs(int64_t nf, const int32_t *__restrict__ lperm, const float *__restrict__ C, float *Cr) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nf * 9) return;
+    const int64_t p = e / 9;
+    Cr[e] = C[(int64_t)lperm[p] * 9 + (e - p * 9)];
+}
+
+// status[7] = the most faces of any row (the apply's rank table holds 8)
+__global__ void k_face_limits(int64_t n, const int32_t *__restrict__ fptr, int32_t *status) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicMax(&status[7], fptr[i + 1] - fptr[i]);
 }
 
 __global__ void k_sym_check(int64_t n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
@@ -95,108 +121,222 @@ __global__ void k_features(int64_t nf, const int32_t *__restrict__ fI, const int
 }
 
 // ---------------------------------------------------------------- MLP (FP32)
-// One thread per face; the 6,537 parameters are staged in LDS.  When H1/H2
-// are given the hidden activations are kept for the backward pass.
+// On the matrix cores (v_mfma_f32_16x16x4_f32: D[16][16] += A[16][4] B[4][16];
+// lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds
+// D[4(l/16) + r][l%16] in accumulator r).  A wavefront evaluates 16 faces at
+// a time with the faces along the columns.  Layer 1 is H1^T (64 x 16) =
+// W1 (64 x 27) X^T as four 16-row tiles over seven steps of four inputs (the
+// 28th input a zero), so lane l = 16 g + j ends with H1^T[16 t + 4 g + r]
+// [face j] in accumulator r of tile t.  Layers 2 and 3 take those registers
+// as their B operand unchanged by visiting their 64 inputs in the order the
+// layout gives (step (t', r) takes inputs 16 t' + 4 g + r from lane group g;
+// every input once), with the weight operand loaded in that same order.
+// The weight operands stay in registers for all of a wavefront's faces.
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ mf4 mfma4(float a, float b, mf4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+constexpr int kMlpBlocks = 2048;  // workgroups of 4 wavefronts, each looping over tiles of 16 faces
+
+// C = W3 relu(W2 relu(W1 x + b1) + b2) + b3 per face; with H1/H2 given the
+// hidden activations are kept for the backward pass.
 __global__ __launch_bounds__(256) void k_mlp_forward(int64_t nf, const float *__restrict__ P,
                                                      const float *__restrict__ X, float *__restrict__ C,
                                                      float *__restrict__ H1, float *__restrict__ H2) {
-    __shared__ float w[kNParam];
-    for (int i = threadIdx.x; i < kNParam; i += blockDim.x) w[i] = P[i];
-    __syncthreads();
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nf) return;
-    float x[kIn], h1[kHid], h2[kHid];
+    const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
+    float w1[4][7], w2[4][16], w3[16], b1[4][4], b2[4][4], b3[4];
 #pragma unroll
-    for (int k = 0; k < kIn; ++k) x[k] = X[f * kIn + k];
+    for (int t = 0; t < 4; ++t) {
 #pragma unroll
-    for (int i = 0; i < kHid; ++i) {
-        float s = w[oB1 + i];
+        for (int s = 0; s < 7; ++s) {
+            const int k = 4 * s + g;
+            w1[t][s] = k < kIn ? P[oW1 + (16 * t + j) * kIn + k] : 0.f;
+        }
 #pragma unroll
-        for (int k = 0; k < kIn; ++k) s += w[oW1 + i * kIn + k] * x[k];
-        h1[i] = s > 0.f ? s : 0.f;
+        for (int u = 0; u < 16; ++u) w2[t][u] = P[oW2 + (16 * t + j) * kHid + 16 * (u >> 2) + 4 * g + (u & 3)];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            b1[t][r] = P[oB1 + 16 * t + 4 * g + r];
+            b2[t][r] = P[oB2 + 16 * t + 4 * g + r];
+        }
     }
 #pragma unroll
-    for (int i = 0; i < kHid; ++i) {
-        float s = w[oB2 + i];
+    for (int u = 0; u < 16; ++u) w3[u] = j < kOut ? P[oW3 + j * kHid + 16 * (u >> 2) + 4 * g + (u & 3)] : 0.f;
 #pragma unroll
-        for (int k = 0; k < kHid; ++k) s += w[oW2 + i * kHid + k] * h1[k];
-        h2[i] = s > 0.f ? s : 0.f;
-    }
-    for (int i = 0; i < kOut; ++i) {
-        float s = w[oB3 + i];
+    for (int r = 0; r < 4; ++r) b3[r] = 4 * g + r < kOut ? P[oB3 + 4 * g + r] : 0.f;
+
+    // one wavefront per SIMD fits these registers: the next tile's inputs are
+    // fetched while the current tile computes
+    auto fetch_x = [&](int64_t tile, float (&xb)[7]) {
+        const int64_t f = tile * 16 + j;
 #pragma unroll
-        for (int k = 0; k < kHid; ++k) s += w[oW3 + i * kHid + k] * h2[k];
-        C[f * kOut + i] = s;
-    }
-    if (H1) {
+        for (int s = 0; s < 7; ++s) {
+            const int k = 4 * s + g;
+            xb[s] = (f < nf && k < kIn) ? X[f * kIn + k] : 0.f;
+        }
+    };
+    const int64_t ntile = (nf + 15) / 16, tstep = (int64_t)gridDim.x * 4;
+    float xn[7];
+    fetch_x((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6), xn);
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntile; tile += tstep) {
+        const int64_t f = tile * 16 + j;
+        const bool fok = f < nf;
+        float xb[7];
 #pragma unroll
-        for (int k = 0; k < kHid; ++k) {
-            H1[f * kHid + k] = h1[k];
-            H2[f * kHid + k] = h2[k];
+        for (int s = 0; s < 7; ++s) xb[s] = xn[s];
+        fetch_x(tile + tstep, xn);
+        mf4 h1[4], h2[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            mf4 acc = {b1[t][0], b1[t][1], b1[t][2], b1[t][3]};
+#pragma unroll
+            for (int s = 0; s < 7; ++s) acc = mfma4(w1[t][s], xb[s], acc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r] = acc[r] > 0.f ? acc[r] : 0.f;
+            h1[t] = acc;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            mf4 acc = {b2[t][0], b2[t][1], b2[t][2], b2[t][3]};
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc = mfma4(w2[t][u], h1[u >> 2][u & 3], acc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r] = acc[r] > 0.f ? acc[r] : 0.f;
+            h2[t] = acc;
+        }
+        mf4 o = {b3[0], b3[1], b3[2], b3[3]};
+#pragma unroll
+        for (int u = 0; u < 16; ++u) o = mfma4(w3[u], h2[u >> 2][u & 3], o);
+        if (fok) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (4 * g + r < kOut) C[f * kOut + 4 * g + r] = o[r];
+            if (H1) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    *reinterpret_cast<mf4 *>(H1 + f * kHid + 16 * t + 4 * g) = h1[t];
+                    *reinterpret_cast<mf4 *>(H2 + f * kHid + 16 * t + 4 * g) = h2[t];
+                }
+            }
         }
     }
 }
 
 // Backward through the two hidden layers, per face: G2 = W3^T dOUT (masked by
-// h2 > 0), G1 = W2^T G2 (masked by h1 > 0).
+// h2 > 0), G1 = W2^T G2 (masked by h1 > 0); the same tiling as the forward
+// pass, the transposed weights as the A operand.
 __global__ __launch_bounds__(256) void k_mlp_backprop(int64_t nf, const float *__restrict__ P,
                                                       const float *__restrict__ dOUT, const float *__restrict__ H1,
                                                       const float *__restrict__ H2, float *__restrict__ G1,
                                                       float *__restrict__ G2) {
-    __shared__ float w[kNParam];
-    for (int i = threadIdx.x; i < kNParam; i += blockDim.x) w[i] = P[i];
-    __syncthreads();
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nf) return;
-    float d[kOut], g2[kHid];
+    const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
+    float w3t[4][3], w2t[4][16];
 #pragma unroll
-    for (int i = 0; i < kOut; ++i) d[i] = dOUT[f * kOut + i];
+    for (int t = 0; t < 4; ++t) {
 #pragma unroll
-    for (int k = 0; k < kHid; ++k) {
-        float s = 0.f;
+        for (int s = 0; s < 3; ++s) {
+            const int k = 4 * s + g;
+            w3t[t][s] = k < kOut ? P[oW3 + k * kHid + 16 * t + j] : 0.f;
+        }
 #pragma unroll
-        for (int i = 0; i < kOut; ++i) s += w[oW3 + i * kHid + k] * d[i];
-        g2[k] = H2[f * kHid + k] > 0.f ? s : 0.f;
-        G2[f * kHid + k] = g2[k];
+        for (int u = 0; u < 16; ++u) w2t[t][u] = P[oW2 + (16 * (u >> 2) + 4 * g + (u & 3)) * kHid + 16 * t + j];
     }
+    const int64_t ntile = (nf + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntile; tile += (int64_t)gridDim.x * 4) {
+        const int64_t f = tile * 16 + j;
+        const bool fok = f < nf;
+        const int64_t fc = fok ? f : 0;  // a valid face for the masks' loads
+        float db[3];
 #pragma unroll
-    for (int k = 0; k < kHid; ++k) {
-        float s = 0.f;
+        for (int s = 0; s < 3; ++s) {
+            const int k = 4 * s + g;
+            db[s] = (fok && k < kOut) ? dOUT[f * kOut + k] : 0.f;
+        }
+        mf4 g2[4];
 #pragma unroll
-        for (int i = 0; i < kHid; ++i) s += w[oW2 + i * kHid + k] * g2[i];
-        G1[f * kHid + k] = H1[f * kHid + k] > 0.f ? s : 0.f;
+        for (int t = 0; t < 4; ++t) {
+            mf4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < 3; ++s) acc = mfma4(w3t[t][s], db[s], acc);
+            const mf4 h = *reinterpret_cast<const mf4 *>(H2 + fc * kHid + 16 * t + 4 * g);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r] = h[r] > 0.f ? acc[r] : 0.f;
+            g2[t] = acc;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            mf4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc = mfma4(w2t[t][u], g2[u >> 2][u & 3], acc);
+            const mf4 h = *reinterpret_cast<const mf4 *>(H1 + fc * kHid + 16 * t + 4 * g);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r] = h[r] > 0.f ? acc[r] : 0.f;
+            if (fok) {
+                *reinterpret_cast<mf4 *>(G1 + f * kHid + 16 * t + 4 * g) = acc;
+                *reinterpret_cast<mf4 *>(G2 + f * kHid + 16 * t + 4 * g) = g2[t];
+            }
+        }
     }
 }
 
-// Weight gradients as sums over faces, deterministic: workgroup (chunk, layer)
-// sums its chunk of faces for every output entry in a fixed order into a FP64
-// partial; k_wgrad_sum adds the chunk partials in order.
-// Layer l: out[i][k] = sum_f A[f][i] B[f][k] (A = dOUT/G2/G1, B = H2/H1/X),
-// bias[i] = sum_f A[f][i].
-constexpr int kFaceChunk = 1024;
+static unsigned mlp_blocks(int64_t nf) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(((nf + 15) / 16 + 3) / 4, kMlpBlocks));
+}
 
-__global__ __launch_bounds__(256) void k_wgrad_partial(int64_t nf, const float *__restrict__ dOUT,
-                                                       const float *__restrict__ G2, const float *__restrict__ G1,
-                                                       const float *__restrict__ H2, const float *__restrict__ H1,
-                                                       const float *__restrict__ X, double *__restrict__ part) {
-    const int chunk = blockIdx.x, layer = blockIdx.y;
+// Weight gradients on the matrix cores.  Layer l's gradient is a product
+// over faces, dW[i][k] = sum_f A[f][i] B[f][k] with A = dOUT / G2 / G1 and
+// B = H2 / H1 / X, and its bias gradient db[i] = sum_f A[f][i] is the same
+// product with a column of ones appended to B.  The outputs are cut into
+// 16x16 tiles (layer 0: 1 x 5 tiles of 9 x 65 entries, layer 1: 4 x 5 of
+// 64 x 65, layer 2: 4 x 2 of 64 x 28; 33 tiles, every parameter in exactly
+// one), and one wavefront accumulates one tile over one chunk of kWgFaces
+// faces with v_mfma_f32_16x16x4_f32 (four faces per instruction: lane l
+// supplies A[f0 + l/16][i0 + l%16] and B[f0 + l/16][k0 + l%16], and holds
+// D[i0 + 4(l/16) + r][k0 + l%16] in accumulator r).  Positions outside a
+// layer's matrix contribute zeros.  The chunk's tile is written as FP64
+// partials and k_wgrad_sum adds the chunks in order, so the result does not
+// depend on timing.
+constexpr int kWgFaces = 256;  // faces per chunk
+constexpr int kWgTiles = 33;   // 16x16 output tiles over the three layers
+
+__global__ __launch_bounds__(256) void k_wgrad_mfma(int64_t nf, const float *__restrict__ dOUT,
+                                                    const float *__restrict__ G2, const float *__restrict__ G1,
+                                                    const float *__restrict__ H2, const float *__restrict__ H1,
+                                                    const float *__restrict__ X, double *__restrict__ part) {
+    const int chunk = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int tile = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (tile >= kWgTiles) return;  // whole wavefronts
     const float *A, *B;
-    int na, nb, ow, ob;
-    if (layer == 0) { A = dOUT; na = kOut; B = H2; nb = kHid; ow = oW3; ob = oB3; }
-    else if (layer == 1) { A = G2; na = kHid; B = H1; nb = kHid; ow = oW2; ob = oB2; }
-    else { A = G1; na = kHid; B = X; nb = kIn; ow = oW1; ob = oB1; }
-    const int64_t f0 = (int64_t)chunk * kFaceChunk;
-    const int64_t f1 = f0 + kFaceChunk < nf ? f0 + kFaceChunk : nf;
+    int na, nb, ow, ob, ti, tk;
+    if (tile < 5) {
+        A = dOUT; na = kOut; B = H2; nb = kHid; ow = oW3; ob = oB3; ti = 0; tk = tile;
+    } else if (tile < 25) {
+        A = G2; na = kHid; B = H1; nb = kHid; ow = oW2; ob = oB2; ti = (tile - 5) / 5; tk = (tile - 5) % 5;
+    } else {
+        A = G1; na = kHid; B = X; nb = kIn; ow = oW1; ob = oB1; ti = (tile - 25) / 2; tk = (tile - 25) % 2;
+    }
+    const int i = ti * 16 + (lane & 15), k = tk * 16 + (lane & 15), fl = lane >> 4;
+    const int64_t f0 = (int64_t)chunk * kWgFaces;
+    mf4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
+    for (int g = 0; g < kWgFaces; g += 4) {
+        const int64_t f = f0 + g + fl;
+        const bool fok = f < nf;
+        const float a = (fok && i < na) ? A[f * na + i] : 0.f;
+        const float b = !fok ? 0.f : (k < nb ? B[f * nb + k] : (k == nb ? 1.f : 0.f));
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    }
     double *out = part + (int64_t)chunk * kNParam;
-    for (int e = threadIdx.x; e < na * (nb + 1); e += blockDim.x) {
-        const int i = e / (nb + 1), k = e % (nb + 1);
-        double s = 0.0;
-        if (k < nb) {
-            for (int64_t f = f0; f < f1; ++f) s += (double)A[f * na + i] * (double)B[f * nb + k];
-            out[ow + i * nb + k] = s;
-        } else {
-            for (int64_t f = f0; f < f1; ++f) s += (double)A[f * na + i];
-            out[ob + i] = s;
+    const int col = tk * 16 + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = ti * 16 + 4 * (lane >> 4) + r;
+        if (row < na) {
+            if (col < nb) out[ow + row * nb + col] = (double)acc[r];
+            else if (col == nb) out[ob + row] = (double)acc[r];
         }
     }
 }
@@ -236,17 +376,30 @@ __global__ __launch_bounds__(256) void k_lic_residual(int64_t m, const double *_
     }
 }
 
-// loss += sum_q (sum of partials of probe q) / (Q den_q); one thread.
-__global__ void k_lic_loss(int Q, int nblk, int part_stride, const double *__restrict__ part,
-                           const double *__restrict__ den, double *loss) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// loss += sum_q (sum of partials of probe q) / (Q den_q); one workgroup.
+// Thread t adds partials t, t + kLossT, ... of each probe in order, then a
+// fixed tree over the workgroup, probes in order: the result does not depend
+// on timing.
+constexpr int kLossT = 256;
+
+__global__ __launch_bounds__(kLossT) void k_lic_loss(int Q, int nblk, int part_stride,
+                                                     const double *__restrict__ part,
+                                                     const double *__restrict__ den, double *loss) {
+    __shared__ double sh[kLossT];
     double L = 0.0;
     for (int q = 0; q < Q; ++q) {
         double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += part[q * part_stride + b];
-        L += s / (Q * den[q]);
+        for (int b = threadIdx.x; b < nblk; b += kLossT) s += part[q * part_stride + b];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = kLossT / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) L += sh[0] / (Q * den[q]);
+        __syncthreads();
     }
-    *loss += L;
+    if (threadIdx.x == 0) *loss += L;
 }
 
 // den_q = ||z_DD,q - z*_q||^2 (one workgroup per probe, fixed order).
@@ -354,8 +507,8 @@ int lic_setup(dd_ctx *h, hipStream_t st) {
     const unsigned g = (unsigned)((h->n + T - 1) / T);
     Lic &L = h->lic;
     hipError_t e;
-    int32_t st6 = 0;
-    e = hipMemcpyAsync(h->status + 6, &st6, sizeof(int32_t), hipMemcpyHostToDevice, st);
+    const int32_t st67[2] = {0, 0};
+    e = hipMemcpyAsync(h->status + 6, st67, 2 * sizeof(int32_t), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return h->fail(DD_EHIP, "memcpy: %s", hipGetErrorString(e));
     k_sym_check<<<g, T, 0, st>>>(h->n, h->aptr, h->acol, h->status);
     int32_t *cnt = nullptr, *flag = nullptr, *bpos = nullptr;
@@ -364,19 +517,23 @@ int lic_setup(dd_ctx *h, hipStream_t st) {
     if (!rc) rc = h->alloc(&bpos, h->n + 1);
     if (!rc && !L.fptr) rc = h->alloc(&L.fptr, h->n + 1);
     if (!rc && !L.diag) rc = h->alloc(&L.diag, h->n);
-    if (!rc && !L.bsub) rc = h->alloc(&L.bsub, h->nsub + 1);
+    if (!rc && !L.rb) rc = h->alloc(&L.rb, 9 * (int64_t)h->nsub);
     if (rc) return rc;
     k_face_count<<<g, T, 0, st>>>(h->n, h->S, h->aptr, h->acol, cnt);
     e = exclusive_scan(cnt, L.fptr, h->n, h->scan_tmp, st);
     if (e != hipSuccess) return h->fail(DD_EHIP, "scan: %s", hipGetErrorString(e));
-    int32_t nf = 0, sym = 0;
+    k_face_limits<<<g, T, 0, st>>>(h->n, L.fptr, h->status);
+    int32_t nf = 0, sym[2] = {0, 0};
     e = hipMemcpyAsync(&nf, L.fptr + h->n, sizeof(int32_t), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(&sym, h->status + 6, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(sym, h->status + 6, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return h->fail(DD_EHIP, "lic setup: %s", hipGetErrorString(e));
-    if (sym) return h->fail(DD_EINVAL, "the learned correction needs a structurally symmetric pattern");
+    if (sym[0]) return h->fail(DD_EINVAL, "the learned correction needs a structurally symmetric pattern");
+    const int maxrank = sym[1];
+    if (maxrank > 8) return h->fail(DD_EINVAL, "the learned correction supports at most 8 cut faces per row");
     L.nf = nf;
-    for (void *q : {(void *)L.fI, (void *)L.fJ, (void *)L.fq, (void *)L.X, (void *)L.C, (void *)L.brow})
+    for (void *q : {(void *)L.fI, (void *)L.fJ, (void *)L.fq, (void *)L.X, (void *)L.C, (void *)L.lrec,
+                    (void *)L.lperm, (void *)L.Cr})
         if (q) {
             h->allocs.erase(std::find(h->allocs.begin(), h->allocs.end(), q));
             (void)hipFree(q);
@@ -386,36 +543,33 @@ int lic_setup(dd_ctx *h, hipStream_t st) {
     if (!rc) rc = h->alloc(&L.fq, nf);
     if (!rc) rc = h->alloc(&L.X, (int64_t)nf * kIn);
     if (!rc) rc = h->alloc(&L.C, (int64_t)nf * kOut);
+    if (!rc) rc = h->alloc(&L.lrec, nf);
+    if (!rc) rc = h->alloc(&L.lperm, nf);
+    if (!rc) rc = h->alloc(&L.Cr, (int64_t)nf * kOut);
     if (rc) return rc;
     k_face_fill<<<g, T, 0, st>>>(h->n, h->S, h->aptr, h->acol, L.fptr, L.fI, L.fJ, L.fq);
-    // diagonal position of every row of the full matrix
-    k_bflag<<<g, T, 0, st>>>(h->n, L.fptr, flag);
-    e = exclusive_scan(flag, bpos, h->n, h->scan_tmp, st);
-    if (e != hipSuccess) return h->fail(DD_EHIP, "scan: %s", hipGetErrorString(e));
-    int32_t nb = 0;
-    e = hipMemcpyAsync(&nb, bpos + h->n, sizeof(int32_t), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return h->fail(DD_EHIP, "lic setup: %s", hipGetErrorString(e));
-    L.nb = nb;
-    rc = h->alloc(&L.brow, nb);
-    if (rc) return rc;
-    k_bfill<<<g, T, 0, st>>>(h->n, h->S, L.fptr, bpos, L.brow, L.bsub);
-    e = hipMemcpyAsync(L.bsub + h->nsub, &nb, sizeof(int32_t), hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return h->fail(DD_EHIP, "memcpy: %s", hipGetErrorString(e));
+    // the apply's rank-major copy of the faces
+    e = hipMemsetAsync(L.rb, 0, 9 * (size_t)h->nsub * sizeof(int32_t), st);
+    if (e != hipSuccess) return h->fail(DD_EHIP, "memset: %s", hipGetErrorString(e));
+    const unsigned gs = (unsigned)((h->nsub + T - 1) / T);
+    for (int k = 0; k < 8; ++k) {
+        if (k < maxrank) {
+            k_rank_flag<<<g, T, 0, st>>>(h->n, k, L.fptr, flag);
+            e = exclusive_scan(flag, bpos, h->n, h->scan_tmp, st);
+            if (e != hipSuccess) return h->fail(DD_EHIP, "scan: %s", hipGetErrorString(e));
+            k_rank_place<<<g, T, 0, st>>>(h->n, h->S, k, L.fptr, L.fJ, bpos, L.rb, L.lrec, L.lperm);
+        } else {
+            // no row has more than k faces: the boundaries after the last rank repeat
+            e = hipMemsetAsync(bpos, 0, (h->n + 1) * sizeof(int32_t), st);
+            if (e != hipSuccess) return h->fail(DD_EHIP, "memset: %s", hipGetErrorString(e));
+        }
+        k_rank_count<<<gs, T, 0, st>>>(h->nsub, h->S, k, bpos, L.rb);
+    }
     hipError_t ed = launch_diag_positions(h, L.diag, st);
     if (ed != hipSuccess) return h->fail(DD_EHIP, "diag: %s", hipGetErrorString(ed));
     if (nf) k_features<<<(unsigned)((nf + T - 1) / T), T, 0, st>>>(nf, L.fI, L.fJ, L.fq, L.diag, h->aval, L.X);
-    // adjoint slot streams
-    const int bb = 9;
-    for (int w = 0; w < 2; ++w) {
-        if (!L.adj_val[w]) {
-            rc = h->alloc(&L.adj_val[w], h->n * (h->slots + w) * bb);
-            if (rc) return rc;
-        }
-    }
-    for (int w = 0; w < 2; ++w)
-        k_pack_adjoint<<<g, T, 0, st>>>(h->n, h->S, w, h->slots, h->tptr, h->tcol, h->lu, h->invd,
-                                        h->lev[w].rows, L.adj_val[w]);
+    // the adjoint apply's streams are packed on first use (training only)
+    L.adj_ready = 0;
     e = hipStreamSynchronize(st);
     for (void *q : {(void *)cnt, (void *)flag, (void *)bpos}) {
         h->allocs.erase(std::find(h->allocs.begin(), h->allocs.end(), q));
@@ -427,6 +581,37 @@ int lic_setup(dd_ctx *h, hipStream_t st) {
     return DD_OK;
 }
 
+int lic_adjoint_streams(dd_ctx *h, hipStream_t st) {
+    Lic &L = h->lic;
+    if (!L.ready) return h->fail(DD_ESTATE, "the adjoint apply needs lic_setup");
+    if (L.adj_ready) return DD_OK;
+    const int T = 256, bb = 9;
+    const unsigned g = (unsigned)((h->n + T - 1) / T);
+    for (int w = 0; w < 2; ++w) {
+        if (!L.adj_val[w]) {
+            int rc = h->alloc(&L.adj_val[w], h->n * (h->slots + w) * bb);
+            if (rc) return rc;
+        }
+    }
+    for (int w = 0; w < 2; ++w)
+        k_pack_adjoint<<<g, T, 0, st>>>(h->n, h->S, w, h->slots, h->tptr, h->tcol, h->lu, h->invd,
+                                        h->lev[w].rows, L.adj_val[w]);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return h->fail(DD_EHIP, "adjoint streams: %s", hipGetErrorString(e));
+    L.adj_ready = 1;
+    return DD_OK;
+}
+
+// The apply reads the coefficients in rank-major order: refresh that copy
+// after every change of C.
+int lic_publish_coeffs(dd_ctx *h, hipStream_t st) {
+    Lic &L = h->lic;
+    if (L.nf) k_rank_coeffs<<<(unsigned)(((int64_t)L.nf * 9 + 255) / 256), 256, 0, st>>>(L.nf, L.lperm, L.C, L.Cr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return h->fail(DD_EHIP, "coefficients: %s", hipGetErrorString(e));
+    return DD_OK;
+}
+
 int lic_coeffs_from_params(dd_ctx *h, const float *params, bool keep_hidden, hipStream_t st) {
     Lic &L = h->lic;
     if (keep_hidden && !L.H1) {
@@ -435,11 +620,11 @@ int lic_coeffs_from_params(dd_ctx *h, const float *params, bool keep_hidden, hip
         if (rc) return rc;
     }
     if (L.nf)
-        k_mlp_forward<<<(unsigned)((L.nf + 255) / 256), 256, 0, st>>>(L.nf, params, L.X, L.C, keep_hidden ? L.H1 : nullptr,
-                                                                     keep_hidden ? L.H2 : nullptr);
+        k_mlp_forward<<<mlp_blocks(L.nf), 256, 0, st>>>(L.nf, params, L.X, L.C, keep_hidden ? L.H1 : nullptr,
+                                                        keep_hidden ? L.H2 : nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return h->fail(DD_EHIP, "mlp forward: %s", hipGetErrorString(e));
-    return DD_OK;
+    return lic_publish_coeffs(h, st);
 }
 
 // Loss and gradient of one problem (see the file comment); adds to *loss and
@@ -467,31 +652,33 @@ int lic_loss_grad_run(dd_ctx *h, const float *params, int Q, const double *R, co
         rc = h->alloc(&L.dC, (int64_t)std::max(L.nf, 1) * 9);
         if (!rc) rc = h->alloc(&L.G1, (int64_t)std::max(L.nf, 1) * kHid);
         if (!rc) rc = h->alloc(&L.G2, (int64_t)std::max(L.nf, 1) * kHid);
-        const int nchunk = (int)((std::max(L.nf, 1) + kFaceChunk - 1) / kFaceChunk);
+        const int nchunk = (int)((std::max(L.nf, 1) + kWgFaces - 1) / kWgFaces);
         if (!rc) rc = h->alloc(&L.wpart, (int64_t)nchunk * kNParam);
         if (rc) return rc;
     }
+    rc = lic_adjoint_streams(h, st);
+    if (rc) return rc;
     const int32_t saved_prec = h->precision, saved_active = L.active;
     h->precision = DD_FP64;
     L.active = 1;
-    hipError_t e = hipSuccess;
-    for (int q = 0; q < Q && e == hipSuccess; ++q) e = launch_apply(h, R + q * m, L.Z + q * m, nullptr, st);
+    // the Q probes' applies in one launch each (grid.y = probe)
+    hipError_t e = launch_apply_batch(h, R, L.Z, Q, st);
     L.active = saved_active;
     const int gres = (int)std::min<int64_t>((m + 255) / 256, 2048);
     if (e == hipSuccess) {
         k_lic_residual<<<dim3(gres, Q), 256, 0, st>>>(m, L.Z, Zs, den, Q, L.G, L.rpart, 2048);
-        k_lic_loss<<<1, 1, 0, st>>>(Q, gres, 2048, L.rpart, den, loss);
+        k_lic_loss<<<1, kLossT, 0, st>>>(Q, gres, 2048, L.rpart, den, loss);
         e = hipGetLastError();
     }
-    for (int q = 0; q < Q && e == hipSuccess; ++q) e = launch_apply_adjoint(h, L.G + q * m, L.A + q * m, st);
+    if (e == hipSuccess) e = launch_apply_adjoint(h, L.G, L.A, Q, st);
     h->precision = saved_prec;
     if (e != hipSuccess) return h->fail(DD_EHIP, "lic applies: %s", hipGetErrorString(e));
     if (L.nf) {
         k_lic_dC<<<(unsigned)((L.nf * 9 + 255) / 256), 256, 0, st>>>(L.nf, m, Q, L.fI, L.fJ, L.A, R, L.dC);
-        const unsigned gf = (unsigned)((L.nf + 255) / 256);
-        k_mlp_backprop<<<gf, 256, 0, st>>>(L.nf, params, L.dC, L.H1, L.H2, L.G1, L.G2);
-        const int nchunk = (int)((L.nf + kFaceChunk - 1) / kFaceChunk);
-        k_wgrad_partial<<<dim3(nchunk, 3), 256, 0, st>>>(L.nf, L.dC, L.G2, L.G1, L.H2, L.H1, L.X, L.wpart);
+        k_mlp_backprop<<<mlp_blocks(L.nf), 256, 0, st>>>(L.nf, params, L.dC, L.H1, L.H2, L.G1, L.G2);
+        const int nchunk = (int)((L.nf + kWgFaces - 1) / kWgFaces);
+        k_wgrad_mfma<<<dim3(nchunk, (kWgTiles + 3) / 4), 256, 0, st>>>(L.nf, L.dC, L.G2, L.G1, L.H2, L.H1, L.X,
+                                                                        L.wpart);
         k_wgrad_sum<<<(kNParam + 255) / 256, 256, 0, st>>>(nchunk, L.wpart, grad, accumulate);
     } else if (!accumulate) {
         e = hipMemsetAsync(grad, 0, kNParam * sizeof(float), st);
@@ -511,7 +698,7 @@ int lic_targets_run(dd_ctx *h, int Q, const double *R, double *Zs, double *den, 
     h->precision = DD_FP64;
     h->lic.active = 0;
     hipError_t e = launch_global_apply(h, R, Zs, Q, st);
-    for (int q = 0; q < Q && e == hipSuccess; ++q) e = launch_apply(h, R + q * m, zdd + q * m, nullptr, st);
+    if (e == hipSuccess) e = launch_apply_batch(h, R, zdd, Q, st);
     h->precision = saved_prec;
     h->lic.active = saved_active;
     if (e == hipSuccess) {

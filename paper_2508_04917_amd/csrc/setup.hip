@@ -261,6 +261,14 @@ hipError_t launch_drop_count(dd_ctx *h, int32_t *tbeg, int32_t *tlen, hipStream_
     return hipGetLastError();
 }
 
+hipError_t launch_gather_blocks(int64_t nblk, int bb, const int32_t *src, const double *val, double *out,
+                                hipStream_t st) {
+    const int T = 256;
+    const int64_t ne = nblk * bb;
+    if (ne > 0) k_gather_blocks<<<(unsigned)((ne + T - 1) / T), T, 0, st>>>(ne, bb, src, val, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_drop_rows(dd_ctx *h, const int32_t *tbeg, int32_t *tsrc, hipStream_t st) {
     const int T = 256;
     k_drop_rows<<<(unsigned)((h->n + T - 1) / T), T, 0, st>>>(h->n, tbeg, h->tptr, h->acol, h->tcol, tsrc,

@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "DD_OK", -1: "DD_EINVAL", -2: "DD_ENOTDIV", -3: "DD_ELDS", -4
 
 # every symbol include/ddilu.h declares
 EXPORTS = ("dd_auto_subdims", "dd_device_caps", "dd_partition", "dd_partition_graph", "dd_get_info", "dd_get_partition",
-           "dd_get_reordered", "ilu0_factor", "dd_set_precision", "dd_get_levels", "dd_get_factors",
+           "dd_get_reordered", "ilu0_factor", "ilu0_refactor", "dd_set_precision", "dd_get_levels", "dd_get_factors",
            "dd_trsv_apply", "dd_spmv", "bicgstab_solve", "bicgstab_solve_noalloc", "dd_set_apply_variant", "dd_set_fusion", "dd_set_lic_fallback",
            "dd_set_profiling",
            "dd_set_residual_history", "dd_global_factor", "dd_global_apply", "dd_set_preconditioner",
@@ -86,6 +86,7 @@ def lib():
             "dd_get_partition": (C.c_int, [vp, vp, vp, vp, vp]),
             "dd_get_reordered": (C.c_int, [vp, vp, vp, vp, vp]),
             "ilu0_factor": (C.c_int, [vp, i32, vp]),
+            "ilu0_refactor": (C.c_int, [vp, vp, vp]),
             "dd_set_precision": (C.c_int, [vp, i32, vp]),
             "dd_get_levels": (C.c_int, [vp, i32, vp, vp, vp, vp]),
             "dd_get_factors": (C.c_int, [vp, vp, vp, vp, vp]),
@@ -264,6 +265,14 @@ def dd_get_reordered(h: Handle, stream=None):
 
 def ilu0_factor(h: Handle, precision=DD_FP64, stream=None):
     _check(lib().ilu0_factor(h.ptr, precision, _stream(stream)), h)
+
+
+def ilu0_refactor(h: Handle, val, stream=None):
+    """New values (CUDA float64, the partitioned matrix's blocks in the order
+    given to dd_partition) on the handle's pattern."""
+    info = dd_get_info(h)
+    _dev_check(val, torch.float64, int(info["nnzb"]) * int(info["bs"]) ** 2, "val")
+    _check(lib().ilu0_refactor(h.ptr, _ptr(val), _stream(stream)), h)
 
 
 def dd_set_precision(h: Handle, precision, stream=None):

@@ -125,6 +125,35 @@ def test_corrected_apply_parity(prob, variant):
     check_close(zg, zo, 3, 1e-12, what=f"corrected apply v{variant}", scale=sc)
 
 
+@pytest.mark.parametrize("variant", [1, 3])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_corrected_apply_several_passes(variant, prec):
+    """Thin subdomains (4x4x12: levels of at most 16 rows, so one wavefront
+    per workgroup) with 224 cut faces each: the correction's 672 items take
+    two passes of the workgroup's lanes, and corner rows have three faces."""
+    print("[lic] problem 16x16x24, subdomains 4x4x12 (several correction passes)", flush=True)
+    p = lognormal_problem(16, 16, 24, seed=45, sigma=1.5, corr_len=3.0)
+    s = DDSolver.from_problem(p, sub=(4, 4, 12))
+    st = O.setup(p, (4, 4, 12))
+    L = O.LicOracle(st)
+    dd.lic_setup(s.h)
+    Co = L.coeffs(trained_like_params()).astype(np.float32)
+    dd.lic_set_coeffs(s.h, cu(Co, torch.float32))
+    dd.dd_set_apply_variant(s.h, variant)
+    r = np.random.default_rng(7).standard_normal(st.n * 3)
+    if prec == "mixed":
+        s.set_precision(dd.DD_MIXED)
+        zo = st.apply_fp32_factors(O.lic_correct(st.n, L.faces, Co.astype(np.float64), r), round_input=False)
+        tol = 1e-10
+    else:
+        zo = L.apply(Co.astype(np.float64), r)
+        tol = 1e-12
+    zg = np_(s.apply(cu(r)))
+    s.close()
+    sc = dd_scale(st, O.lic_correct(st.n, L.faces, np.abs(Co.astype(np.float64)), np.abs(r)))
+    check_close(zg, zo, 3, tol, what=f"corrected apply, several passes, v{variant} {prec}", scale=sc)
+
+
 def test_targets_loss_and_gradient(prob):
     """GPU FP32 network + FP64 applies vs the FP64 oracle: loss to 1e-5,
     gradient to 1e-3 (relative, in norm)."""
