@@ -117,6 +117,13 @@ typedef struct {
                                   more copy of A's blocks), 0 = the CSR
                                   arrays (rows of more than 7 blocks, or
                                   no memory for the copy)                 */
+    int32_t apply_layout;      /* streams the automatic apply reads: 1 =
+                                  slot layout (rows of at most 3 blocks per
+                                  triangle), 2 = segmented slot layout
+                                  (longer rows split into segments of 3
+                                  blocks within one wavefront), 0 = CSR
+                                  streams only (rows of more than 24
+                                  blocks per triangle)                    */
 } dd_info;
 
 /* Result of bicgstab_solve. */

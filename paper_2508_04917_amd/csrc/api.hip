@@ -317,6 +317,7 @@ extern "C" int dd_get_info(dd_handle h, dd_info *info) {
     info->lds_bytes = apply_lds_bytes(h, h->precision);
     info->max_row_blocks = h->max_row_a;
     info->spmv_layout = h->ell_state == 1 ? 1 : 0;
+    info->apply_layout = h->slots ? 1 : (h->seg ? 2 : 0);
     return DD_OK;
 }
 
@@ -411,12 +412,23 @@ static int build_slots(dd_ctx *h, hipStream_t st) {
         if (s.desc) { release(h, s.desc); release(h, s.sval64); }
         if (s.sval32) release(h, s.sval32);
         s.desc = nullptr; s.sval64 = nullptr; s.sval32 = nullptr;
+        s.snpos = 0;
     }
     const int mr = std::max(h->sw[0].max_row, h->sw[1].max_row);
     h->slots = mr <= kMaxSlots ? std::max(mr, 1) : 0;
-    if (!h->slots) return DD_OK;
+    h->seg = 0;
+    if (!h->slots) {
+        // rows of more than three blocks: the segmented layout, for the apply's
+        // workgroups of 1,024 lanes, when no row needs more than kSegMax segments
+        if (mr > 3 * kSegMax) return DD_OK;
+        const int rpw = kWave / h->bs, cw = rpw * (1024 / kWave);
+        for (int w = 0; w < 2; ++w) RCHK(build_seg_layout(h, w, cw, rpw, st));
+        h->seg = 1;
+        return DD_OK;
+    }
     for (int w = 0; w < 2; ++w) {
         Sweep &s = h->sw[w];
+        s.snpos = h->n;
         RCHK(h->alloc(&s.desc, h->n));
         RCHK(h->alloc(&s.sval64, h->n * (h->slots + w) * bb));  // upper: + inv_D
         HCHK(launch_pack_slots(h, w, st));
@@ -426,10 +438,12 @@ static int build_slots(dd_ctx *h, hipStream_t st) {
 
 static int ensure_fp32(dd_ctx *h, hipStream_t st) {
     const int bb = h->bs * h->bs;
-    if (h->sw[0].val32 && h->sw[1].val32 && h->sw[1].d32 && (!h->slots || h->sw[0].sval32)) return DD_OK;
+    const bool sl = h->slots || h->seg;
+    const int mb = h->seg ? 3 : h->slots;
+    if (h->sw[0].val32 && h->sw[1].val32 && h->sw[1].d32 && (!sl || h->sw[0].sval32)) return DD_OK;
     for (int w = 0; w < 2; ++w) {
         if (!h->sw[w].val32) RCHK(h->alloc(&h->sw[w].val32, h->sw[w].nblk * bb));
-        if (h->slots && !h->sw[w].sval32) RCHK(h->alloc(&h->sw[w].sval32, h->n * (h->slots + w) * bb));
+        if (sl && !h->sw[w].sval32) RCHK(h->alloc(&h->sw[w].sval32, h->sw[w].snpos * (mb + w) * bb));
     }
     if (!h->sw[1].d32) RCHK(h->alloc(&h->sw[1].d32, h->n * bb));
     HCHK(launch_cast32(h, st));
@@ -534,6 +548,10 @@ extern "C" int ilu0_refactor(dd_handle h, const double *val, void *hip_stream) {
     if (h->slots) {
         HCHK(launch_pack_slots(h, 0, st));
         HCHK(launch_pack_slots(h, 1, st));
+    }
+    if (h->seg) {
+        HCHK(launch_seg_pack(h, 0, st));
+        HCHK(launch_seg_pack(h, 1, st));
     }
     if (h->sw[0].val32) HCHK(launch_cast32(h, st));
     HCHK(hipStreamSynchronize(st));

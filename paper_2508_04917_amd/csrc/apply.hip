@@ -679,11 +679,21 @@ __device__ __forceinline__ void slot_claim(SlotRegs<BS, TS, MB, UPPER> &R) {
     if constexpr (RR::T4) asm volatile("; claim %0" : "+v"(R.run.w));
 }
 
-template <int BS, typename TS, typename TC, int MB, bool UPPER>
+// SEG: the segmented layout (15-bit descriptor fields, see Sweep).  A
+// position computes the partial result of its segment: the owner (a row's
+// first segment) starts from y_I (lower) or inv_D y_I (upper), a
+// continuation from zero (its inv_D run is zero); the owner then adds its
+// continuations' partials, held by the next m - 1 positions of the same
+// wavefront, in segment order through cross-lane reads, and alone writes the
+// row.  All lanes take part in the reads (those without a position hold
+// zero), so every value read is defined.
+template <int BS, typename TS, typename TC, int MB, bool UPPER, bool SEG = false>
 __device__ __forceinline__ void slot_compute(TC *__restrict__ y, const SlotRegs<BS, TS, MB, UPPER> &R, int c) {
     using SR = SlotRegs<BS, TS, MB, UPPER>;
     using RR = RawRun<SR::NB>;
-    if (!R.ok) return;
+    if constexpr (!SEG) {
+        if (!R.ok) return;
+    }
     uint32_t wd[SR::NB / 4];
 #pragma unroll
     for (int i = 0; i < RR::N16; ++i)
@@ -703,7 +713,8 @@ __device__ __forceinline__ void slot_compute(TC *__restrict__ y, const SlotRegs<
             vals[v] = __builtin_bit_cast(TS, wd[v]);
     }
     const uint64_t desc = (uint64_t)R.desc[0] | ((uint64_t)R.desc[1] << 32);
-    const int I = (int)(desc & 0xffffu);
+    constexpr uint64_t FM = SEG ? 0x7fffu : 0xffffu;  // field mask; all ones = empty slot
+    const int I = SEG && !R.ok ? 0 : (int)(desc & FM);
     // gather every LDS operand first (one round of LDS latency), then the
     // fixed-order arithmetic.  An empty slot holds a zero block: it is
     // applied to y_I (a valid LDS address) instead of being branched around.
@@ -713,49 +724,71 @@ __device__ __forceinline__ void slot_compute(TC *__restrict__ y, const SlotRegs<
     for (int d = 0; d < NI; ++d) yi[d] = y[I * BS + (UPPER ? d : c)];
 #pragma unroll
     for (int k = 0; k < MB; ++k) {
-        const int J = (int)((desc >> (16 * (k + 1))) & 0xffffu);
-        const int Jc = J != 0xffff ? J : I;
+        const int J = (int)((desc >> (16 * (k + 1))) & FM);
+        const int Jc = (J != (int)FM && !(SEG && !R.ok)) ? J : I;
 #pragma unroll
         for (int d = 0; d < BS; ++d) yj[k][d] = y[Jc * BS + d];
     }
     __builtin_amdgcn_sched_barrier(0);
+    const bool cont = SEG && (((desc >> 15) & 1u) != 0 || !R.ok);
     TC acc;
     if constexpr (UPPER) {
         acc = 0;
 #pragma unroll
         for (int d = 0; d < BS; ++d) acc += static_cast<TC>(vals[MB * BS + d]) * yi[d];
     } else {
-        acc = yi[0];
+        acc = cont ? TC(0) : yi[0];
     }
 #pragma unroll
     for (int k = 0; k < MB; ++k)
 #pragma unroll
         for (int d = 0; d < BS; ++d) acc -= static_cast<TC>(vals[k * BS + d]) * yj[k][d];
-    // all lanes of this row read y_I above (same wavefront)
-    __asm__ volatile("" ::: "memory");
-    y[I * BS + c] = acc;
+    if constexpr (SEG) {
+        if (!R.ok) acc = 0;
+        const int m = cont ? 1
+                           : 1 + (int)((desc >> 31) & 1u) + 2 * (int)((desc >> 47) & 1u) +
+                                 4 * (int)((desc >> 63) & 1u);
+        const int lane = threadIdx.x & (kWave - 1);
+        for (int j = 1; j < kSegMax; ++j) {
+            if (!__any(j < m)) break;  // wavefront-uniform
+            const TC v = __shfl(acc, lane + BS * j);
+            if (j < m) acc += v;
+        }
+        __asm__ volatile("" ::: "memory");
+        if (!cont) y[I * BS + c] = acc;
+    } else {
+        // all lanes of this row read y_I above (same wavefront)
+        __asm__ volatile("" ::: "memory");
+        y[I * BS + c] = acc;
+    }
 }
 
-template <int BS, typename TS, typename TC, int MB, int PD, bool UPPER>
-__device__ __forceinline__ void sweep_slots(TC *__restrict__ y, int64_t base, int S, int s,
+// pbase, pcount: the subdomain's positions in the streams (s*S and S, or
+// the segmented layout's offset and count).  SEG: the level table is the
+// chunk table (starts in bits 0-29, bit 30 = barrier after the chunk).
+template <int BS, typename TS, typename TC, int MB, int PD, bool UPPER, bool SEG = false>
+__device__ __forceinline__ void sweep_slots(TC *__restrict__ y, int64_t pbase, int64_t pcount, int s,
                                             const int32_t *__restrict__ off, const int32_t *__restrict__ lp,
                                             const uint64_t *__restrict__ desc, const TS *__restrict__ sval,
                                             int slot, int wrow0, bool lane_ok, int c) {
     static_assert(PD >= 1 && PD <= 3, "prefetch depth 1 to 3");
     using SR = SlotRegs<BS, TS, MB, UPPER>;
     constexpr int PS = SR::NV * BS;  // values per position
-    const u32x4 srd_desc = slice_srd(desc + base, (int64_t)S * 8);
-    const u32x4 srd_val = slice_srd(sval + base * PS, (int64_t)S * PS * sizeof(TS));
+    constexpr int32_t QM = SEG ? 0x3fffffff : 0x7fffffff;
+    const u32x4 srd_desc = slice_srd(desc + pbase, pcount * 8);
+    const u32x4 srd_val = slice_srd(sval + pbase * PS, pcount * PS * (int64_t)sizeof(TS));
     const int32_t o = off[s];
     const int nl = off[s + 1] - o - 1;
     SR R[PD + 1];
-    int busy[PD + 1];
+    int busy[PD + 1], bar[PD + 1];
     // level bounds are read one fetch ahead, so their scalar loads complete
     // during a level's update instead of after the barrier that follows it
     int32_t q0 = lp[o], q1 = lp[o + 1];
     auto fetch = [&](int k, int l) {
-        busy[k] = q0 + wrow0 < q1 ? 1 : 0;
-        slot_fetch<BS, TS, MB, UPPER>(R[k], srd_desc, srd_val, q0, q1, slot, lane_ok, c, busy[k]);
+        const int32_t a0 = q0 & QM, a1 = q1 & QM;
+        bar[k] = SEG ? (q0 >> 30) & 1 : 1;
+        busy[k] = a0 + wrow0 < a1 ? 1 : 0;
+        slot_fetch<BS, TS, MB, UPPER>(R[k], srd_desc, srd_val, a0, a1, slot, lane_ok, c, busy[k]);
         const int ln = l + 1 < nl ? l + 1 : nl - 1;
         q0 = lp[o + ln];
         q1 = lp[o + ln + 1];
@@ -776,9 +809,10 @@ __device__ __forceinline__ void sweep_slots(TC *__restrict__ y, int64_t base, in
             else
                 vm_wait_all();
             slot_claim(R[u]);
+            const int b = bar[u];
             fetch((u + PD) % (PD + 1), l0 + u + PD);
-            slot_compute<BS, TS, TC, MB, UPPER>(y, R[u], c);
-            __syncthreads();
+            slot_compute<BS, TS, TC, MB, UPPER, SEG>(y, R[u], c);
+            if (b) __syncthreads();
         }
     }
     const int rem = nl - nfull;
@@ -787,8 +821,8 @@ __device__ __forceinline__ void sweep_slots(TC *__restrict__ y, int64_t base, in
         if (u < rem) {
             vm_wait_all();
             slot_claim(R[u]);
-            slot_compute<BS, TS, TC, MB, UPPER>(y, R[u], c);
-            __syncthreads();
+            slot_compute<BS, TS, TC, MB, UPPER, SEG>(y, R[u], c);
+            if (bar[u]) __syncthreads();
         }
     }
     // nothing may still be loading into these registers once they are free
@@ -800,12 +834,13 @@ __device__ __forceinline__ void sweep_slots(TC *__restrict__ y, int64_t base, in
 // One subdomain's apply with the slot layout: r's slice into LDS (plus the
 // learned correction), the lower sweep, the upper sweep with the diagonal
 // scaling, and the slice back to z.
-template <int BS, typename TS, typename TC, int MB, int PD, bool LIC>
+template <int BS, typename TS, typename TC, int MB, int PD, bool LIC, bool SEG = false>
 __device__ __forceinline__ void apply_slots_sub(
     TC *__restrict__ y, int s, const double *__restrict__ r, double *__restrict__ z, int S,
     const int32_t *__restrict__ Loff, const int32_t *__restrict__ Llp, const uint64_t *__restrict__ Ldesc,
     const TS *__restrict__ Lval, const int32_t *__restrict__ Uoff, const int32_t *__restrict__ Ulp,
-    const uint64_t *__restrict__ Udesc, const TS *__restrict__ Uval, const LicArgs &la) {
+    const uint64_t *__restrict__ Udesc, const TS *__restrict__ Uval, const LicArgs &la,
+    const int32_t *__restrict__ Lgpos = nullptr, const int32_t *__restrict__ Ugpos = nullptr) {
     constexpr int RPW = kWave / BS;
     const int64_t base = (int64_t)s * S;
     const int tid = threadIdx.x;
@@ -825,24 +860,33 @@ __device__ __forceinline__ void apply_slots_sub(
     __syncthreads();
     if constexpr (LIC) lic_finish<BS, TC>(y, r, lst, lpass, la, tid, nt);
     const int wrow0 = __builtin_amdgcn_readfirstlane(wave) * RPW;  // first slot of this wavefront
-    sweep_slots<BS, TS, TC, MB, PD, false>(y, base, S, s, Loff, Llp, Ldesc, Lval, slot, wrow0, lane_ok, c);
-    sweep_slots<BS, TS, TC, MB, PD, true>(y, base, S, s, Uoff, Ulp, Udesc, Uval, slot, wrow0, lane_ok, c);
+    if constexpr (SEG) {
+        const int64_t lb = Lgpos[s], ub = Ugpos[s];
+        sweep_slots<BS, TS, TC, MB, PD, false, true>(y, lb, Lgpos[s + 1] - lb, s, Loff, Llp, Ldesc, Lval, slot,
+                                                     wrow0, lane_ok, c);
+        sweep_slots<BS, TS, TC, MB, PD, true, true>(y, ub, Ugpos[s + 1] - ub, s, Uoff, Ulp, Udesc, Uval, slot,
+                                                    wrow0, lane_ok, c);
+    } else {
+        sweep_slots<BS, TS, TC, MB, PD, false>(y, base, S, s, Loff, Llp, Ldesc, Lval, slot, wrow0, lane_ok, c);
+        sweep_slots<BS, TS, TC, MB, PD, true>(y, base, S, s, Uoff, Ulp, Udesc, Uval, slot, wrow0, lane_ok, c);
+    }
     double *zs = z + base * BS;
     store_slice<TC>(zs, y, S * BS, tid, nt);
 }
 
-template <int BS, typename TS, typename TC, int NT, int MB, int PD, bool LIC>
+template <int BS, typename TS, typename TC, int NT, int MB, int PD, bool LIC, bool SEG = false>
 __global__ __launch_bounds__(NT) void k_dd_apply_slots(
     const double *__restrict__ r, double *__restrict__ z, int S, const int32_t *__restrict__ Loff,
     const int32_t *__restrict__ Llp, const uint64_t *__restrict__ Ldesc, const TS *__restrict__ Lval,
     const int32_t *__restrict__ Uoff, const int32_t *__restrict__ Ulp, const uint64_t *__restrict__ Udesc,
-    const TS *__restrict__ Uval, const int32_t *__restrict__ state, LicArgs la, int64_t vstride) {
+    const TS *__restrict__ Uval, const int32_t *__restrict__ state, LicArgs la, int64_t vstride,
+    const int32_t *__restrict__ Lgpos, const int32_t *__restrict__ Ugpos) {
     if (state != nullptr && *state != 0) return;
     extern __shared__ unsigned char dd_smem[];
     // right-hand side blockIdx.y of a batch stored one after another
     const int64_t off = (int64_t)blockIdx.y * vstride;
-    apply_slots_sub<BS, TS, TC, MB, PD, LIC>(reinterpret_cast<TC *>(dd_smem), blockIdx.x, r + off, z + off, S, Loff,
-                                             Llp, Ldesc, Lval, Uoff, Ulp, Udesc, Uval, la);
+    apply_slots_sub<BS, TS, TC, MB, PD, LIC, SEG>(reinterpret_cast<TC *>(dd_smem), blockIdx.x, r + off, z + off, S,
+                                                  Loff, Llp, Ldesc, Lval, Uoff, Ulp, Udesc, Uval, la, Lgpos, Ugpos);
 }
 
 // ------------------------------------------------------------------------
@@ -1304,7 +1348,25 @@ static hipError_t launch_slots(dd_ctx *h, const double *r, double *z, const int3
     const int nt = std::max(kWave, std::min(NT, (h->max_level_width + RPW - 1) / RPW * kWave));
     kern<<<dim3(h->nsub, nrhs), nt, lds, st>>>(r, z, h->S, h->lev[0].off, h->lev[0].ptr, h->sw[0].desc, lv,
                                                h->lev[1].off, h->lev[1].ptr, h->sw[1].desc, uv, state, lic_args(h),
-                                               h->n * BS);
+                                               h->n * BS, nullptr, nullptr);
+    return hipGetLastError();
+}
+
+// The segmented slot layout (rows of more than three blocks): workgroups of
+// 1,024 lanes (the layout's chunks are cut for that width), chunk tables as
+// level tables.
+template <int BS, typename TS, typename TC>
+static hipError_t launch_seg(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st,
+                             const TS *lv, const TS *uv, int nrhs) {
+    constexpr int PD = sizeof(TS) == 8 ? DDILU_PD64 : DDILU_PD32;
+    auto kern = k_dd_apply_slots<BS, TS, TC, 1024, 3, PD, false, true>;
+    static bool done = false;
+    hipError_t e = allow_full_lds(kern, done);
+    if (e != hipSuccess) return e;
+    const int lds = h->S * BS * (int)sizeof(TC);
+    const Sweep &L = h->sw[0], &U = h->sw[1];
+    kern<<<dim3(h->nsub, nrhs), 1024, lds, st>>>(r, z, h->S, L.gchk, L.chk, L.desc, lv, U.gchk, U.chk, U.desc, uv,
+                                                 state, lic_args(h), h->n * BS, L.gpos, U.gpos);
     return hipGetLastError();
 }
 
@@ -1500,6 +1562,12 @@ static hipError_t launch_typed(dd_ctx *h, const double *r, double *z, const int3
     // loop (measured faster than the pipelined one on rows of up to 17
     // blocks: 438 against 730 us at 2M unstructured rows)
     if (variant == 0) variant = 3;
+    // rows of more than three blocks: the segmented slot layout
+    if (variant == 3 && h->seg && !lic) {
+        const TS *lv, *uv, *dv;
+        factor_ptrs<TS>(h, true, &lv, &uv, &dv);
+        return launch_seg<BS, TS, TC>(h, r, z, state, st, lv, uv, nrhs);
+    }
     if (variant == 3 && (!one_pass || !h->slots)) variant = 1;
     if (variant == 2 && lic) variant = 1;  // the correction runs in 1 and 3
     if (variant == 3) {

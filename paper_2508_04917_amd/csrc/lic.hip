@@ -85,10 +85,20 @@ __global__ void k_rank_coeffs(int64_t nf, const int32_t *__restrict__ lperm, con
     Cr[e] = C[(int64_t)lperm[p] * 9 + (e - p * 9)];
 }
 
-// status[7] = the most faces of any row (the apply's rank table holds 8)
-__global__ void k_face_limits(int64_t n, const int32_t *__restrict__ fptr, int32_t *status) {
+// status[7] = the most faces of any row (the apply's rank table holds 8);
+// a maximum over the workgroup first, then one atomic per workgroup
+__global__ __launch_bounds__(256) void k_face_limits(int64_t n, const int32_t *__restrict__ fptr, int32_t *status) {
+    __shared__ int32_t wmax[4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) atomicMax(&status[7], fptr[i + 1] - fptr[i]);
+    int32_t m = i < n ? fptr[i + 1] - fptr[i] : 0;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) m = max(m, __shfl_xor(m, d));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = max(m, wmax[w]);
+        if (m > 0) atomicMax(&status[7], m);
+    }
 }
 
 __global__ void k_sym_check(int64_t n, const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,

@@ -3,6 +3,8 @@
 // 3.2), per-subdomain level sets (Section 4.2.1), block ILU0 + ILDU0
 // (Section 4.3, Algorithm 5) and the packing of the factors into the
 // streaming layout of the apply.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace ddilu {
@@ -681,6 +683,170 @@ hipError_t launch_pack_slots(dd_ctx *h, int which, hipStream_t st) {
     return hipGetLastError();
 }
 
+// ------------------------------------------------- segmented slot layout
+// For sweeps with rows of more than three blocks.  A row with nb blocks
+// becomes m = max(1, ceil(nb/3)) segments of up to three blocks (in column
+// order) at consecutive positions of one wavefront; the first segment (the
+// row's owner) adds the others' partial sums in the apply.  Each level is
+// laid out in chunks of at most cw positions (one workgroup pass of the
+// apply, rpw positions per wavefront); a group that would straddle a
+// wavefront is moved to the next one (the positions skipped are padding), a
+// group that would not fit the chunk starts the next chunk of the level.
+// Only the last chunk of a level is followed by a barrier in the apply.  One
+// thread per subdomain walks its levels (count pass, then fill pass).
+template <bool FILL>
+__global__ void k_seg_walk(int nsub, int S, int cw, int rpw, const int32_t *__restrict__ off,
+                           const int32_t *__restrict__ lp, const int32_t *__restrict__ bptr, int32_t *npos,
+                           int32_t *nchk, const int32_t *__restrict__ gpos, const int32_t *__restrict__ gchk,
+                           int2 *pmap, int32_t *chk) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsub) return;
+    const int32_t o = off[s];
+    const int nl = off[s + 1] - o - 1;
+    const int64_t base = (int64_t)s * S;
+    const int32_t pb = FILL ? gpos[s] : 0, cb = FILL ? gchk[s] : 0;
+    int32_t pos = 0, nc = 0;
+    for (int l = 0; l < nl; ++l) {
+        if (FILL) chk[cb + nc] = pos;  // a level starts a chunk
+        ++nc;
+        int inchunk = 0;
+        for (int32_t k = lp[o + l]; k < lp[o + l + 1]; ++k) {
+            const int64_t p = base + k;
+            const int32_t nb = bptr[p + 1] - bptr[p];
+            const int m = nb > 0 ? (nb + 2) / 3 : 1;
+            int pad = (inchunk % rpw) + m > rpw ? rpw - inchunk % rpw : 0;
+            if (inchunk + pad + m > cw) {  // the next chunk of this level
+                if (FILL) chk[cb + nc] = pos;
+                ++nc;
+                inchunk = 0;
+                pad = 0;
+            }
+            for (int q = 0; q < pad; ++q)
+                if (FILL) pmap[pb + pos + q] = make_int2(-1, 0);
+            pos += pad;
+            inchunk += pad;
+            for (int q = 0; q < m; ++q)
+                if (FILL) pmap[pb + pos + q] = make_int2((int32_t)p, q | (m << 8));
+            pos += m;
+            inchunk += m;
+        }
+        if (FILL) chk[cb + nc - 1] |= 1 << 30;  // barrier after the level's last chunk
+    }
+    if (FILL) {
+        chk[cb + nc] = pos;
+    } else {
+        npos[s] = pos;
+        nchk[s] = nc + 1;
+    }
+}
+
+// Position q: its segment's descriptor and values in the lane-run layout of
+// k_pack_slots (MB = 3).  Padding positions are continuations of local row 0
+// with no blocks (they read y_0 and write nothing); a continuation's inv_D
+// run (upper sweep) is zero.
+template <int BS>
+__global__ void k_seg_pack(int64_t npos, int which, const int2 *__restrict__ pmap, const uint16_t *__restrict__ prow,
+                           const int32_t *__restrict__ bptr, const uint16_t *__restrict__ bcol,
+                           const double *__restrict__ val, const double *__restrict__ dval, uint64_t *desc,
+                           double *sval) {
+    constexpr int BB = BS * BS;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= npos) return;
+    const int NV = (3 + which) * BS;
+    double *o = sval + q * BS * NV;
+    const int2 e = pmap[q];
+    int32_t b0 = 0, b1 = 0;
+    int k = 0;
+    uint64_t d;
+    if (e.x < 0) {
+        d = 0x8000ull;
+        for (int j = 0; j < 3; ++j) d |= 0x7fffull << (16 * (j + 1));
+    } else {
+        k = e.y & 0xff;
+        const int m = e.y >> 8;
+        d = (uint64_t)prow[e.x] | (k > 0 ? 0x8000ull : 0ull);
+        b0 = bptr[e.x] + 3 * k;
+        b1 = min(b0 + 3, bptr[e.x + 1]);
+        for (int j = 0; j < 3; ++j) d |= (uint64_t)(b0 + j < b1 ? bcol[b0 + j] : 0x7fff) << (16 * (j + 1));
+        if (k == 0)
+            for (int j = 0; j < 3; ++j)
+                if (((m - 1) >> j) & 1) d |= 1ull << (16 * (j + 1) + 15);
+    }
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int i = 0; i < BS; ++i)
+#pragma unroll
+            for (int jj = 0; jj < BS; ++jj)
+                o[i * NV + j * BS + jj] = b0 + j < b1 ? val[(int64_t)(b0 + j) * BB + i * BS + jj] : 0.0;
+    if (which == 1)
+#pragma unroll
+        for (int i = 0; i < BS; ++i)
+#pragma unroll
+            for (int jj = 0; jj < BS; ++jj)
+                o[i * NV + 3 * BS + jj] = (e.x >= 0 && k == 0) ? dval[(int64_t)e.x * BB + i * BS + jj] : 0.0;
+    desc[q] = d;
+}
+
+hipError_t launch_seg_pack(dd_ctx *h, int which, hipStream_t st) {
+    const int T = 256;
+    Sweep &w = h->sw[which];
+    const unsigned g = (unsigned)((w.snpos + T - 1) / T);
+    if (w.snpos == 0) return hipSuccess;
+    if (h->bs == 3)
+        k_seg_pack<3><<<g, T, 0, st>>>(w.snpos, which, w.pmap, w.prow, w.bptr, w.bcol, w.val64, w.d64, w.desc,
+                                       w.sval64);
+    else
+        k_seg_pack<1><<<g, T, 0, st>>>(w.snpos, which, w.pmap, w.prow, w.bptr, w.bcol, w.val64, w.d64, w.desc,
+                                       w.sval64);
+    return hipGetLastError();
+}
+
+int build_seg_layout(dd_ctx *h, int which, int cw, int rpw, hipStream_t st) {
+    Sweep &w = h->sw[which];
+    const Levels &L = h->lev[which];
+    const int nsub = h->nsub, T = 256;
+    const unsigned gs = (unsigned)((nsub + T - 1) / T);
+    int32_t *npos = nullptr, *nchk = nullptr;
+    int rc = h->alloc(&npos, nsub);
+    if (!rc) rc = h->alloc(&nchk, nsub);
+    if (!rc && !w.gpos) rc = h->alloc(&w.gpos, nsub + 1);
+    if (!rc && !w.gchk) rc = h->alloc(&w.gchk, nsub + 1);
+    if (rc) return rc;
+    auto drop = [&](void *q) {
+        auto it = std::find(h->allocs.begin(), h->allocs.end(), q);
+        if (it != h->allocs.end()) {
+            (void)hipFree(q);
+            h->allocs.erase(it);
+        }
+    };
+    k_seg_walk<false><<<gs, T, 0, st>>>(nsub, h->S, cw, rpw, L.off, L.ptr, w.bptr, npos, nchk, nullptr, nullptr,
+                                        nullptr, nullptr);
+    hipError_t e = exclusive_scan(npos, w.gpos, nsub, h->scan_tmp, st);
+    if (e == hipSuccess) e = exclusive_scan(nchk, w.gchk, nsub, h->scan_tmp, st);
+    int32_t tot[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(&tot[0], w.gpos + nsub, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&tot[1], w.gchk + nsub, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return h->fail(DD_EHIP, "segmented layout: %s", hipGetErrorString(e));
+    for (void *q : {(void *)w.pmap, (void *)w.chk, (void *)w.desc, (void *)w.sval64, (void *)w.sval32}) drop(q);
+    w.pmap = nullptr; w.chk = nullptr; w.desc = nullptr; w.sval64 = nullptr; w.sval32 = nullptr;
+    const int bb = h->bs * h->bs;
+    w.snpos = tot[0];
+    rc = h->alloc(&w.pmap, tot[0]);
+    if (!rc) rc = h->alloc(&w.chk, tot[1]);
+    if (!rc) rc = h->alloc(&w.desc, tot[0]);
+    if (!rc) rc = h->alloc(&w.sval64, (int64_t)tot[0] * (3 + which) * bb);
+    if (rc) return rc;
+    k_seg_walk<true><<<gs, T, 0, st>>>(nsub, h->S, cw, rpw, L.off, L.ptr, w.bptr, nullptr, nullptr, w.gpos, w.gchk,
+                                       w.pmap, w.chk);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = launch_seg_pack(h, which, st);
+    drop(npos);
+    drop(nchk);
+    if (e != hipSuccess) return h->fail(DD_EHIP, "segmented layout: %s", hipGetErrorString(e));
+    return DD_OK;
+}
+
 // FP64 -> FP32 copies, round to nearest even.
 __global__ void k_cast32(int64_t m, const double *in, float *out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -697,10 +863,11 @@ hipError_t launch_cast32(dd_ctx *h, hipStream_t st) {
     }
     const int64_t m = h->n * bb;
     k_cast32<<<(unsigned)((m + T - 1) / T), T, 0, st>>>(m, h->sw[1].d64, h->sw[1].d32);
-    if (h->slots) {
+    if (h->slots || h->seg) {
+        const int mb = h->seg ? 3 : h->slots;
         for (int w = 0; w < 2; ++w) {
-            const int64_t ms = h->n * (h->slots + w) * bb;  // the upper stream carries inv_D
-            k_cast32<<<(unsigned)((ms + T - 1) / T), T, 0, st>>>(ms, h->sw[w].sval64, h->sw[w].sval32);
+            const int64_t ms = h->sw[w].snpos * (mb + w) * bb;  // the upper stream carries inv_D
+            if (ms) k_cast32<<<(unsigned)((ms + T - 1) / T), T, 0, st>>>(ms, h->sw[w].sval64, h->sw[w].sval32);
         }
     }
     return hipGetLastError();

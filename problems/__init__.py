@@ -12,6 +12,7 @@ from .generators import (  # noqa: F401
     grid_graph,
     unstructured_problem,
     laplacian_scalar,
+    laplacian_blocks,
     random_blocks,
     lognormal_field,
     lognormal_problem,

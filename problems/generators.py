@@ -109,6 +109,19 @@ def random_blocks(nx: int = 64, ny: int = 64, nz: int = 64, seed: int = 2) -> Pr
     return Problem("random_blocks", nx, ny, nz, 3, ptr, col, val, b, seed)
 
 
+def laplacian_blocks(nx: int, ny: int, nz: int, seed: int = 0) -> Problem:
+    """3x3 block 7-point Laplacian (Dirichlet boundary eliminated): diagonal
+    blocks 6 I, coupling blocks -I, i.e. the scalar operator of
+    laplacian_scalar times I_3; the paper's structured test matrices are 3x3
+    BSR Laplacians of this pattern (it does not print their values).  b is
+    N(0,1) from default_rng(seed)."""
+    ptr, col, kind = stencil_pattern(nx, ny, nz)
+    n = nx * ny * nz
+    val = np.where((kind == 3)[:, None, None], 6.0 * np.eye(3), -np.eye(3))
+    b = np.random.default_rng(seed).standard_normal(3 * n)
+    return Problem("laplacian_blocks", nx, ny, nz, 3, ptr, col, np.ascontiguousarray(val), b, seed)
+
+
 def grid_graph(nx: int, ny: int, nz: int):
     """Pattern (brow_ptr, bcol) of the 7-point grid operator (5-point in 2D,
     a path in 1D), diagonal included: a graph with known geometry."""
@@ -278,6 +291,10 @@ WORKLOADS = {
     "unstructured4m_scalar": (unstructured_problem, dict(n=4_096_000, seed=22, bs=1), None),
     # unseen evaluation problems for the learned correction, 128^3
     "lognormal128_eval": (lognormal_problem, dict(nx=128, ny=128, nz=128, seed=2000), None),
+    # the shapes of the paper's laplacian1 / laplacian2 (Table 5): 3x3 block
+    # Laplacians cut into 8x16x16 boxes of 2,048 block rows
+    "laplacian1_bsr3": (laplacian_blocks, dict(nx=128, ny=128, nz=128, seed=31), (8, 16, 16)),
+    "laplacian2_bsr3": (laplacian_blocks, dict(nx=128, ny=128, nz=256, seed=32), (8, 16, 16)),
 }
 
 

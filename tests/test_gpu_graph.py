@@ -111,7 +111,7 @@ def test_reorder_levels_factors(name):
     check_close(np_(f), st.f, st.bs * st.bs, 1e-12, what=f"graph {name} factor blocks")
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 4, 8])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 8])
 @pytest.mark.parametrize("name", list(CASES))
 def test_apply(name, variant):
     p, s, st = case(name)
@@ -123,6 +123,41 @@ def test_apply(name, variant):
         check_close(z_g, z_o, p.bs, 1e-12, what=f"graph {name} apply v{variant}", scale=dd_scale(st, r))
     finally:
         dd.dd_set_apply_variant(s.h, 0)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp32"])
+@pytest.mark.parametrize("name", ["unstructured_bs3", "unstructured_bs1", "unstructured_wide_bs3",
+                                  "unstructured_wide_bs1"])
+def test_apply_reduced_precision(name, prec):
+    """FP32 factors on the graph cases (rows of more than three blocks run the
+    segmented slot layout): against the oracle with the factors rounded to
+    FP32 (and, for DD_FP32, the input and arithmetic in FP32: a bound from
+    FP32 rounding, not from the FP64 tolerance)."""
+    p, s, st = case(name)
+    s.set_precision(dd.DD_MIXED if prec == "mixed" else dd.DD_FP32)
+    try:
+        r = np.random.default_rng(8).standard_normal(p.n * p.bs)
+        z_o = st.apply_fp32_factors(r, round_input=(prec == "fp32"))
+        z_g = np_(s.apply(torch.as_tensor(r, device="cuda")))
+    finally:
+        s.set_precision(dd.DD_FP64)
+    if prec == "mixed":
+        check_close(z_g, z_o, p.bs, 1e-10, what=f"graph {name} apply mixed", scale=dd_scale(st, r))
+    else:  # the FP32 bounds of the structured parity cases
+        check_close(z_g, z_o, p.bs, 2e-4, floor=1e-3, norm_tol=2e-5, what=f"graph {name} apply fp32")
+
+
+@pytest.mark.parametrize("name", ["unstructured_bs3", "unstructured_bs1", "unstructured_wide_bs3"])
+def test_segmented_layout_in_use(name):
+    """Rows of more than three blocks per sweep: the handle builds the
+    segmented slot layout, which the automatic apply then runs."""
+    p, s, st = case(name)
+    ptr, col = np.asarray(st.tptr), np.asarray(st.tcol)
+    rows = np.repeat(np.arange(p.n), np.diff(ptr))
+    longest = max(np.bincount(rows[col < rows], minlength=p.n).max(),
+                  np.bincount(rows[col > rows], minlength=p.n).max())
+    assert longest > 3
+    assert dd.dd_get_info(s.h)["apply_layout"] == 2
 
 
 @pytest.mark.parametrize("name", ["unstructured_wide_bs3", "unstructured_wide_bs1"])
