@@ -98,6 +98,29 @@ def kernels_only(args, p, sub, ptr_d, col_d, val_d, dd, torch):
         nbytes = dd.dd_get_info(h)["apply_bytes"]
         out[name] = {"us_per_apply": round(us, 2), "bytes_per_apply": nbytes, "GB/s": round(nbytes / us / 1e3, 1)}
         log(f"{name}: {us:.1f} us per apply, {nbytes / us / 1e3:.1f} GB/s")
+    # the learned correction on FP32 factors (the metric's learned leg), with
+    # the shipped parameters; bytes as the mixed apply's plus 64 per face
+    # (C_f in FP32, the face's column and r_J)
+    lic_path = os.path.join(ROOT, "paper_2508_04917_amd", "lic_params.npz")
+    if p.bs == 3 and os.path.exists(lic_path):
+        from paper_2508_04917_amd.lic import load_params
+        dd.dd_set_precision(h, dd.DD_MIXED)
+        dd.lic_setup(h)
+        dd.lic_set_params(h, torch.as_tensor(load_params(lic_path)[0], device="cuda:0"))
+        nf = dd.lic_get_faces(h)[0].numel()
+        dd.dd_trsv_apply(h, r, z)
+        ev[0].record()
+        for _ in range(args.applies):
+            dd.dd_trsv_apply(h, r, z)
+        ev[1].record()
+        torch.cuda.synchronize()
+        us = 1e3 * ev[0].elapsed_time(ev[1]) / args.applies
+        nbytes = dd.dd_get_info(h)["apply_bytes"] + 64 * nf
+        out["learned_mixed"] = {"us_per_apply": round(us, 2), "bytes_per_apply": nbytes, "faces": nf,
+                                "GB/s": round(nbytes / us / 1e3, 1)}
+        log(f"learned_mixed: {us:.1f} us per apply, {nbytes / us / 1e3:.1f} GB/s")
+        dd.lic_set_params(h, None)
+        dd.dd_set_precision(h, dd.DD_FP64)
     # SpMV bursts on the layout the handle uses; bytes as the BSR count
     # (FP64 blocks, int32 columns and row pointers, x once, y)
     info = dd.dd_get_info(h)
@@ -110,8 +133,9 @@ def kernels_only(args, p, sub, ptr_d, col_d, val_d, dd, torch):
     us = 1e3 * ev[0].elapsed_time(ev[1]) / args.applies
     bb = info["bs"] * info["bs"]
     nbytes = info["nnzb"] * (bb * 8 + 4) + (info["n"] + 1) * 4 + 2 * info["n"] * info["bs"] * 8
-    out["spmv"] = {"us_per_call": round(us, 2), "layout": "sliced ELL" if info["spmv_layout"] else "CSR",
-                   "bytes_per_call": nbytes, "GB/s": round(nbytes / us / 1e3, 1)}
+    layout = {0: "CSR", 1: "sliced ELL", 2: "sliced ELL, one width per slice"}[info["spmv_layout"]]
+    out["spmv"] = {"us_per_call": round(us, 2), "layout": layout, "bytes_per_call": nbytes,
+                   "GB/s": round(nbytes / us / 1e3, 1)}
     log(f"spmv: {us:.1f} us per call, {nbytes / us / 1e3:.1f} GB/s")
     h.close()
     print(json.dumps(out), flush=True)
@@ -257,7 +281,7 @@ def graph_mode(args, p, ptr_d, col_d, val_d, dd, torch):
     rtol, each timed."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    h = dd.dd_partition_graph(p.n, p.bs, ptr_d, col_d, val_d)
+    h = dd.dd_partition_graph(p.n, p.bs, ptr_d, col_d, val_d, part_rows=args.part_rows)
     torch.cuda.synchronize()
     t_part = time.perf_counter() - t0
     dd.ilu0_factor(h, dd.DD_FP64)
@@ -275,6 +299,14 @@ def graph_mode(args, p, ptr_d, col_d, val_d, dd, torch):
     ev[1].record()
     torch.cuda.synchronize()
     us = 1e3 * ev[0].elapsed_time(ev[1]) / args.applies
+    y = torch.empty_like(r)
+    dd.dd_spmv(h, r, y)
+    ev[0].record()
+    for _ in range(args.applies):
+        dd.dd_spmv(h, r, y)
+    ev[1].record()
+    torch.cuda.synchronize()
+    spmv_us = 1e3 * ev[0].elapsed_time(ev[1]) / args.applies
     b = torch.as_tensor(p.b, device="cuda:0")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -285,11 +317,14 @@ def graph_mode(args, p, ptr_d, col_d, val_d, dd, torch):
            "part_rows": inf["S"], "n_subdomains": inf["nsub"], "dropped_blocks": p.nnzb - inf["nnzb_dropped"],
            "max_levels": list(inf["max_levels"]), "partition_s": round(t_part, 3),
            "setup_s": round(t_setup, 3), "apply_us": round(us, 2), "apply_bytes": nbytes,
-           "apply_GB/s": round(nbytes / us / 1e3, 1),
-           "bicgstab": {"iters": info["iters"], "status": info["status"], "solve_s": round(t_solve, 4),
+           "apply_GB/s": round(nbytes / us / 1e3, 1), "spmv_us": round(spmv_us, 2),
+           "spmv_layout": inf["spmv_layout"], "max_row_blocks": inf["max_row_blocks"],
+           "bicgstab": {"iters": info["iters"], "status": info["status"],
+                        "solve_s": round(info["solve_seconds"], 4), "call_wall_s": round(t_solve, 4),
                         "rel_res_true": info["rel_res_true"]}}
     log(f"graph partition {t_part:.3f} s, setup {t_setup:.3f} s, apply {us:.1f} us "
-        f"({nbytes / us / 1e3:.1f} GB/s), BiCGSTAB {info['iters']} it {t_solve:.3f} s")
+        f"({nbytes / us / 1e3:.1f} GB/s), BiCGSTAB {info['iters']} it {info['solve_seconds']:.3f} s "
+        f"({t_solve:.3f} s for the first call, with its workspace allocation)")
     h.close()
     print(json.dumps(out), flush=True)
 
@@ -519,6 +554,8 @@ def main():
                          "graph: graph partition, apply and solve of a workload without geometry; "
                          "precision: error, nonlinearity and solves of the FP32-factor applies")
     ap.add_argument("--applies", type=int, default=10)
+    ap.add_argument("--part-rows", type=int, default=0,
+                    help="graph mode: rows per part (0: the library's automatic choice)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -727,7 +764,7 @@ def main():
         },
         "roofline": {"bound": "hbm", "achieved": round(gbs64, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs64 / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_dd_apply_slots<3, double, double, 1024, 3, 2, false>",
+                     "traffic": traffic, "kernel": "k_dd_apply_slots<3, double, double, 1024, 3, 2, false, false>",
                      "bytes_per_launch": bytes64, "copy_GBs": round(copy_gbs, 1),
                      "frac_of_copy": round(gbs64 / copy_gbs, 4), "read_GBs": round(read_gbs, 1),
                      "frac_of_read": round(gbs64 / read_gbs, 4)},

@@ -80,11 +80,12 @@ typedef struct {
     int64_t n;                 /* block rows (graph vertices)             */
     int32_t bs;                /* 1 or 3                                  */
     int32_t part_rows;         /* rows per subdomain S (n % S == 0), or 0:
-                                  the largest divisor of n whose vector
-                                  (S*bs*8 bytes) fits the LDS budget and
-                                  that leaves at least n_cu parts (else the
-                                  largest that fits), as dd_auto_subdims
-                                  does for boxes                          */
+                                  among the divisors of n whose vector
+                                  (S*bs*8 bytes) fits the LDS budget, the
+                                  one that leaves each compute unit the
+                                  fewest rows, ceil((n/S)/n_cu)*S (the
+                                  apply runs one part per CU at a time),
+                                  or the largest within 5% of that        */
     int64_t lds_budget_bytes;  /* LDS per workgroup, or 0 (device's)      */
     int32_t n_cu;              /* compute units, or 0 (device's)          */
     int32_t reserved;          /* 0                                       */
@@ -113,10 +114,12 @@ typedef struct {
     int32_t spmv_layout;       /* layout dd_spmv and bicgstab_solve read A
                                   in: 1 = a sliced ELL copy built by the
                                   partition step (the k-th blocks of each
-                                  wavefront's rows stored together; one
-                                  more copy of A's blocks), 0 = the CSR
-                                  arrays (rows of more than 7 blocks, or
-                                  no memory for the copy)                 */
+                                  wavefront's rows stored together, 7
+                                  positions per row; one more copy of A's
+                                  blocks), 2 = the same with one width
+                                  per wavefront's rows, longest row first
+                                  (rows of more than 7 blocks), 0 = the
+                                  CSR arrays (no memory for the copy)     */
     int32_t apply_layout;      /* streams the automatic apply reads: 1 =
                                   slot layout (rows of at most 3 blocks per
                                   triangle), 2 = segmented slot layout
@@ -171,9 +174,10 @@ int dd_device_caps(int32_t *n_cu, int64_t *lds_per_workgroup);
  * with its subdomain, renumber cells subdomain by subdomain (stable in the
  * old index, i.e. local lexicographic order inside each box), and build the
  * reordered matrix P A P^T with each row's blocks sorted by column.  The
- * full reordered matrix is kept for SpMV (Section 3.2); when no row holds
- * more than 7 blocks, a second, sliced ELL copy of it is built for the SpMV
- * (dd_info.spmv_layout), so a handle holds A's blocks twice.
+ * full reordered matrix is kept for SpMV (Section 3.2), and a second,
+ * sliced ELL copy of it is built for the SpMV (dd_info.spmv_layout), so a
+ * handle holds A's blocks twice (the copy pads each wavefront's rows to its
+ * longest one).
  * brow_ptr, bcol, val: device, the matrix in grid order, nnzb blocks,
  * at most 64 blocks per row.  The library copies what it needs; the caller
  * may free them after the call returns.

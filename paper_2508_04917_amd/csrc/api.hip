@@ -187,15 +187,23 @@ extern "C" int dd_partition_graph(const dd_graph_desc *d, const int32_t *brow_pt
         if (n_cu <= 0) n_cu = c;
     }
     int64_t S = d->part_rows;
-    if (S == 0) {  // largest divisor of n that fits the LDS, preferring at least n_cu parts
+    if (S == 0) {
+        // Divisors of n whose vector fits the LDS.  The apply runs one part
+        // per compute unit at a time, so a CU works through ceil(parts/n_cu)
+        // parts of S rows in turn: take the divisor with the fewest rows per
+        // CU by that count, and among those within 5% of the fewest the
+        // largest (fewer couplings dropped between parts).
         const int64_t cap = std::min<int64_t>(65535, lds / (8 * d->bs));
-        int64_t fit = 0, full = 0;
-        for (int64_t c = std::min(cap, n); c >= 1 && full == 0; --c) {
-            if (n % c) continue;
-            if (fit == 0) fit = c;
-            if (n / c >= n_cu) full = c;
-        }
-        S = full ? full : fit;
+        auto load = [&](int64_t c) { return (n / c + n_cu - 1) / n_cu * c; };
+        int64_t best = 0;
+        for (int64_t c = std::min(cap, n); c >= 1; --c)
+            if (n % c == 0 && (best == 0 || load(c) < load(best))) best = c;
+        S = best;
+        for (int64_t c = std::min(cap, n); c > best; --c)
+            if (n % c == 0 && load(c) * 100 <= load(best) * 105) {
+                S = c;
+                break;
+            }
     }
     if (S <= 0 || n % S)
         return set_global_error(DD_ENOTDIV, "dd_partition_graph: %lld block rows not divisible by part_rows %lld",
@@ -316,7 +324,7 @@ extern "C" int dd_get_info(dd_handle h, dd_info *info) {
                         2 * h->n * h->bs * 8;
     info->lds_bytes = apply_lds_bytes(h, h->precision);
     info->max_row_blocks = h->max_row_a;
-    info->spmv_layout = h->ell_state == 1 ? 1 : 0;
+    info->spmv_layout = h->ell_state == 1 ? (h->sell_row ? 2 : 1) : 0;
     info->apply_layout = h->slots ? 1 : (h->seg ? 2 : 0);
     return DD_OK;
 }

@@ -155,8 +155,12 @@ struct dd_ctx {
     int32_t spmv_part_stride = 0;
     int32_t max_row_a = 0;               // most blocks in a row of the full matrix
     int32_t ell_state = 0;               // sliced-ELL copy for the SpMV: 0 not built, 1 ready, -1 not used
-    int32_t *ell_col = nullptr;          // [groups][kUnroll][rows per wavefront]
+    int32_t *ell_col = nullptr;          // [slices][width][rows per wavefront]
     double *ell_val = nullptr;           // the same slots, bs*bs values each
+    // per-slice widths (rows of more than kUnroll blocks; null otherwise):
+    int32_t *sell_row = nullptr;         // [slices][rows per wavefront] block row, longest first (-1: none)
+    int32_t *sell_len = nullptr;         // its length
+    int64_t *sell_off = nullptr;         // [slices + 1] first slot run of each slice
     int32_t lic_fallback = 1;            // rerun a failed learned solve with plain DD-ILU0
     int32_t fuse = 0;                    // apply + SpMV as one launch inside bicgstab_solve (opt-in)
     int32_t *fdep = nullptr;             // [2 nsub] dependency ranges of the SpMV tiles

@@ -79,86 +79,243 @@ __global__ __launch_bounds__(256) void k_ell_fill(int64_t n, const int32_t *__re
     }
 }
 
-// Build the sliced ELL copy once per handle when the rows are short enough
-// and the memory is there; otherwise the SpMV stays on the CSR arrays.
+// Sliced ELL with per-slice widths (rows of more than kUnroll blocks): one
+// workgroup per window of kSellWin slices (the rows of one SpMV workgroup)
+// ranks the window's rows by length, longest first (ties by row number),
+// and writes the window's row order, the rows' lengths and each slice's
+// width (its first, longest row).  Positions past the matrix's last row get
+// row -1 and length 0.
+constexpr int kSellWin = kRedT / kWave;
+
+template <int BS>
+__global__ __launch_bounds__(256) void k_sell_rank(int64_t n, int64_t nslice, const int32_t *__restrict__ ptr,
+                                                  int32_t *__restrict__ srow, int32_t *__restrict__ slen,
+                                                  int64_t *__restrict__ soff) {
+    constexpr int RPW = kWave / BS, WIN = RPW * kSellWin;
+    __shared__ int len_s[WIN];
+    const int64_t w0 = (int64_t)blockIdx.x * WIN;
+    for (int i = threadIdx.x; i < WIN; i += blockDim.x) {
+        const int64_t row = w0 + i;
+        len_s[i] = row < n ? ptr[row + 1] - ptr[row] : -1;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < WIN; i += blockDim.x) {
+        const int li = len_s[i];
+        int rank = 0;
+        for (int p = 0; p < WIN; ++p) {
+            const int lp = len_s[p];
+            rank += (lp > li || (lp == li && p < i)) ? 1 : 0;
+        }
+        const int64_t pos = w0 + rank, g = pos / RPW;
+        if (g < nslice) {
+            srow[pos] = li >= 0 ? (int32_t)(w0 + i) : -1;
+            slen[pos] = max(li, 0);
+            if (rank % RPW == 0) soff[g] = max(li, 0);
+        }
+    }
+}
+
+// Exclusive prefix sum of the slice widths in place (soff[0..nslice)), and
+// soff[nslice] = the total: one workgroup, each thread a contiguous run.
+__global__ __launch_bounds__(1024) void k_sell_scan(int64_t nslice, int64_t *__restrict__ soff) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t run = (nslice + 1023) / 1024, lo = t * run, hi = min(nslice, lo + run);
+    int64_t sum = 0;
+    for (int64_t i = lo; i < hi; ++i) sum += soff[i];
+    part[t] = sum;
+    __syncthreads();
+    if (t == 0) {
+        int64_t acc = 0;
+        for (int i = 0; i < 1024; ++i) {
+            const int64_t v = part[i];
+            part[i] = acc;
+            acc += v;
+        }
+        soff[nslice] = acc;
+    }
+    __syncthreads();
+    int64_t acc = part[t];
+    for (int64_t i = lo; i < hi; ++i) {
+        const int64_t v = soff[i];
+        soff[i] = acc;
+        acc += v;
+    }
+}
+
+// Fill (or refill, for new values) the per-slice-width copy: one workgroup
+// per slice at a time, consecutive threads writing consecutive words.
+template <int BS>
+__global__ __launch_bounds__(256) void k_sell_fill(int64_t nslice, const int32_t *__restrict__ ptr,
+                                                  const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                  const int32_t *__restrict__ srow, const int32_t *__restrict__ slen,
+                                                  const int64_t *__restrict__ soff, int32_t *__restrict__ ecol,
+                                                  double *__restrict__ eval) {
+    constexpr int RPW = kWave / BS, BB = BS * BS;
+    for (int64_t g = blockIdx.x; g < nslice; g += gridDim.x) {
+        const int64_t base = soff[g] * RPW, cnt = (soff[g + 1] - soff[g]) * RPW * BB;
+        for (int64_t t = threadIdx.x; t < cnt; t += blockDim.x) {
+            const int64_t i = t / BB;
+            const int e = (int)(t % BB), k = (int)(i / RPW), q = (int)(i % RPW);
+            const int32_t row = srow[g * RPW + q];
+            const int64_t b = k < slen[g * RPW + q] ? (int64_t)ptr[row] + k : -1;
+            if (e == 0) ecol[base + i] = b >= 0 ? col[b] : -1;
+            eval[(base + i) * BB + e] = b >= 0 ? val[b * BB + e] : 0.0;
+        }
+    }
+}
+
+template <int BS>
+static void launch_ell_fill(dd_ctx *h, hipStream_t st) {
+    const int rpw = kWave / BS, bb = BS * BS;
+    const int64_t nslice = (h->n + rpw - 1) / rpw;
+    if (h->ell_state == 1 && h->sell_row) {
+        const unsigned g = (unsigned)std::min<int64_t>(nslice, 1 << 20);
+        k_sell_fill<BS><<<g, 256, 0, st>>>(nslice, h->aptr, h->acol, h->aval, h->sell_row, h->sell_len,
+                                           h->sell_off, h->ell_col, h->ell_val);
+        return;
+    }
+    const int64_t nslots = nslice * kUnroll * rpw;
+    const unsigned g = (unsigned)std::min<int64_t>((nslots * bb + 255) / 256, 1 << 20);  // grid-stride beyond
+    k_ell_fill<BS><<<g, 256, 0, st>>>(h->n, h->aptr, h->acol, h->aval, h->ell_col, h->ell_val, nslots);
+}
+
+// Build the sliced ELL copy once per handle when the memory is there
+// (otherwise the SpMV stays on the CSR arrays): fixed width kUnroll when no
+// row is longer, per-slice widths with the rows ranked by length otherwise.
 // Called at the end of the partition step (so its time counts as setup);
 // the SpMV entry points call it again, which does nothing once it has run.
 void build_spmv_layout(dd_ctx *h, hipStream_t st) {
     if (h->ell_state != 0) return;
     h->ell_state = -1;
-    if (h->max_row_a > kUnroll || h->max_row_a < 1) return;
+    if (h->max_row_a < 1) return;
     const int rpw = kWave / h->bs, bb = h->bs * h->bs;
-    const int64_t nslots = (h->n + rpw - 1) / rpw * kUnroll * rpw;
-    void *c = nullptr, *v = nullptr;
-    if (hipMalloc(&c, (size_t)nslots * sizeof(int32_t)) != hipSuccess) {
-        (void)hipGetLastError();
+    const int64_t nslice = (h->n + rpw - 1) / rpw;
+    auto grab = [&](size_t bytes) -> void * {
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        h->allocs.push_back(p);  // released with the handle, used or not
+        return p;
+    };
+    int64_t nslots = nslice * kUnroll * rpw;
+    if (h->max_row_a > kUnroll) {
+        h->sell_row = static_cast<int32_t *>(grab((size_t)nslice * rpw * sizeof(int32_t)));
+        h->sell_len = static_cast<int32_t *>(grab((size_t)nslice * rpw * sizeof(int32_t)));
+        h->sell_off = static_cast<int64_t *>(grab((size_t)(nslice + 1) * sizeof(int64_t)));
+        if (!h->sell_row || !h->sell_len || !h->sell_off) {
+            h->sell_row = nullptr;
+            return;
+        }
+        const unsigned g = (unsigned)((nslice + kSellWin - 1) / kSellWin);
+        if (h->bs == 3)
+            k_sell_rank<3><<<g, 256, 0, st>>>(h->n, nslice, h->aptr, h->sell_row, h->sell_len, h->sell_off);
+        else
+            k_sell_rank<1><<<g, 256, 0, st>>>(h->n, nslice, h->aptr, h->sell_row, h->sell_len, h->sell_off);
+        k_sell_scan<<<1, 1024, 0, st>>>(nslice, h->sell_off);
+        int64_t total = 0;
+        if (hipMemcpyAsync(&total, h->sell_off + nslice, sizeof(total), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            (void)hipGetLastError();
+            h->sell_row = nullptr;
+            return;
+        }
+        nslots = total * rpw;
+    }
+    h->ell_col = static_cast<int32_t *>(grab((size_t)std::max<int64_t>(nslots, 1) * sizeof(int32_t)));
+    h->ell_val = static_cast<double *>(grab((size_t)std::max<int64_t>(nslots, 1) * bb * sizeof(double)));
+    if (!h->ell_col || !h->ell_val) {
+        h->sell_row = nullptr;
         return;
     }
-    if (hipMalloc(&v, (size_t)nslots * bb * sizeof(double)) != hipSuccess) {
-        (void)hipGetLastError();
-        (void)hipFree(c);
-        return;
-    }
-    h->allocs.push_back(c);
-    h->allocs.push_back(v);
-    h->ell_col = static_cast<int32_t *>(c);
-    h->ell_val = static_cast<double *>(v);
-    const unsigned g = (unsigned)std::min<int64_t>((nslots * bb + 255) / 256, 1 << 20);  // grid-stride beyond
+    h->ell_state = 1;
     if (h->bs == 3)
-        k_ell_fill<3><<<g, 256, 0, st>>>(h->n, h->aptr, h->acol, h->aval, h->ell_col, h->ell_val, nslots);
+        launch_ell_fill<3>(h, st);
     else
-        k_ell_fill<1><<<g, 256, 0, st>>>(h->n, h->aptr, h->acol, h->aval, h->ell_col, h->ell_val, nslots);
+        launch_ell_fill<1>(h, st);
     // later SpMVs may run on other streams: the copy is complete before any
     // of them is enqueued
-    if (hipGetLastError() == hipSuccess && hipStreamSynchronize(st) == hipSuccess) h->ell_state = 1;
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+        h->ell_state = -1;
+        h->sell_row = nullptr;
+    }
 }
 
 // New values of A on the same pattern: rewrite the sliced ELL copy in place.
 hipError_t refresh_spmv_layout(dd_ctx *h, hipStream_t st) {
     if (h->ell_state != 1) return hipSuccess;
-    const int rpw = kWave / h->bs, bb = h->bs * h->bs;
-    const int64_t nslots = (h->n + rpw - 1) / rpw * kUnroll * rpw;
-    const unsigned g = (unsigned)std::min<int64_t>((nslots * bb + 255) / 256, 1 << 20);
     if (h->bs == 3)
-        k_ell_fill<3><<<g, 256, 0, st>>>(h->n, h->aptr, h->acol, h->aval, h->ell_col, h->ell_val, nslots);
+        launch_ell_fill<3>(h, st);
     else
-        k_ell_fill<1><<<g, 256, 0, st>>>(h->n, h->aptr, h->acol, h->aval, h->ell_col, h->ell_val, nslots);
+        launch_ell_fill<1>(h, st);
     return hipGetLastError();
 }
 
-// one row product, CSR or sliced ELL
-template <int BS, bool ELL>
-__device__ __forceinline__ double row_product(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
-                                              const double *__restrict__ val, const int32_t *__restrict__ ecol,
-                                              const double *__restrict__ eval, const double *__restrict__ x,
-                                              int64_t gw, int rl, int c) {
-    if constexpr (ELL)
-        return ell_row<BS>(ecol, eval, x, gw, rl, c);
-    else
-        return bsr_row<BS>(ptr, col, val, x, gw * (kWave / BS) + rl, c);
+// The matrix as the SpMV kernels read it: CSR arrays, and the sliced ELL
+// copy in one of its two forms (layout 1 fixed width, 2 per-slice widths).
+struct SpmvMat {
+    int64_t n;
+    const int32_t *ptr, *col;
+    const double *val;
+    const int32_t *ecol;
+    const double *eval;
+    const int32_t *srow, *slen;
+    const int64_t *soff;
+};
+
+static SpmvMat spmv_mat(const dd_ctx *h) {
+    return {h->n, h->aptr, h->acol, h->aval, h->ell_col, h->ell_val, h->sell_row, h->sell_len, h->sell_off};
 }
 
-template <int BS, bool ELL>
-__global__ __launch_bounds__(kRedT) void k_spmv(int64_t n, const int32_t *__restrict__ ptr,
-                                               const int32_t *__restrict__ col, const double *__restrict__ val,
-                                               const int32_t *__restrict__ ecol, const double *__restrict__ eval,
-                                               const double *__restrict__ x, double *__restrict__ y) {
+static int spmv_layout(const dd_ctx *h) { return h->ell_state == 1 ? (h->sell_row ? 2 : 1) : 0; }
+
+// The block row a lane's wavefront slot (gw, rl) computes (-1: none), and
+// its product with x in components c.
+template <int BS, int LAYOUT>
+__device__ __forceinline__ int64_t slot_row(const SpmvMat &m, int64_t gw, int rl) {
     constexpr int RPW = kWave / BS;
+    if (rl >= RPW || gw * RPW >= m.n) return -1;
+    if constexpr (LAYOUT == 2) return m.srow[gw * RPW + rl];
+    const int64_t row = gw * RPW + rl;
+    return row < m.n ? row : -1;
+}
+
+template <int BS, int LAYOUT>
+__device__ __forceinline__ double row_product(const SpmvMat &m, const double *__restrict__ x, int64_t gw, int rl,
+                                              int64_t row, int c) {
+    constexpr int RPW = kWave / BS;
+    if constexpr (LAYOUT == 2) {
+        const int len = m.slen[gw * RPW + rl];
+        if (len == 0) return 0.0;
+        return sell_row<BS>(m.ecol, m.eval, x, m.soff[gw] * RPW, (int)(m.soff[gw + 1] - m.soff[gw]), rl, len, c);
+    } else if constexpr (LAYOUT == 1) {
+        return ell_row<BS>(m.ecol, m.eval, x, gw, rl, c);
+    } else {
+        return bsr_row<BS>(m.ptr, m.col, m.val, x, row, c);
+    }
+}
+
+template <int BS, int LAYOUT>
+__global__ __launch_bounds__(kRedT) void k_spmv(SpmvMat m, const double *__restrict__ x, double *__restrict__ y) {
     const int lane = threadIdx.x & 63;
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int c = lane % BS, rl = lane / BS;
-    const int64_t row = gw * RPW + rl;
-    if (rl < RPW && row < n) y[row * BS + c] = row_product<BS, ELL>(ptr, col, val, ecol, eval, x, gw, rl, c);
+    const int64_t row = slot_row<BS, LAYOUT>(m, gw, rl);
+    if (row >= 0) y[row * BS + c] = row_product<BS, LAYOUT>(m, x, gw, rl, row, c);
 }
 
 template <int BS>
 static void launch_spmv_bs(dd_ctx *h, const double *x, double *y, hipStream_t st) {
     const int rpb = (kWave / BS) * (kRedT / kWave);
     const unsigned g = (unsigned)((h->n + rpb - 1) / rpb);
-    if (h->ell_state == 1)
-        k_spmv<BS, true><<<g, kRedT, 0, st>>>(h->n, h->aptr, h->acol, h->aval, h->ell_col, h->ell_val, x, y);
-    else
-        k_spmv<BS, false><<<g, kRedT, 0, st>>>(h->n, h->aptr, h->acol, h->aval, nullptr, nullptr, x, y);
+    const SpmvMat m = spmv_mat(h);
+    switch (spmv_layout(h)) {
+        case 2: k_spmv<BS, 2><<<g, kRedT, 0, st>>>(m, x, y); break;
+        case 1: k_spmv<BS, 1><<<g, kRedT, 0, st>>>(m, x, y); break;
+        default: k_spmv<BS, 0><<<g, kRedT, 0, st>>>(m, x, y);
+    }
 }
 
 hipError_t launch_spmv(dd_ctx *h, const double *x, double *y, hipStream_t st) {
@@ -175,17 +332,13 @@ hipError_t launch_spmv(dd_ctx *h, const double *x, double *y, hipStream_t st) {
 // dot r0.v.  mode 1: t = A s^, dots t.s and t.t.  mode 2: t = A x,
 // r = b - t (init), dots r.r and b.b.  mode 3: t = A x, dot (b-t).(b-t)
 // (true residual).
-template <int BS, int MODE, bool ELL>
-__global__ __launch_bounds__(kRedT) void k_spmv_dots(int64_t n, const int32_t *__restrict__ ptr,
-                                                    const int32_t *__restrict__ col,
-                                                    const double *__restrict__ val, const int32_t *__restrict__ ecol,
-                                                    const double *__restrict__ eval, const double *__restrict__ x,
+template <int BS, int MODE, int LAYOUT>
+__global__ __launch_bounds__(kRedT) void k_spmv_dots(SpmvMat m, const double *__restrict__ x,
                                                     double *__restrict__ y, const double *__restrict__ w,
                                                     double *__restrict__ r_out, double *__restrict__ r0_out,
                                                     double *__restrict__ p_out, double *__restrict__ part,
                                                     int part_stride, const int32_t *__restrict__ state) {
     if (state != nullptr && *state != ST_RUN) return;
-    constexpr int RPW = kWave / BS;
     constexpr int NV = MODE == 0 ? 1 : (MODE == 3 ? 1 : 2);
     const int lane = threadIdx.x & 63;
     const int c = lane % BS, rl = lane / BS;
@@ -193,10 +346,10 @@ __global__ __launch_bounds__(kRedT) void k_spmv_dots(int64_t n, const int32_t *_
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t row = gw * RPW + rl;
-    if (rl < RPW && row < n) {
+    const int64_t row = slot_row<BS, LAYOUT>(m, gw, rl);
+    if (row >= 0) {
         const int64_t e = row * BS + c;
-        const double t = row_product<BS, ELL>(ptr, col, val, ecol, eval, x, gw, rl, c);
+        const double t = row_product<BS, LAYOUT>(m, x, gw, rl, row, c);
         if constexpr (MODE == 0) {
             y[e] = t;
             acc[0] += w[e] * t;
@@ -219,17 +372,22 @@ __global__ __launch_bounds__(kRedT) void k_spmv_dots(int64_t n, const int32_t *_
     block_partials<NV>(acc, part, part_stride);
 }
 
-// Launch k_spmv_dots on the handle's layout (sliced ELL when built).
+// Launch k_spmv_dots on the handle's layout.
 template <int BS, int MODE>
 static void spmv_dots(const dd_ctx *h, int grid, const double *x, double *y, const double *w, double *r_out,
                       double *r0_out, double *p_out, double *part, int stride, const int32_t *state,
                       hipStream_t st) {
-    if (h->ell_state == 1)
-        k_spmv_dots<BS, MODE, true><<<grid, kRedT, 0, st>>>(h->n, h->aptr, h->acol, h->aval, h->ell_col, h->ell_val,
-                                                            x, y, w, r_out, r0_out, p_out, part, stride, state);
-    else
-        k_spmv_dots<BS, MODE, false><<<grid, kRedT, 0, st>>>(h->n, h->aptr, h->acol, h->aval, nullptr, nullptr, x,
-                                                             y, w, r_out, r0_out, p_out, part, stride, state);
+    const SpmvMat m = spmv_mat(h);
+    switch (spmv_layout(h)) {
+        case 2:
+            k_spmv_dots<BS, MODE, 2><<<grid, kRedT, 0, st>>>(m, x, y, w, r_out, r0_out, p_out, part, stride, state);
+            break;
+        case 1:
+            k_spmv_dots<BS, MODE, 1><<<grid, kRedT, 0, st>>>(m, x, y, w, r_out, r0_out, p_out, part, stride, state);
+            break;
+        default:
+            k_spmv_dots<BS, MODE, 0><<<grid, kRedT, 0, st>>>(m, x, y, w, r_out, r0_out, p_out, part, stride, state);
+    }
 }
 
 // s = r - alpha v; partial s.s
@@ -529,7 +687,10 @@ static int run_typed(dd_ctx *h, const KrylovWork &W, const double *b, double *x,
     if (profile && (int)h->events.size() < 4 * chunk) {
         while ((int)h->events.size() < 4 * chunk) {
             hipEvent_t ev;
-            KCHK(hipEventCreate(&ev));
+            // timing only (read after the stream synchronises): no system-scope
+            // fence, whose cache writeback and invalidation would slow the
+            // kernel after each event and inflate the time it measures
+            KCHK(hipEventCreateWithFlags(&ev, hipEventDisableSystemFence));
             h->events.push_back(ev);
         }
     }

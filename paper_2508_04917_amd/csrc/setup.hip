@@ -695,7 +695,7 @@ hipError_t launch_pack_slots(dd_ctx *h, int which, hipStream_t st) {
 // Only the last chunk of a level is followed by a barrier in the apply.  One
 // thread per subdomain walks its levels (count pass, then fill pass).
 template <bool FILL>
-__global__ void k_seg_walk(int nsub, int S, int cw, int rpw, const int32_t *__restrict__ off,
+__global__ void k_seg_walk(int nsub, int S, int which, int cw, int rpw, const int32_t *__restrict__ off,
                            const int32_t *__restrict__ lp, const int32_t *__restrict__ bptr, int32_t *npos,
                            int32_t *nchk, const int32_t *__restrict__ gpos, const int32_t *__restrict__ gchk,
                            int2 *pmap, int32_t *chk) {
@@ -707,19 +707,22 @@ __global__ void k_seg_walk(int nsub, int S, int cw, int rpw, const int32_t *__re
     const int32_t pb = FILL ? gpos[s] : 0, cb = FILL ? gchk[s] : 0;
     int32_t pos = 0, nc = 0;
     for (int l = 0; l < nl; ++l) {
-        if (FILL) chk[cb + nc] = pos;  // a level starts a chunk
-        ++nc;
         int inchunk = 0;
+        bool open = false;  // a level's first position opens its first chunk
         for (int32_t k = lp[o + l]; k < lp[o + l + 1]; ++k) {
             const int64_t p = base + k;
             const int32_t nb = bptr[p + 1] - bptr[p];
-            const int m = nb > 0 ? (nb + 2) / 3 : 1;
+            // a lower-sweep row without blocks keeps y_I = r_I: no position
+            // (a level of such rows, the lower sweep's first, has no chunk)
+            const int m = nb > 0 ? (nb + 2) / 3 : (which == 0 ? 0 : 1);
+            if (m == 0) continue;
             int pad = (inchunk % rpw) + m > rpw ? rpw - inchunk % rpw : 0;
-            if (inchunk + pad + m > cw) {  // the next chunk of this level
+            if (!open || inchunk + pad + m > cw) {  // the level's first or next chunk
                 if (FILL) chk[cb + nc] = pos;
                 ++nc;
                 inchunk = 0;
                 pad = 0;
+                open = true;
             }
             for (int q = 0; q < pad; ++q)
                 if (FILL) pmap[pb + pos + q] = make_int2(-1, 0);
@@ -730,7 +733,11 @@ __global__ void k_seg_walk(int nsub, int S, int cw, int rpw, const int32_t *__re
             pos += m;
             inchunk += m;
         }
-        if (FILL) chk[cb + nc - 1] |= 1 << 30;  // barrier after the level's last chunk
+        if (FILL && open) chk[cb + nc - 1] |= 1 << 30;  // barrier after the level's last chunk
+    }
+    if (nc == 0) {  // no positions: one empty chunk, so the apply's table reads stay inside it
+        if (FILL) chk[cb] = 1 << 30;
+        ++nc;
     }
     if (FILL) {
         chk[cb + nc] = pos;
@@ -819,8 +826,8 @@ int build_seg_layout(dd_ctx *h, int which, int cw, int rpw, hipStream_t st) {
             h->allocs.erase(it);
         }
     };
-    k_seg_walk<false><<<gs, T, 0, st>>>(nsub, h->S, cw, rpw, L.off, L.ptr, w.bptr, npos, nchk, nullptr, nullptr,
-                                        nullptr, nullptr);
+    k_seg_walk<false><<<gs, T, 0, st>>>(nsub, h->S, which, cw, rpw, L.off, L.ptr, w.bptr, npos, nchk, nullptr,
+                                        nullptr, nullptr, nullptr);
     hipError_t e = exclusive_scan(npos, w.gpos, nsub, h->scan_tmp, st);
     if (e == hipSuccess) e = exclusive_scan(nchk, w.gchk, nsub, h->scan_tmp, st);
     int32_t tot[2] = {0, 0};
@@ -837,8 +844,8 @@ int build_seg_layout(dd_ctx *h, int which, int cw, int rpw, hipStream_t st) {
     if (!rc) rc = h->alloc(&w.desc, tot[0]);
     if (!rc) rc = h->alloc(&w.sval64, (int64_t)tot[0] * (3 + which) * bb);
     if (rc) return rc;
-    k_seg_walk<true><<<gs, T, 0, st>>>(nsub, h->S, cw, rpw, L.off, L.ptr, w.bptr, nullptr, nullptr, w.gpos, w.gchk,
-                                       w.pmap, w.chk);
+    k_seg_walk<true><<<gs, T, 0, st>>>(nsub, h->S, which, cw, rpw, L.off, L.ptr, w.bptr, nullptr, nullptr, w.gpos,
+                                       w.gchk, w.pmap, w.chk);
     e = hipGetLastError();
     if (e == hipSuccess) e = launch_seg_pack(h, which, st);
     drop(npos);

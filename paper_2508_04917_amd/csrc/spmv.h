@@ -108,4 +108,70 @@ __device__ __forceinline__ double ell_row(const int32_t *__restrict__ ecol, cons
     return acc;
 }
 
+// Sliced ELL with one width per slice, for rows of more than kUnroll blocks.
+// A slice is one wavefront's RPW rows; the rows of each SpMV workgroup (four
+// slices) are stored longest first, so a slice's rows have similar lengths,
+// and its width w (wavefront-uniform) is its longest row's length.  Slot
+// (k, q) of the slice (at base + k*RPW + q) holds the k-th block of its q-th
+// row.  Blocks are fetched in chunks of kSellChunk positions and one last
+// chunk of w mod kSellChunk, each chunk straight-line code (column indices
+// and blocks issued together, then x), so a slice issues loads for exactly w
+// positions and waits twice per chunk.  A position past the row's own
+// length re-reads the row's last block (a line the lane has just fetched)
+// and adds 0.  Blocks are summed in the row's CSR order.  len >= 1.
+constexpr int kSellChunk = 8;
+
+template <int BS, int CH>
+__device__ __forceinline__ void sell_chunk(const int32_t *__restrict__ ecol, const double *__restrict__ eval,
+                                           const double *__restrict__ x, int64_t base, int k0, int q, int len,
+                                           int c, double &acc) {
+    constexpr int RPW = 64 / BS, BB = BS * BS;
+    int32_t J[CH];
+    double v[CH][BS];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+        const int64_t s = base + (int64_t)min(k0 + j, len - 1) * RPW + q;
+        J[j] = ecol[s];
+        const double *blk = eval + s * BB + c * BS;
+#pragma unroll
+        for (int d = 0; d < BS; ++d) v[j][d] = blk[d];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    double xv[CH][BS];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+        const double *xb = x + (int64_t)J[j] * BS;
+#pragma unroll
+        for (int d = 0; d < BS; ++d) xv[j][d] = xb[d];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+        double t = 0.0;
+#pragma unroll
+        for (int d = 0; d < BS; ++d) t += v[j][d] * xv[j][d];
+        acc += k0 + j < len ? t : 0.0;
+    }
+}
+
+template <int BS>
+__device__ __forceinline__ double sell_row(const int32_t *__restrict__ ecol, const double *__restrict__ eval,
+                                           const double *__restrict__ x, int64_t base, int w, int q, int len,
+                                           int c) {
+    double acc = 0.0;
+    int k0 = 0;
+    for (; k0 + kSellChunk <= w; k0 += kSellChunk) sell_chunk<BS, kSellChunk>(ecol, eval, x, base, k0, q, len, c, acc);
+    switch (w - k0) {
+        case 1: sell_chunk<BS, 1>(ecol, eval, x, base, k0, q, len, c, acc); break;
+        case 2: sell_chunk<BS, 2>(ecol, eval, x, base, k0, q, len, c, acc); break;
+        case 3: sell_chunk<BS, 3>(ecol, eval, x, base, k0, q, len, c, acc); break;
+        case 4: sell_chunk<BS, 4>(ecol, eval, x, base, k0, q, len, c, acc); break;
+        case 5: sell_chunk<BS, 5>(ecol, eval, x, base, k0, q, len, c, acc); break;
+        case 6: sell_chunk<BS, 6>(ecol, eval, x, base, k0, q, len, c, acc); break;
+        case 7: sell_chunk<BS, 7>(ecol, eval, x, base, k0, q, len, c, acc); break;
+        default: break;
+    }
+    return acc;
+}
+
 }  // namespace ddilu

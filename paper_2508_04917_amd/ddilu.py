@@ -221,8 +221,9 @@ def dd_partition(nx, ny, nz, bs, brow_ptr, bcol, val, sub=(0, 0, 0), n_cu=0, lds
 def dd_partition_graph(n, bs, brow_ptr, bcol, val, part_rows=0, lds_budget_bytes=0, n_cu=0,
                        stream=None) -> Handle:
     """Partition a matrix graph without geometry (recursive BFS bisection
-    into parts of part_rows vertices; 0 = largest divisor of n that fits the
-    LDS), then reorder as dd_partition does."""
+    into parts of part_rows vertices; 0 = the divisor of n that fits the LDS
+    and leaves each compute unit the fewest rows to apply), then reorder as
+    dd_partition does."""
     nnzb = bcol.numel()
     _dev_check(brow_ptr, torch.int32, n + 1, "brow_ptr")
     _dev_check(bcol, torch.int32, nnzb, "bcol")

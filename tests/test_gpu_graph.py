@@ -58,9 +58,10 @@ def np_(t):
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_spmv_layouts(name):
-    """SpMV against the oracle on graph-partitioned matrices: the sliced ELL
-    copy where rows hold at most 7 blocks, the CSR arrays where the k-nearest
-    neighbour pattern gives longer rows."""
+    """SpMV against the oracle on graph-partitioned matrices: the fixed-width
+    sliced ELL copy where rows hold at most 7 blocks, the copy with one width
+    per wavefront's rows where the k-nearest neighbour pattern gives longer
+    rows."""
     p, s, st = case(name)
     x = np.random.default_rng(6).standard_normal(st.n * st.bs)
     y_o = st.spmv(x)
@@ -70,7 +71,7 @@ def test_spmv_layouts(name):
     longest = int(np.diff(st.aptr).max())
     print(f"[graph {name}] longest row {longest} blocks, layout {inf['spmv_layout']}", flush=True)
     assert inf["max_row_blocks"] == longest
-    assert inf["spmv_layout"] == (1 if longest <= 7 else 0)
+    assert inf["spmv_layout"] == (1 if longest <= 7 else 2)
 
 
 def test_worked_example_matches_oracle():
@@ -194,6 +195,7 @@ def chain_with_hub(n, extra, bs=3, seed=21):
     blocks, the largest in the matrix."""
     rng = np.random.default_rng(seed)
     far = [20, 30, 40, 50, 60][:extra]
+    far += [j for j in range(n) if abs(j - 10) > 1 and j not in far][:extra - len(far)]
     nb = [{i} | {j for j in (i - 1, i + 1) if 0 <= j < n} for i in range(n)]
     for j in far:
         nb[10].add(j)
@@ -214,10 +216,12 @@ def chain_with_hub(n, extra, bs=3, seed=21):
                    b=rng.standard_normal(n * bs), seed=seed)
 
 
-@pytest.mark.parametrize("extra,layout", [(4, 1), (5, 0)])
+@pytest.mark.parametrize("extra,layout", [(4, 1), (5, 2), (40, 2)])
 def test_spmv_layout_threshold(extra, layout):
-    """A longest row of 7 blocks takes the sliced ELL copy, 8 blocks the CSR
-    arrays; both agree with the oracle's product on the reordered matrix."""
+    """A longest row of 7 blocks takes the fixed-width sliced ELL copy, 8
+    blocks (and a hub of 43, several chunks of 8) the copy with one width
+    per wavefront's rows; both agree with the oracle's product on the
+    reordered matrix."""
     p = chain_with_hub(64, extra)
     S = 16
     s = DDSolver(p.n, 1, 1, p.bs, p.brow_ptr, p.bcol, p.val, graph_part_rows=S)
@@ -300,13 +304,20 @@ def test_learned_correction_on_graph_partition():
 
 
 def test_automatic_part_size():
-    """part_rows = 0: the largest divisor of n whose vector fits the LDS and
-    that leaves at least n_cu parts, else the largest that fits."""
+    """part_rows = 0: among the divisors of n whose vector fits the LDS, the
+    one that leaves each compute unit the fewest rows, ceil(parts/n_cu)*S,
+    or the largest within 5% of that.  64,000 rows: with 8 CUs, 8,000 (one
+    part each; 16,000 would leave 16,000 rows on four CUs); with 2 CUs and
+    room for 20,480 rows, 16,000 (two parts each, 32,000 rows: the fewest
+    possible); with 3 CUs, 3,200 (20 parts, 7 per CU, 22,400 rows: parts of
+    1 or 2 rows would leave 21,334, and 3,200 is the largest divisor within
+    5% of that); with 1,000 CUs, 64 (one part each)."""
     p = unstructured_problem(64000, seed=16, bs=1)
     ptr = torch.as_tensor(p.brow_ptr, device="cuda")
     col = torch.as_tensor(p.bcol, device="cuda")
     val = torch.as_tensor(p.val.reshape(-1), device="cuda")
-    for n_cu, lds, S in ((8, 163840, 8000), (2, 163840, 16000), (4, 80000, 8000), (1000, 163840, 64)):
+    for n_cu, lds, S in ((8, 163840, 8000), (2, 163840, 16000), (4, 80000, 8000), (1000, 163840, 64),
+                         (3, 163840, 3200)):
         h = dd.dd_partition_graph(p.n, 1, ptr, col, val, part_rows=0, lds_budget_bytes=lds, n_cu=n_cu)
         try:
             assert dd.dd_get_info(h)["S"] == S, (n_cu, lds)
