@@ -240,6 +240,47 @@ def test_spmv_layout_threshold(extra, layout):
         s.close()
 
 
+def test_spmv_long_rows_and_empty_rows():
+    """Per-slice-width layout with rows of 0 to 18 blocks: a hub chain with
+    four rows emptied (no blocks, no references), ragged final slice
+    (n = 70 is not a multiple of one wavefront's 21 rows).  Only the
+    partition and the SpMV run (empty rows have no pivot); the oracle's
+    partition, renumbering and product give the reference."""
+    from types import SimpleNamespace
+    p = chain_with_hub(70, 16)
+    empty = {30, 31, 32, 33}
+    ptr, cols, vals = [0], [], []
+    blocks = p.val.reshape(-1, p.bs, p.bs)
+    for i in range(p.n):
+        for q in range(p.brow_ptr[i], p.brow_ptr[i + 1]):
+            j = int(p.bcol[q])
+            if i not in empty and j not in empty:
+                cols.append(j)
+                vals.append(blocks[q])
+        ptr.append(len(cols))
+    ptr = np.array(ptr, dtype=np.int32)
+    col = np.array(cols, dtype=np.int32)
+    val = np.array(vals).reshape(-1)
+    S = 14
+    h = dd.dd_partition_graph(p.n, p.bs, torch.as_tensor(ptr, device="cuda"), torch.as_tensor(col, device="cuda"),
+                              torch.as_tensor(val, device="cuda"), part_rows=S)
+    try:
+        pid = O.graph_partition(p.n, ptr, col, S)
+        assert np.array_equal(np_(dd.dd_get_partition(h)[0]), pid)
+        n2o, o2n = O.permutation(pid, p.n // S)
+        aptr, acol, aval = O.reorder(p.n, p.bs, ptr, col, val, n2o, o2n)
+        st = SimpleNamespace(n=p.n, bs=p.bs, aptr=aptr, acol=acol, aval=aval)
+        x = np.random.default_rng(8).standard_normal(p.n * p.bs)
+        y_o = O.spmv(p.n, p.bs, aptr, acol, aval, x)
+        y_g = np_(dd.dd_spmv(h, torch.as_tensor(x, device="cuda")))
+        check_spmv(st, x, y_g, y_o, "hub chain with empty rows")
+        inf = dd.dd_get_info(h)
+        assert inf["spmv_layout"] == 2 and inf["max_row_blocks"] == int(np.diff(ptr).max()) > 8
+        assert np.all(y_g.reshape(-1, p.bs)[o2n[sorted(empty)]] == 0.0)
+    finally:
+        h.close()
+
+
 def test_isolated_vertices_match_oracle():
     n, S = 48, 4
     ptr = np.arange(n + 1, dtype=np.int32)

@@ -11,7 +11,7 @@ import pytest
 
 import oracle as O
 from parity import check_close, dd_scale
-from problems import lognormal_problem, random_blocks
+from problems import lognormal_problem, random_blocks, unstructured_problem
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -117,3 +117,44 @@ def test_refactor_state_and_errors():
         dd.ilu0_refactor(h, cu(q.val))
     assert e.value.code == dd.DD_ESTATE
     h.close()
+
+
+def test_refactor_graph_partition():
+    """The same on a matrix without geometry (rows of up to 15 blocks): the
+    apply's segmented slot layout and the SpMV's per-slice-width copy are
+    rewritten in place, and everything again equals a fresh setup."""
+    import dataclasses
+    p1 = unstructured_problem(6000, seed=31, bs=3)
+    blocks = p1.val.reshape(-1, 3, 3)
+    off = (p1.bcol != np.repeat(np.arange(p1.n), np.diff(p1.brow_ptr)))[:, None, None]
+    scale = 1.0 - 0.2 * np.random.default_rng(32).random((blocks.shape[0], 1, 1))
+    p2 = dataclasses.replace(p1, val=np.where(off, blocks * scale, blocks))
+    S = 600
+    s = DDSolver.from_problem(p1, graph_part_rows=S)
+    inf = dd.dd_get_info(s.h)
+    print(f"[refactor] graph: n {p1.n}, longest row {inf['max_row_blocks']} blocks, "
+          f"apply layout {inf['apply_layout']}, SpMV layout {inf['spmv_layout']}", flush=True)
+    assert inf["apply_layout"] == 2 and inf["spmv_layout"] == 2
+    b2 = cu(p2.b)
+    s.solve(b2, rtol=1e-8)
+    s.set_precision(dd.DD_MIXED)
+    dd.ilu0_refactor(s.h, cu(p2.val))
+    fresh = DDSolver.from_problem(p2, graph_part_rows=S)
+    fresh.set_precision(dd.DD_MIXED)
+    for a, b_, what in zip(factors(s.h), factors(fresh.h), ("ptr", "col", "factors", "reordered values")):
+        assert torch.equal(a, b_), f"graph: {what} differ after ilu0_refactor"
+    r = cu(np.random.default_rng(3).standard_normal(p2.n * p2.bs))
+    for prec in (dd.DD_MIXED, dd.DD_FP32, dd.DD_FP64):
+        s.set_precision(prec)
+        fresh.set_precision(prec)
+        assert torch.equal(s.apply(r), fresh.apply(r)), f"graph: apply differs (precision {prec})"
+        assert torch.equal(s.spmv(r), fresh.spmv(r)), "graph: SpMV differs"
+    x, info = s.solve(b2, rtol=1e-8)
+    xf, inff = fresh.solve(b2, rtol=1e-8)
+    assert info["status"] == dd.DD_OK and info["iters"] == inff["iters"] and torch.equal(x, xf)
+    st = O.setup_graph(p2, S)
+    rn = r.cpu().numpy()
+    check_close(s.apply(r).cpu().numpy(), st.apply(rn), p2.bs, 1e-12, what="graph apply after refactor",
+                scale=dd_scale(st, rn))
+    s.close()
+    fresh.close()
