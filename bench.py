@@ -385,6 +385,66 @@ def precision_mode(args, p, sub, ptr_d, col_d, val_d, lic_params, dd, torch):
     print(json.dumps(out), flush=True)
 
 
+def dd_vs_global(args, p, subs, ptr_d, col_d, val_d, dd, torch):
+    """What the decomposition costs and buys on one matrix (the comparison of
+    Section 5.3, Tables 6 and 7, there against a rocSPARSE-based solver):
+    BiCGSTAB to rtol with the DD-ILU0 preconditioner and with the global
+    (undecomposed) ILU0 of the same reordered matrix, this library's
+    level-scheduled kernels (one launch per level, vector in global memory),
+    for each subdomain shape in subs: setup, apply and solve times and
+    iteration counts."""
+    b = torch.as_tensor(p.b, device="cuda:0")
+    r = torch.randn(p.n * p.bs, dtype=torch.float64, device="cuda:0")
+    z = torch.empty_like(r)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def burst(fn, k):
+        fn()
+        ev[0].record()
+        for _ in range(k):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return 1e3 * ev[0].elapsed_time(ev[1]) / k
+
+    rows = []
+    for sub in subs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = dd.dd_partition(p.nx, p.ny, p.nz, p.bs, ptr_d, col_d, val_d, sub=sub)
+        dd.ilu0_factor(h, dd.DD_FP64)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        inf = dd.dd_get_info(h)
+        us = burst(lambda: dd.dd_trsv_apply(h, r, z), args.applies)
+        x, i_dd = dd.bicgstab_solve(h, b, rtol=args.rtol, maxit=args.maxit)
+        log(f"{p.name} {inf['sx']}x{inf['sy']}x{inf['sz']}: DD-ILU0 setup {setup:.3f} s, apply {us:.1f} us, "
+            f"BiCGSTAB {i_dd['iters']} it {i_dd['solve_seconds']:.3f} s")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dd.dd_global_factor(h)
+        torch.cuda.synchronize()
+        gsetup = time.perf_counter() - t0
+        gus = burst(lambda: dd.dd_global_apply(h, r, z), max(2, args.applies // 5))
+        dd.dd_set_preconditioner(h, 1)
+        x, i_g = dd.bicgstab_solve(h, b, rtol=args.rtol, maxit=args.maxit)
+        dd.dd_set_preconditioner(h, 0)
+        log(f"{p.name}: global ILU0 setup {gsetup:.3f} s, apply {gus:.1f} us, "
+            f"BiCGSTAB {i_g['iters']} it {i_g['solve_seconds']:.3f} s")
+        rows.append({"subdomain": [inf["sx"], inf["sy"], inf["sz"]], "n_subdomains": inf["nsub"],
+                     "blocks": inf["nnzb"], "blocks_after_drop": inf["nnzb_dropped"],
+                     "dd_ilu0": {"setup_s": round(setup, 3), "apply_us": round(us, 2), "iters": i_dd["iters"],
+                                 "status": i_dd["status"], "solve_s": round(i_dd["solve_seconds"], 4),
+                                 "rel_res_true": i_dd["rel_res_true"]},
+                     "global_ilu0": {"setup_s": round(gsetup, 3), "apply_us": round(gus, 2), "iters": i_g["iters"],
+                                     "status": i_g["status"], "solve_s": round(i_g["solve_seconds"], 4),
+                                     "rel_res_true": i_g["rel_res_true"]},
+                     "iteration_ratio": round(i_dd["iters"] / max(1, i_g["iters"]), 3),
+                     "solve_speedup": round(i_g["solve_seconds"] / max(1e-9, i_dd["solve_seconds"]), 2)})
+        h.close()
+    print(json.dumps({"workload": args.workload, "block_rows": p.n, "rtol": args.rtol, "rows": rows}), flush=True)
+
+
 def host_cpu():
     """(model name, threads available to this process)."""
     model = "unknown"
@@ -546,13 +606,15 @@ def main():
                     help="1: after the timed steps, compare plain FP64, FP32-factor and learned solves on "
                          "the anisotropic 160^3 and the 128^3 evaluation workloads")
     ap.add_argument("--mode", default="full",
-                    choices=["full", "kernels", "ablation", "rocsparse", "graph", "precision"],
+                    choices=["full", "kernels", "ablation", "rocsparse", "graph", "precision", "global"],
                     help="kernels: only a copy kernel of known size and bursts of applies and SpMVs "
                          "(the short program the rocprofv3 counter runs profile); "
                          "ablation: the FP64 apply kernel variants, timed on the same factors; "
                          "rocsparse: rocSPARSE's block ILU0 apply on the decomposed and the full matrix; "
                          "graph: graph partition, apply and solve of a workload without geometry; "
-                         "precision: error, nonlinearity and solves of the FP32-factor applies")
+                         "precision: error, nonlinearity and solves of the FP32-factor applies; "
+                         "global: BiCGSTAB with DD-ILU0 against the global ILU0 of the same matrix "
+                         "(the workload's subdomains, then the automatic ones)")
     ap.add_argument("--applies", type=int, default=10)
     ap.add_argument("--part-rows", type=int, default=0,
                     help="graph mode: rows per part (0: the library's automatic choice)")
@@ -589,6 +651,11 @@ def main():
 
     if args.mode == "graph":
         graph_mode(args, p, ptr_d, col_d, val_d, dd, torch)
+        return
+    if args.mode == "global":
+        wsub = tuple(WORKLOADS[args.workload][2] or (0, 0, 0)) if args.sub == "auto" else sub
+        subs = [wsub] + ([(0, 0, 0)] if args.sub == "auto" and wsub != (0, 0, 0) else [])
+        dd_vs_global(args, p, subs, ptr_d, col_d, val_d, dd, torch)
         return
     if args.mode == "kernels":
         kernels_only(args, p, sub, ptr_d, col_d, val_d, dd, torch)
