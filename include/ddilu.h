@@ -123,10 +123,14 @@ typedef struct {
     int32_t apply_layout;      /* streams the automatic apply reads: 1 =
                                   slot layout (rows of at most 3 blocks per
                                   triangle), 2 = segmented slot layout
-                                  (longer rows split into segments of 3
-                                  blocks within one wavefront), 0 = CSR
-                                  streams only (rows of more than 24
-                                  blocks per triangle)                    */
+                                  (longer rows split into segments within
+                                  one wavefront), 0 = CSR streams only
+                                  (rows too long for 8 segments)          */
+    int32_t seg_blocks;        /* segmented layout: blocks per segment (2,
+                                  or 3 when a lower-sweep row holds more
+                                  than 16 blocks or an upper-sweep row more
+                                  than 23; then up to 24 and 31); 0 for the
+                                  other layouts                           */
 } dd_info;
 
 /* Result of bicgstab_solve. */

@@ -326,6 +326,7 @@ extern "C" int dd_get_info(dd_handle h, dd_info *info) {
     info->max_row_blocks = h->max_row_a;
     info->spmv_layout = h->ell_state == 1 ? (h->sell_row ? 2 : 1) : 0;
     info->apply_layout = h->slots ? 1 : (h->seg ? 2 : 0);
+    info->seg_blocks = h->seg;
     return DD_OK;
 }
 
@@ -427,11 +428,23 @@ static int build_slots(dd_ctx *h, hipStream_t st) {
     h->seg = 0;
     if (!h->slots) {
         // rows of more than three blocks: the segmented layout, for the apply's
-        // workgroups of 1,024 lanes, when no row needs more than kSegMax segments
-        if (mr > 3 * kSegMax) return DD_OK;
+        // workgroups of 1,024 lanes, with segments of two blocks (the least
+        // zero padding on the row lengths of k-nearest-neighbour graphs:
+        // 1.18x the algorithmic bytes against 1.29x with three), or of three
+        // when a row would need more than kSegMax segments of two
+        const int lo = h->sw[0].max_row, up = h->sw[1].max_row;
+        auto fits = [&](int mb) { return lo <= mb * kSegMax && up <= mb + (kSegMax - 1) * (mb + 1); };
+        const int mb = fits(2) ? 2 : (fits(3) ? 3 : 0);
+        if (!mb) return DD_OK;
         const int rpw = kWave / h->bs, cw = rpw * (1024 / kWave);
-        for (int w = 0; w < 2; ++w) RCHK(build_seg_layout(h, w, cw, rpw, st));
-        h->seg = 1;
+        h->seg = mb;  // the packing reads it
+        for (int w = 0; w < 2; ++w) {
+            const int rc = build_seg_layout(h, w, mb, cw, rpw, st);
+            if (rc) {
+                h->seg = 0;
+                return rc;
+            }
+        }
         return DD_OK;
     }
     for (int w = 0; w < 2; ++w) {
@@ -447,7 +460,7 @@ static int build_slots(dd_ctx *h, hipStream_t st) {
 static int ensure_fp32(dd_ctx *h, hipStream_t st) {
     const int bb = h->bs * h->bs;
     const bool sl = h->slots || h->seg;
-    const int mb = h->seg ? 3 : h->slots;
+    const int mb = h->seg ? h->seg : h->slots;
     if (h->sw[0].val32 && h->sw[1].val32 && h->sw[1].d32 && (!sl || h->sw[0].sval32)) return DD_OK;
     for (int w = 0; w < 2; ++w) {
         if (!h->sw[w].val32) RCHK(h->alloc(&h->sw[w].val32, h->sw[w].nblk * bb));

@@ -681,12 +681,13 @@ __device__ __forceinline__ void slot_claim(SlotRegs<BS, TS, MB, UPPER> &R) {
 
 // SEG: the segmented layout (15-bit descriptor fields, see Sweep).  A
 // position computes the partial result of its segment: the owner (a row's
-// first segment) starts from y_I (lower) or inv_D y_I (upper), a
-// continuation from zero (its inv_D run is zero); the owner then adds its
-// continuations' partials, held by the next m - 1 positions of the same
-// wavefront, in segment order through cross-lane reads, and alone writes the
-// row.  All lanes take part in the reads (those without a position hold
-// zero), so every value read is defined.
+// first segment) starts from y_I (lower) or inv_D y_I (upper), a lower
+// continuation from zero, an upper continuation from minus its extra block
+// (in the inv_D slot) times z at the column its row field names; the owner
+// then adds its continuations' partials, held by the next m - 1 positions
+// of the same wavefront, in segment order through cross-lane reads, and
+// alone writes the row.  All lanes take part in the reads (those without a
+// position hold zero), so every value read is defined.
 template <int BS, typename TS, typename TC, int MB, bool UPPER, bool SEG = false>
 __device__ __forceinline__ void slot_compute(TC *__restrict__ y, const SlotRegs<BS, TS, MB, UPPER> &R, int c) {
     using SR = SlotRegs<BS, TS, MB, UPPER>;
@@ -736,6 +737,8 @@ __device__ __forceinline__ void slot_compute(TC *__restrict__ y, const SlotRegs<
         acc = 0;
 #pragma unroll
         for (int d = 0; d < BS; ++d) acc += static_cast<TC>(vals[MB * BS + d]) * yi[d];
+        if constexpr (SEG)
+            if (cont) acc = -acc;
     } else {
         acc = cont ? TC(0) : yi[0];
     }
@@ -1354,20 +1357,23 @@ static hipError_t launch_slots(dd_ctx *h, const double *r, double *z, const int3
 
 // The segmented slot layout (rows of more than three blocks): workgroups of
 // 1,024 lanes (the layout's chunks are cut for that width), chunk tables as
-// level tables.
+// level tables, MB = the layout's blocks per segment (2 or 3).
 template <int BS, typename TS, typename TC>
 static hipError_t launch_seg(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st,
                              const TS *lv, const TS *uv, int nrhs) {
     constexpr int PD = sizeof(TS) == 8 ? DDILU_PD64 : DDILU_PD32;
-    auto kern = k_dd_apply_slots<BS, TS, TC, 1024, 3, PD, false, true>;
-    static bool done = false;
-    hipError_t e = allow_full_lds(kern, done);
-    if (e != hipSuccess) return e;
-    const int lds = h->S * BS * (int)sizeof(TC);
-    const Sweep &L = h->sw[0], &U = h->sw[1];
-    kern<<<dim3(h->nsub, nrhs), 1024, lds, st>>>(r, z, h->S, L.gchk, L.chk, L.desc, lv, U.gchk, U.chk, U.desc, uv,
-                                                 state, lic_args(h), h->n * BS, L.gpos, U.gpos);
-    return hipGetLastError();
+    auto go = [&](auto kern, bool &done) -> hipError_t {
+        hipError_t e = allow_full_lds(kern, done);
+        if (e != hipSuccess) return e;
+        const int lds = h->S * BS * (int)sizeof(TC);
+        const Sweep &L = h->sw[0], &U = h->sw[1];
+        kern<<<dim3(h->nsub, nrhs), 1024, lds, st>>>(r, z, h->S, L.gchk, L.chk, L.desc, lv, U.gchk, U.chk, U.desc,
+                                                     uv, state, lic_args(h), h->n * BS, L.gpos, U.gpos);
+        return hipGetLastError();
+    };
+    static bool done2 = false, done3 = false;
+    if (h->seg == 2) return go(k_dd_apply_slots<BS, TS, TC, 1024, 2, PD, false, true>, done2);
+    return go(k_dd_apply_slots<BS, TS, TC, 1024, 3, PD, false, true>, done3);
 }
 
 template <int BS, typename TS, typename TC, int NT, bool LIC>

@@ -44,18 +44,22 @@ struct Sweep {
     float *sval32 = nullptr;
     int64_t snpos = 0;          // positions of the slot layout (n, or the segmented layout's count)
     // Segmented slot layout (rows of more than kMaxSlots blocks): a row is
-    // split into segments of up to 3 blocks at consecutive positions of one
-    // wavefront; levels wider than a workgroup pass are cut into chunks.
-    // desc then holds 15-bit fields: local row | continuation flag << 15,
-    // columns at 16(k+1) (0x7FFF empty), and, for a row's first segment, its
-    // segment count minus one in bits 31, 47 and 63.
+    // split into segments at consecutive positions of one wavefront; levels
+    // wider than a workgroup pass are cut into chunks.  With MB blocks per
+    // segment (dd_ctx::seg): a lower-sweep segment holds MB blocks; in the
+    // upper sweep the row's first segment holds MB blocks and inv_D, each
+    // continuation MB + 1 blocks, the last one in the inv_D slot.  desc then
+    // holds 15-bit fields: local row (a continuation of the upper sweep: the
+    // column of its extra block) | continuation flag << 15, columns at
+    // 16(k+1) (0x7FFF empty), and, for a row's first segment, its segment
+    // count minus one in bits 31, 47 and 63.
     int32_t *gpos = nullptr;    // [nsub+1] first position of each subdomain
     int32_t *gchk = nullptr;    // [nsub+1] first entry of each subdomain's chunk table
     int32_t *chk = nullptr;     // per subdomain: chunk starts (relative; bit 30 = barrier after), end
     int2 *pmap = nullptr;       // [snpos] CSR sweep position (-1 = padding), segment | count << 8
 };
 
-constexpr int kSegMax = 8;      // segments of a row in the segmented layout (24 blocks)
+constexpr int kSegMax = 8;  // segments of a row in the segmented layout
 
 // Level sets of one factor, per subdomain.
 struct Levels {
@@ -132,7 +136,7 @@ struct dd_ctx {
     int32_t max_level_width = 0;  // widest level of any subdomain, L or U
     int32_t profile = 0;          // time every apply inside bicgstab_solve
     int32_t slots = 0;            // MB of the slot layout (0: CSR layout only)
-    int32_t seg = 0;              // 1: the segmented slot layout (MB = 3) serves rows of any length
+    int32_t seg = 0;              // MB of the segmented slot layout (2 or 3; 0: not built)
     int32_t variant = 0;          // apply kernel: 0 auto, 1 simple, 2 pipelined CSR, 3 slots, 4-8 ablations
     double *hist = nullptr;       // optional residual history (device, caller-owned)
     ddilu::Lic lic;
@@ -224,7 +228,7 @@ hipError_t launch_cast32(dd_ctx *h, hipStream_t st);
 hipError_t launch_pack_slots(dd_ctx *h, int which, hipStream_t st);
 // segmented slot layout: positions and chunk tables (which: 0 lower, 1
 // upper; chunk width cw positions, rpw per wavefront), then the values
-int build_seg_layout(dd_ctx *h, int which, int cw, int rpw, hipStream_t st);
+int build_seg_layout(dd_ctx *h, int which, int mb, int cw, int rpw, hipStream_t st);
 hipError_t launch_seg_pack(dd_ctx *h, int which, hipStream_t st);
 hipError_t launch_max_count(int64_t n, const int32_t *cnt, int32_t *out, hipStream_t st);
 hipError_t launch_export_factors(dd_ctx *h, double *f, hipStream_t st);

@@ -684,10 +684,13 @@ hipError_t launch_pack_slots(dd_ctx *h, int which, hipStream_t st) {
 }
 
 // ------------------------------------------------- segmented slot layout
-// For sweeps with rows of more than three blocks.  A row with nb blocks
-// becomes m = max(1, ceil(nb/3)) segments of up to three blocks (in column
-// order) at consecutive positions of one wavefront; the first segment (the
-// row's owner) adds the others' partial sums in the apply.  Each level is
+// For sweeps with rows of more than three blocks.  With MB blocks per
+// segment, a lower-sweep row with nb blocks becomes ceil(nb/MB) segments (none
+// when nb = 0), an upper-sweep row one segment of MB blocks and inv_D plus
+// ceil((nb - MB)/(MB + 1)) continuations of MB + 1 blocks (the extra block
+// in the inv_D slot, which a continuation does not need); blocks in column
+// order, segments at consecutive positions of one wavefront; the first
+// segment (the row's owner) adds the others' partial sums in the apply.  Each level is
 // laid out in chunks of at most cw positions (one workgroup pass of the
 // apply, rpw positions per wavefront); a group that would straddle a
 // wavefront is moved to the next one (the positions skipped are padding), a
@@ -695,7 +698,7 @@ hipError_t launch_pack_slots(dd_ctx *h, int which, hipStream_t st) {
 // Only the last chunk of a level is followed by a barrier in the apply.  One
 // thread per subdomain walks its levels (count pass, then fill pass).
 template <bool FILL>
-__global__ void k_seg_walk(int nsub, int S, int which, int cw, int rpw, const int32_t *__restrict__ off,
+__global__ void k_seg_walk(int nsub, int S, int which, int mb, int cw, int rpw, const int32_t *__restrict__ off,
                            const int32_t *__restrict__ lp, const int32_t *__restrict__ bptr, int32_t *npos,
                            int32_t *nchk, const int32_t *__restrict__ gpos, const int32_t *__restrict__ gchk,
                            int2 *pmap, int32_t *chk) {
@@ -714,7 +717,7 @@ __global__ void k_seg_walk(int nsub, int S, int which, int cw, int rpw, const in
             const int32_t nb = bptr[p + 1] - bptr[p];
             // a lower-sweep row without blocks keeps y_I = r_I: no position
             // (a level of such rows, the lower sweep's first, has no chunk)
-            const int m = nb > 0 ? (nb + 2) / 3 : (which == 0 ? 0 : 1);
+            const int m = which == 0 ? (nb + mb - 1) / mb : 1 + (max(nb - mb, 0) + mb) / (mb + 1);
             if (m == 0) continue;
             int pad = (inchunk % rpw) + m > rpw ? rpw - inchunk % rpw : 0;
             if (!open || inchunk + pad + m > cw) {  // the level's first or next chunk
@@ -748,10 +751,15 @@ __global__ void k_seg_walk(int nsub, int S, int which, int cw, int rpw, const in
 }
 
 // Position q: its segment's descriptor and values in the lane-run layout of
-// k_pack_slots (MB = 3).  Padding positions are continuations of local row 0
-// with no blocks (they read y_0 and write nothing); a continuation's inv_D
-// run (upper sweep) is zero.
-template <int BS>
+// k_pack_slots (MB blocks, then inv_D in the upper sweep).  Padding
+// positions are continuations of local row 0 with no blocks (they read y_0
+// and write nothing).  An upper-sweep continuation holds its (MB+1)-th block
+// in the inv_D slot and that block's column in the row field (its own row
+// when the slot is empty: a valid LDS entry, times a zero block).  The
+// descriptor keeps three 16-bit column fields whatever MB (fields past MB
+// empty), so that the bits 15 of fields 1 to 3 hold m - 1 on a row's first
+// segment.
+template <int BS, int MB>
 __global__ void k_seg_pack(int64_t npos, int which, const int2 *__restrict__ pmap, const uint16_t *__restrict__ prow,
                            const int32_t *__restrict__ bptr, const uint16_t *__restrict__ bcol,
                            const double *__restrict__ val, const double *__restrict__ dval, uint64_t *desc,
@@ -759,10 +767,10 @@ __global__ void k_seg_pack(int64_t npos, int which, const int2 *__restrict__ pma
     constexpr int BB = BS * BS;
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= npos) return;
-    const int NV = (3 + which) * BS;
+    const int NV = (MB + which) * BS;
     double *o = sval + q * BS * NV;
     const int2 e = pmap[q];
-    int32_t b0 = 0, b1 = 0;
+    int32_t b0 = 0, b1 = 0, bx = -1;  // segment blocks [b0, b1); bx: a continuation's extra block (upper)
     int k = 0;
     uint64_t d;
     if (e.x < 0) {
@@ -771,15 +779,17 @@ __global__ void k_seg_pack(int64_t npos, int which, const int2 *__restrict__ pma
     } else {
         k = e.y & 0xff;
         const int m = e.y >> 8;
-        d = (uint64_t)prow[e.x] | (k > 0 ? 0x8000ull : 0ull);
-        b0 = bptr[e.x] + 3 * k;
-        b1 = min(b0 + 3, bptr[e.x + 1]);
-        for (int j = 0; j < 3; ++j) d |= (uint64_t)(b0 + j < b1 ? bcol[b0 + j] : 0x7fff) << (16 * (j + 1));
+        const int32_t rb = bptr[e.x], re = bptr[e.x + 1];
+        b0 = rb + (which == 0 || k == 0 ? MB * k : MB + (k - 1) * (MB + 1));
+        b1 = min(b0 + MB, re);
+        if (which == 1 && k > 0 && b0 + MB < re) bx = b0 + MB;
+        d = (uint64_t)(bx >= 0 ? bcol[bx] : prow[e.x]) | (k > 0 ? 0x8000ull : 0ull);
+        for (int j = 0; j < 3; ++j) d |= (uint64_t)(j < MB && b0 + j < b1 ? bcol[b0 + j] : 0x7fff) << (16 * (j + 1));
         if (k == 0)
             for (int j = 0; j < 3; ++j)
                 if (((m - 1) >> j) & 1) d |= 1ull << (16 * (j + 1) + 15);
     }
-    for (int j = 0; j < 3; ++j)
+    for (int j = 0; j < MB; ++j)
 #pragma unroll
         for (int i = 0; i < BS; ++i)
 #pragma unroll
@@ -790,7 +800,9 @@ __global__ void k_seg_pack(int64_t npos, int which, const int2 *__restrict__ pma
         for (int i = 0; i < BS; ++i)
 #pragma unroll
             for (int jj = 0; jj < BS; ++jj)
-                o[i * NV + 3 * BS + jj] = (e.x >= 0 && k == 0) ? dval[(int64_t)e.x * BB + i * BS + jj] : 0.0;
+                o[i * NV + MB * BS + jj] = e.x < 0 ? 0.0
+                                           : k == 0 ? dval[(int64_t)e.x * BB + i * BS + jj]
+                                           : bx >= 0 ? val[(int64_t)bx * BB + i * BS + jj] : 0.0;
     desc[q] = d;
 }
 
@@ -799,16 +811,18 @@ hipError_t launch_seg_pack(dd_ctx *h, int which, hipStream_t st) {
     Sweep &w = h->sw[which];
     const unsigned g = (unsigned)((w.snpos + T - 1) / T);
     if (w.snpos == 0) return hipSuccess;
-    if (h->bs == 3)
-        k_seg_pack<3><<<g, T, 0, st>>>(w.snpos, which, w.pmap, w.prow, w.bptr, w.bcol, w.val64, w.d64, w.desc,
-                                       w.sval64);
-    else
-        k_seg_pack<1><<<g, T, 0, st>>>(w.snpos, which, w.pmap, w.prow, w.bptr, w.bcol, w.val64, w.d64, w.desc,
-                                       w.sval64);
+    auto go = [&](auto kern) {
+        kern<<<g, T, 0, st>>>(w.snpos, which, w.pmap, w.prow, w.bptr, w.bcol, w.val64, w.d64, w.desc, w.sval64);
+    };
+    if (h->bs == 3) {
+        if (h->seg == 2) go(k_seg_pack<3, 2>); else go(k_seg_pack<3, 3>);
+    } else {
+        if (h->seg == 2) go(k_seg_pack<1, 2>); else go(k_seg_pack<1, 3>);
+    }
     return hipGetLastError();
 }
 
-int build_seg_layout(dd_ctx *h, int which, int cw, int rpw, hipStream_t st) {
+int build_seg_layout(dd_ctx *h, int which, int mb, int cw, int rpw, hipStream_t st) {
     Sweep &w = h->sw[which];
     const Levels &L = h->lev[which];
     const int nsub = h->nsub, T = 256;
@@ -826,7 +840,7 @@ int build_seg_layout(dd_ctx *h, int which, int cw, int rpw, hipStream_t st) {
             h->allocs.erase(it);
         }
     };
-    k_seg_walk<false><<<gs, T, 0, st>>>(nsub, h->S, which, cw, rpw, L.off, L.ptr, w.bptr, npos, nchk, nullptr,
+    k_seg_walk<false><<<gs, T, 0, st>>>(nsub, h->S, which, mb, cw, rpw, L.off, L.ptr, w.bptr, npos, nchk, nullptr,
                                         nullptr, nullptr, nullptr);
     hipError_t e = exclusive_scan(npos, w.gpos, nsub, h->scan_tmp, st);
     if (e == hipSuccess) e = exclusive_scan(nchk, w.gchk, nsub, h->scan_tmp, st);
@@ -842,9 +856,9 @@ int build_seg_layout(dd_ctx *h, int which, int cw, int rpw, hipStream_t st) {
     rc = h->alloc(&w.pmap, tot[0]);
     if (!rc) rc = h->alloc(&w.chk, tot[1]);
     if (!rc) rc = h->alloc(&w.desc, tot[0]);
-    if (!rc) rc = h->alloc(&w.sval64, (int64_t)tot[0] * (3 + which) * bb);
+    if (!rc) rc = h->alloc(&w.sval64, (int64_t)tot[0] * (mb + which) * bb);
     if (rc) return rc;
-    k_seg_walk<true><<<gs, T, 0, st>>>(nsub, h->S, which, cw, rpw, L.off, L.ptr, w.bptr, nullptr, nullptr, w.gpos,
+    k_seg_walk<true><<<gs, T, 0, st>>>(nsub, h->S, which, mb, cw, rpw, L.off, L.ptr, w.bptr, nullptr, nullptr, w.gpos,
                                        w.gchk, w.pmap, w.chk);
     e = hipGetLastError();
     if (e == hipSuccess) e = launch_seg_pack(h, which, st);
@@ -871,7 +885,7 @@ hipError_t launch_cast32(dd_ctx *h, hipStream_t st) {
     const int64_t m = h->n * bb;
     k_cast32<<<(unsigned)((m + T - 1) / T), T, 0, st>>>(m, h->sw[1].d64, h->sw[1].d32);
     if (h->slots || h->seg) {
-        const int mb = h->seg ? 3 : h->slots;
+        const int mb = h->seg ? h->seg : h->slots;
         for (int w = 0; w < 2; ++w) {
             const int64_t ms = h->sw[w].snpos * (mb + w) * bb;  // the upper stream carries inv_D
             if (ms) k_cast32<<<(unsigned)((ms + T - 1) / T), T, 0, st>>>(ms, h->sw[w].sval64, h->sw[w].sval32);

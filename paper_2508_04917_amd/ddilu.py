@@ -56,7 +56,8 @@ class Info(C.Structure):
                 ("level_ptr_len", C.c_int32 * 2), ("max_levels", C.c_int32 * 2),
                 ("factored", C.c_int32), ("precision", C.c_int32),
                 ("apply_bytes", C.c_int64), ("lds_bytes", C.c_int64),
-                ("max_row_blocks", C.c_int32), ("spmv_layout", C.c_int32), ("apply_layout", C.c_int32)]
+                ("max_row_blocks", C.c_int32), ("spmv_layout", C.c_int32), ("apply_layout", C.c_int32),
+                ("seg_blocks", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

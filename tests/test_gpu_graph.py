@@ -216,6 +216,55 @@ def chain_with_hub(n, extra, bs=3, seed=21):
                    b=rng.standard_normal(n * bs), seed=seed)
 
 
+def chain_with_links(n, links, bs=3, seed=23):
+    """A chain of n block rows plus the given couplings (i, j), both ways;
+    diagonal blocks N(0,1) + 8 I, the rest N(0,1)."""
+    rng = np.random.default_rng(seed)
+    nb = [{i} | {j for j in (i - 1, i + 1) if 0 <= j < n} for i in range(n)]
+    for i, j in links:
+        nb[i].add(j)
+        nb[j].add(i)
+    ptr = np.zeros(n + 1, dtype=np.int32)
+    cols = []
+    for i in range(n):
+        cols += sorted(nb[i])
+        ptr[i + 1] = len(cols)
+    col = np.array(cols, dtype=np.int32)
+    val = rng.standard_normal((col.size, bs, bs))
+    val[col == np.repeat(np.arange(n), np.diff(ptr))] += 8.0 * np.eye(bs)
+    from problems.generators import Problem
+    return Problem(name="chain_links", nx=n, ny=1, nz=1, bs=bs, brow_ptr=ptr, bcol=col, val=val.reshape(-1),
+                   b=rng.standard_normal(n * bs), seed=seed)
+
+
+@pytest.mark.parametrize("lower_far,width", [(12, 2), (20, 3)])
+def test_segment_width(lower_far, width):
+    """The segmented apply cuts rows into segments of two blocks, or of three
+    when a lower-sweep row holds more than 16 blocks.  Row 60 of a 64-row
+    chain couples to lower_far rows below it (lower sweep: lower_far + 1
+    blocks), row 3 to 21 rows above it (upper sweep: 22 blocks, several
+    continuations that carry an extra block each).  One part, so nothing is
+    dropped; the apply (every precision) against the oracle."""
+    links = [(60, 58 - 2 * k) for k in range(lower_far)] + [(3, 6 + 2 * k) for k in range(21)]
+    p = chain_with_links(64, links)
+    s = DDSolver(p.n, 1, 1, p.bs, p.brow_ptr, p.bcol, p.val, graph_part_rows=64)
+    try:
+        inf = dd.dd_get_info(s.h)
+        print(f"[segments] lower rows up to {lower_far + 1} blocks: apply layout {inf['apply_layout']}, "
+              f"segments of {inf['seg_blocks']}", flush=True)
+        assert inf["apply_layout"] == 2 and inf["seg_blocks"] == width
+        st = O.setup_graph(p, 64)
+        r = np.random.default_rng(4).standard_normal(p.n * p.bs)
+        rd = torch.as_tensor(r, device="cuda")
+        check_close(np_(s.apply(rd)), st.apply(r), 3, 1e-12, what=f"segments of {width}", scale=dd_scale(st, r))
+        s.set_precision(dd.DD_MIXED)
+        check_close(np_(s.apply(rd)), st.apply_fp32_factors(r, round_input=False), 3, 1e-10,
+                    what=f"segments of {width}, FP32 factors")
+        s.set_precision(dd.DD_FP64)
+    finally:
+        s.close()
+
+
 @pytest.mark.parametrize("extra,layout", [(4, 1), (5, 2), (40, 2)])
 def test_spmv_layout_threshold(extra, layout):
     """A longest row of 7 blocks takes the fixed-width sliced ELL copy, 8
