@@ -3,7 +3,7 @@
 One step = one pass of the whole path over the workload's matrix, already
 resident in HBM: partition + reorder, drop + level sets + block ILU0/ILDU0,
 BiCGSTAB to rel. residual 1e-8 with the FP64 preconditioner (once with every
-apply timed by HIP event pairs, once untimed), FP32 factor copies, BiCGSTAB
+apply timed by a HIP event pair, once untimed), FP32 factor copies, BiCGSTAB
 to 1e-8 with FP32-stored factors and FP64 trisolve arithmetic (DD_MIXED;
 timed and untimed), BiCGSTAB to 1e-8 with FP32 trisolves (DD_FP32, timed),
 and, when trained parameters are present
@@ -13,10 +13,12 @@ mixed-precision preconditioner.  Reported solve times are the untimed
 solves' (no event records between the kernels).
 
 Printed (one JSON line): the trisolve bandwidth of the FP64 apply -- its
-algorithmic bytes divided by its average duration, timed by HIP event pairs
-on the solve's stream around every apply inside the timed solves -- and its
-fraction of the 8 TB/s HBM peak, the BiCGSTAB times, and the oracle's
-single-thread apply bandwidth on the same matrix as a CPU baseline.
+algorithmic bytes divided by its average duration, timed by a HIP event
+pair that the apply kernel's launch records at its start and end
+(hipExtLaunchKernel, on the solve's stream) for every apply inside the
+timed solve -- and its fraction of the 8 TB/s HBM peak, the BiCGSTAB times,
+and the oracle's apply bandwidth on the same matrix (on the host's cores
+and on one) as a CPU baseline.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -678,7 +680,7 @@ def main():
         dd.ilu0_factor(h, dd.DD_FP64)
         torch.cuda.synchronize()
         rec["setup_s"] = time.perf_counter() - t0
-        # FP64 solve with every apply timed by event pairs (the trisolve
+        # FP64 solve with every apply timed by an event pair (the trisolve
         # GB/s), then the same solve untimed (its wall time is the plain FP64
         # solve time)
         dd.dd_set_profiling(h, True)

@@ -146,8 +146,10 @@ typedef struct {
                                   ||b - A x|| exceeds 2 rtol ||b||, the
                                   solve restarts (r = r^ = p = b - A x), at
                                   most 4 times within maxit iterations    */
-    double apply_seconds;      /* summed duration of those applies (event
-                                  pairs on the stream; 0 unless profiling
+    double apply_seconds;      /* summed duration of those applies (HIP
+                                  events recorded at the apply kernel's
+                                  start and end, or around the launches of
+                                  a multi-kernel apply; 0 unless profiling
                                   was switched on with dd_set_profiling)  */
     int32_t fused;             /* 1 when each apply ran in one launch with
                                   the SpMV after it (dd_set_fusion)       */
@@ -338,8 +340,10 @@ int bicgstab_solve_noalloc(dd_handle h, const double *b, double *x, double rtol,
 int dd_set_apply_variant(dd_handle h, int32_t variant);
 
 /* Switch per-apply timing inside bicgstab_solve on (1) or off (0): a HIP
- * event pair on the solve's stream brackets every preconditioner apply and
- * the summed durations are reported in dd_solve_info.apply_seconds. */
+ * event pair times every preconditioner apply (a slot-layout apply records
+ * it at its kernel's own start and end through hipExtLaunchKernel; other
+ * variants on the solve's stream around their launches) and the summed
+ * durations are reported in dd_solve_info.apply_seconds. */
 int dd_set_profiling(dd_handle h, int32_t on);
 
 /* Run each preconditioner apply of bicgstab_solve and the SpMV that

@@ -18,6 +18,8 @@
 // Types: TS is the storage type of the factor blocks (double or float), TC
 // the type of the LDS vector and of the arithmetic (double for DD_FP64 and
 // DD_MIXED, float for DD_FP32).  Input r and output z are always FP64.
+#include <hip/hip_ext.h>
+
 #include "internal.h"
 #include "spmv.h"
 
@@ -1337,6 +1339,18 @@ static LicArgs lic_args(const dd_ctx *h) {
     return LicArgs{h->lic.fptr, h->lic.rb, h->lic.lrec, h->lic.Cr};
 }
 
+// Launch a slot kernel; with timing events pending on the handle, through
+// hipExtLaunchKernel, which records them at the kernel's own start and end.
+template <typename K, typename... A>
+static void launch_timed(dd_ctx *h, K kern, dim3 grid, int nt, int lds, hipStream_t st, A... args) {
+    if (h->tev[0]) {
+        hipExtLaunchKernelGGL(kern, grid, dim3(nt), (uint32_t)lds, st, h->tev[0], h->tev[1], 0u, args...);
+        h->tev_used = 1;
+    } else {
+        kern<<<grid, nt, lds, st>>>(args...);
+    }
+}
+
 template <int BS, typename TS, typename TC, int NT, int MB, bool LIC>
 static hipError_t launch_slots(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st,
                                const TS *lv, const TS *uv, int nrhs) {
@@ -1349,9 +1363,9 @@ static hipError_t launch_slots(dd_ctx *h, const double *r, double *z, const int3
     // wavefronts for the widest level (at most NT / 64)
     constexpr int RPW = kWave / BS;
     const int nt = std::max(kWave, std::min(NT, (h->max_level_width + RPW - 1) / RPW * kWave));
-    kern<<<dim3(h->nsub, nrhs), nt, lds, st>>>(r, z, h->S, h->lev[0].off, h->lev[0].ptr, h->sw[0].desc, lv,
-                                               h->lev[1].off, h->lev[1].ptr, h->sw[1].desc, uv, state, lic_args(h),
-                                               h->n * BS, nullptr, nullptr);
+    launch_timed(h, kern, dim3(h->nsub, nrhs), nt, lds, st, r, z, h->S, h->lev[0].off, h->lev[0].ptr,
+                 h->sw[0].desc, lv, h->lev[1].off, h->lev[1].ptr, h->sw[1].desc, uv, state, lic_args(h),
+                 (int64_t)h->n * BS, (const int32_t *)nullptr, (const int32_t *)nullptr);
     return hipGetLastError();
 }
 
@@ -1367,8 +1381,10 @@ static hipError_t launch_seg(dd_ctx *h, const double *r, double *z, const int32_
         if (e != hipSuccess) return e;
         const int lds = h->S * BS * (int)sizeof(TC);
         const Sweep &L = h->sw[0], &U = h->sw[1];
-        kern<<<dim3(h->nsub, nrhs), 1024, lds, st>>>(r, z, h->S, L.gchk, L.chk, L.desc, lv, U.gchk, U.chk, U.desc,
-                                                     uv, state, lic_args(h), h->n * BS, L.gpos, U.gpos);
+        launch_timed(h, kern, dim3(h->nsub, nrhs), 1024, lds, st, r, z, h->S, (const int32_t *)L.gchk,
+                     (const int32_t *)L.chk, (const uint64_t *)L.desc, lv, (const int32_t *)U.gchk,
+                     (const int32_t *)U.chk, (const uint64_t *)U.desc, uv, state, lic_args(h), (int64_t)h->n * BS,
+                     (const int32_t *)L.gpos, (const int32_t *)U.gpos);
         return hipGetLastError();
     };
     static bool done2 = false, done3 = false;
@@ -1681,9 +1697,23 @@ hipError_t launch_apply_adjoint(dd_ctx *h, const double *g, double *a, int nrhs,
     }
 }
 
-hipError_t launch_precond(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st) {
-    if (h->pc_kind == 1) return launch_global_apply(h, r, z, 1, st);
-    return launch_apply(h, r, z, state, st);
+hipError_t launch_precond(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st,
+                          hipEvent_t ev0, hipEvent_t ev1) {
+    if (!ev0) {
+        if (h->pc_kind == 1) return launch_global_apply(h, r, z, 1, st);
+        return launch_apply(h, r, z, state, st);
+    }
+    // the stream-ordered record stands for paths of several launches; a slot
+    // kernel records both events again at its own start and end
+    hipError_t e = hipEventRecord(ev0, st);
+    if (e != hipSuccess) return e;
+    h->tev[0] = ev0;
+    h->tev[1] = ev1;
+    h->tev_used = 0;
+    e = h->pc_kind == 1 ? launch_global_apply(h, r, z, 1, st) : launch_apply(h, r, z, state, st);
+    h->tev[0] = h->tev[1] = nullptr;
+    if (e == hipSuccess && !h->tev_used) e = hipEventRecord(ev1, st);
+    return e;
 }
 
 }  // namespace ddilu

@@ -135,6 +135,11 @@ struct dd_ctx {
     int32_t precision = DD_FP64;
     int32_t max_level_width = 0;  // widest level of any subdomain, L or U
     int32_t profile = 0;          // time every apply inside bicgstab_solve
+    // events the next apply launch records at its kernel's start and end
+    // (set by launch_precond for per-apply timing; tev_used: a slot kernel
+    // took them)
+    hipEvent_t tev[2] = {nullptr, nullptr};
+    int32_t tev_used = 0;
     int32_t slots = 0;            // MB of the slot layout (0: CSR layout only)
     int32_t seg = 0;              // MB of the segmented slot layout (2 or 3; 0: not built)
     int32_t variant = 0;          // apply kernel: 0 auto, 1 simple, 2 pipelined CSR, 3 slots, 4-8 ablations
@@ -306,7 +311,11 @@ hipError_t launch_apply_adjoint(dd_ctx *h, const double *g, double *a, int nrhs,
 // pack the transposed factor streams of the adjoint apply (once per factorisation)
 int lic_adjoint_streams(dd_ctx *h, hipStream_t st);
 // the preconditioner bicgstab_solve uses (DD apply, or the global ILU0 apply)
-hipError_t launch_precond(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st);
+// ev0/ev1 (optional): timing events around the apply; a slot-layout apply
+// records them at its kernel's own start and end (hipExtLaunchKernel), any
+// other path on the stream around its launches.
+hipError_t launch_precond(dd_ctx *h, const double *r, double *z, const int32_t *state, hipStream_t st,
+                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 constexpr int32_t kWaitFailed = -64;  // solve state word after a dependency wait hit its bound
 // BiCGSTAB's apply and the SpMV behind it as one launch (mode 0: y = A z with
 // the dot w.y; mode 1: the dots y.w and y.y), partials one per subdomain.

@@ -727,9 +727,8 @@ static int run_typed(dd_ctx *h, const KrylovWork &W, const double *b, double *x,
                     KCHK(launch_apply_spmv(h, 0, p, ph, v, r0, part, sps, ++fepoch, ftick, &ks->state, st));
                     ftick += 2ull * h->nsub;
                 } else {
-                    if (profile) KCHK(hipEventRecord(h->events[4 * k], st));
-                    KCHK(launch_precond(h, p, ph, state, st));  // p^ = M^{-1} p
-                    if (profile) KCHK(hipEventRecord(h->events[4 * k + 1], st));
+                    KCHK(launch_precond(h, p, ph, state, st, profile ? h->events[4 * k] : nullptr,
+                                        profile ? h->events[4 * k + 1] : nullptr));  // p^ = M^{-1} p
                     spmv_dots<BS, 0>(h, gsp, ph, v, r0, nullptr, nullptr, nullptr, part, sps, state,
                                      st);  // v = A p^, r0.v
                 }
@@ -741,9 +740,8 @@ static int run_typed(dd_ctx *h, const KrylovWork &W, const double *b, double *x,
                     KCHK(launch_apply_spmv(h, 1, s, shat, t, s, part, sps, ++fepoch, ftick, &ks->state, st));
                     ftick += 2ull * h->nsub;
                 } else {
-                    if (profile) KCHK(hipEventRecord(h->events[4 * k + 2], st));
-                    KCHK(launch_precond(h, s, shat, state, st));  // s^ = M^{-1} s
-                    if (profile) KCHK(hipEventRecord(h->events[4 * k + 3], st));
+                    KCHK(launch_precond(h, s, shat, state, st, profile ? h->events[4 * k + 2] : nullptr,
+                                        profile ? h->events[4 * k + 3] : nullptr));  // s^ = M^{-1} s
                     spmv_dots<BS, 1>(h, gsp, shat, t, s, nullptr, nullptr, nullptr, part, sps, state,
                                      st);  // t = A s^, t.s, t.t
                 }

@@ -336,3 +336,27 @@ def test_errors():
     with pytest.raises(P.DDError) as e:
         DDSolver.from_problem(p, sub=(4, 4, 4))
     assert e.value.code == P.ddilu.DD_EZEROPIVOT
+
+
+@pytest.mark.parametrize("variant", [0, 1, 4])
+def test_profiling_times_every_apply(variant):
+    """Per-apply timing (the slot kernel records its events at its own start
+    and end; the plain loop and the split ablation, on the stream around
+    their launches) reports a positive duration for every apply and leaves
+    the solve unchanged bit for bit."""
+    p, s, st = case("logn_24_32_40")
+    b = torch.as_tensor(p.b, device="cuda")
+    P.ddilu.dd_set_apply_variant(s.h, variant)
+    try:
+        x0, i0 = s.solve(b, rtol=1e-8)
+        P.ddilu.dd_set_profiling(s.h, True)
+        try:
+            x1, i1 = s.solve(b, rtol=1e-8)
+        finally:
+            P.ddilu.dd_set_profiling(s.h, False)
+    finally:
+        P.ddilu.dd_set_apply_variant(s.h, 0)
+    per = i1["apply_seconds"] / max(1, i1["applies"])
+    print(f"[profiling v{variant}] {i1['applies']} applies, {1e6 * per:.1f} us each", flush=True)
+    assert i1["iters"] == i0["iters"] and torch.equal(x1, x0)
+    assert i1["applies"] >= 2 * i1["iters"] - 1 and per > 0
