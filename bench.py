@@ -135,7 +135,8 @@ def kernels_only(args, p, sub, ptr_d, col_d, val_d, dd, torch):
     us = 1e3 * ev[0].elapsed_time(ev[1]) / args.applies
     bb = info["bs"] * info["bs"]
     nbytes = info["nnzb"] * (bb * 8 + 4) + (info["n"] + 1) * 4 + 2 * info["n"] * info["bs"] * 8
-    layout = {0: "CSR", 1: "sliced ELL", 2: "sliced ELL, one width per slice"}[info["spmv_layout"]]
+    layout = {0: "CSR", 1: "sliced ELL", 2: "sliced ELL, one width per slice",
+              3: "sliced ELL per part, x in LDS"}[info["spmv_layout"]]
     out["spmv"] = {"us_per_call": round(us, 2), "layout": layout, "bytes_per_call": nbytes,
                    "GB/s": round(nbytes / us / 1e3, 1)}
     log(f"spmv: {us:.1f} us per call, {nbytes / us / 1e3:.1f} GB/s")

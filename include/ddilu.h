@@ -118,7 +118,11 @@ typedef struct {
                                   positions per row; one more copy of A's
                                   blocks), 2 = the same with one width
                                   per wavefront's rows, longest row first
-                                  (rows of more than 7 blocks), 0 = the
+                                  (rows of more than 7 blocks), 3 = as 2
+                                  with the slices aligned to the parts of
+                                  dd_partition_graph, the SpMV run part
+                                  by part with the part's x in LDS (scalar
+                                  rows, parts of at least 256 rows), 0 = the
                                   CSR arrays (no memory for the copy)     */
     int32_t apply_layout;      /* streams the automatic apply reads: 1 =
                                   slot layout (rows of at most 3 blocks per

@@ -324,7 +324,7 @@ extern "C" int dd_get_info(dd_handle h, dd_info *info) {
                         2 * h->n * h->bs * 8;
     info->lds_bytes = apply_lds_bytes(h, h->precision);
     info->max_row_blocks = h->max_row_a;
-    info->spmv_layout = h->ell_state == 1 ? (h->sell_row ? 2 : 1) : 0;
+    info->spmv_layout = h->ell_state == 1 ? (h->sell_row ? (h->sell_spp ? 3 : 2) : 1) : 0;
     info->apply_layout = h->slots ? 1 : (h->seg ? 2 : 0);
     info->seg_blocks = h->seg;
     return DD_OK;

@@ -170,6 +170,8 @@ struct dd_ctx {
     int32_t *sell_row = nullptr;         // [slices][rows per wavefront] block row, longest first (-1: none)
     int32_t *sell_len = nullptr;         // its length
     int64_t *sell_off = nullptr;         // [slices + 1] first slot run of each slice
+    int64_t sell_nslice = 0;             // slices of the copy
+    int32_t sell_spp = 0;                // slices per part (part-aligned slices, graphs), 0 otherwise
     int32_t lic_fallback = 1;            // rerun a failed learned solve with plain DD-ILU0
     int32_t fuse = 0;                    // apply + SpMV as one launch inside bicgstab_solve (opt-in)
     int32_t *fdep = nullptr;             // [2 nsub] dependency ranges of the SpMV tiles

@@ -115,6 +115,42 @@ __global__ __launch_bounds__(256) void k_sell_rank(int64_t n, int64_t nslice, co
     }
 }
 
+// The same ranking with the slices aligned to the parts of a graph
+// partition (parts of S rows): part k owns slices k*spp .. k*spp + spp - 1,
+// spp = ceil(S / RPW), and a window (kSellWin slices) never crosses a part;
+// positions past the part's last row get row -1 and length 0.
+template <int BS>
+__global__ __launch_bounds__(256) void k_sell_rank_part(int S, int spp, int nwin, const int32_t *__restrict__ ptr,
+                                                       int32_t *__restrict__ srow, int32_t *__restrict__ slen,
+                                                       int64_t *__restrict__ soff) {
+    constexpr int RPW = kWave / BS, WIN = RPW * kSellWin;
+    __shared__ int len_s[WIN];
+    const int64_t k = blockIdx.x / nwin;
+    const int wi = blockIdx.x % nwin;
+    const int64_t row0 = k * S;
+    const int l0 = wi * WIN;
+    for (int i = threadIdx.x; i < WIN; i += blockDim.x) {
+        const int lr = l0 + i;
+        len_s[i] = lr < S ? ptr[row0 + lr + 1] - ptr[row0 + lr] : -1;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < WIN; i += blockDim.x) {
+        const int li = len_s[i];
+        int rank = 0;
+        for (int p = 0; p < WIN; ++p) {
+            const int lp = len_s[p];
+            rank += (lp > li || (lp == li && p < i)) ? 1 : 0;
+        }
+        const int ls = wi * kSellWin + rank / RPW, q = rank % RPW;
+        if (ls < spp) {
+            const int64_t g = k * spp + ls;
+            srow[g * RPW + q] = li >= 0 ? (int32_t)(row0 + l0 + i) : -1;
+            slen[g * RPW + q] = max(li, 0);
+            if (q == 0) soff[g] = max(li, 0);
+        }
+    }
+}
+
 // Exclusive prefix sum of the slice widths in place (soff[0..nslice)), and
 // soff[nslice] = the total: one workgroup, each thread a contiguous run.
 __global__ __launch_bounds__(1024) void k_sell_scan(int64_t nslice, int64_t *__restrict__ soff) {
@@ -170,8 +206,8 @@ static void launch_ell_fill(dd_ctx *h, hipStream_t st) {
     const int rpw = kWave / BS, bb = BS * BS;
     const int64_t nslice = (h->n + rpw - 1) / rpw;
     if (h->ell_state == 1 && h->sell_row) {
-        const unsigned g = (unsigned)std::min<int64_t>(nslice, 1 << 20);
-        k_sell_fill<BS><<<g, 256, 0, st>>>(nslice, h->aptr, h->acol, h->aval, h->sell_row, h->sell_len,
+        const unsigned g = (unsigned)std::min<int64_t>(h->sell_nslice, 1 << 20);
+        k_sell_fill<BS><<<g, 256, 0, st>>>(h->sell_nslice, h->aptr, h->acol, h->aval, h->sell_row, h->sell_len,
                                            h->sell_off, h->ell_col, h->ell_val);
         return;
     }
@@ -180,9 +216,29 @@ static void launch_ell_fill(dd_ctx *h, hipStream_t st) {
     k_ell_fill<BS><<<g, 256, 0, st>>>(h->n, h->aptr, h->acol, h->aval, h->ell_col, h->ell_val, nslots);
 }
 
+// Whether the SpMV of a graph-partitioned matrix runs part by part with the
+// part's x in LDS (layout 3): scalar rows (each lane's x_J is an 8-byte
+// gather, a cache line of its own in the global-memory form; measured at
+// 4,096,000 rows: 233 -> 154 us.  With 3x3 blocks the 24-byte x_J fills
+// more of a line and the one-workgroup-per-CU occupancy of the part kernel
+// costs more than it saves: 322 against 334 us at 2,048,000 rows), parts of
+// at least one ranking window whose x fits the LDS next to the kernel's own
+// 1 KB, and one partial sum per part within the Krylov driver's partial-sum
+// stride.
+constexpr int kPartLds = 163840 - 1024;
+
+static bool part_local_spmv(const dd_ctx *h) {
+    const int rpw = kWave / h->bs, rpb = rpw * (kRedT / kWave);
+    const int64_t stride = std::max<int64_t>((h->n + rpb - 1) / rpb, kMaxGrid);
+    return h->graph && h->bs == 1 && h->S >= rpw * kSellWin && (int64_t)h->S * h->bs * 8 <= kPartLds &&
+           h->nsub <= stride;
+}
+
 // Build the sliced ELL copy once per handle when the memory is there
-// (otherwise the SpMV stays on the CSR arrays): fixed width kUnroll when no
-// row is longer, per-slice widths with the rows ranked by length otherwise.
+// (otherwise the SpMV stays on the CSR arrays): for graph partitions,
+// slices aligned to the parts with per-slice widths (the SpMV then runs part
+// by part, the part's x in LDS); otherwise fixed width kUnroll when no row
+// is longer, per-slice widths with the rows ranked by length when one is.
 // Called at the end of the partition step (so its time counts as setup);
 // the SpMV entry points call it again, which does nothing once it has run.
 void build_spmv_layout(dd_ctx *h, hipStream_t st) {
@@ -190,7 +246,11 @@ void build_spmv_layout(dd_ctx *h, hipStream_t st) {
     h->ell_state = -1;
     if (h->max_row_a < 1) return;
     const int rpw = kWave / h->bs, bb = h->bs * h->bs;
-    const int64_t nslice = (h->n + rpw - 1) / rpw;
+    const bool parts = part_local_spmv(h);
+    const int spp = parts ? (h->S + rpw - 1) / rpw : 0;
+    const int64_t nslice = parts ? (int64_t)h->nsub * spp : (h->n + rpw - 1) / rpw;
+    h->sell_nslice = nslice;
+    h->sell_spp = spp;
     auto grab = [&](size_t bytes) -> void * {
         void *p = nullptr;
         if (hipMalloc(&p, bytes) != hipSuccess) {
@@ -201,7 +261,7 @@ void build_spmv_layout(dd_ctx *h, hipStream_t st) {
         return p;
     };
     int64_t nslots = nslice * kUnroll * rpw;
-    if (h->max_row_a > kUnroll) {
+    if (parts || h->max_row_a > kUnroll) {
         h->sell_row = static_cast<int32_t *>(grab((size_t)nslice * rpw * sizeof(int32_t)));
         h->sell_len = static_cast<int32_t *>(grab((size_t)nslice * rpw * sizeof(int32_t)));
         h->sell_off = static_cast<int64_t *>(grab((size_t)(nslice + 1) * sizeof(int64_t)));
@@ -209,11 +269,22 @@ void build_spmv_layout(dd_ctx *h, hipStream_t st) {
             h->sell_row = nullptr;
             return;
         }
-        const unsigned g = (unsigned)((nslice + kSellWin - 1) / kSellWin);
-        if (h->bs == 3)
-            k_sell_rank<3><<<g, 256, 0, st>>>(h->n, nslice, h->aptr, h->sell_row, h->sell_len, h->sell_off);
-        else
-            k_sell_rank<1><<<g, 256, 0, st>>>(h->n, nslice, h->aptr, h->sell_row, h->sell_len, h->sell_off);
+        if (parts) {
+            const int nwin = (spp + kSellWin - 1) / kSellWin;
+            const unsigned g = (unsigned)((int64_t)h->nsub * nwin);
+            if (h->bs == 3)
+                k_sell_rank_part<3><<<g, 256, 0, st>>>(h->S, spp, nwin, h->aptr, h->sell_row, h->sell_len,
+                                                       h->sell_off);
+            else
+                k_sell_rank_part<1><<<g, 256, 0, st>>>(h->S, spp, nwin, h->aptr, h->sell_row, h->sell_len,
+                                                       h->sell_off);
+        } else {
+            const unsigned g = (unsigned)((nslice + kSellWin - 1) / kSellWin);
+            if (h->bs == 3)
+                k_sell_rank<3><<<g, 256, 0, st>>>(h->n, nslice, h->aptr, h->sell_row, h->sell_len, h->sell_off);
+            else
+                k_sell_rank<1><<<g, 256, 0, st>>>(h->n, nslice, h->aptr, h->sell_row, h->sell_len, h->sell_off);
+        }
         k_sell_scan<<<1, 1024, 0, st>>>(nslice, h->sell_off);
         int64_t total = 0;
         if (hipMemcpyAsync(&total, h->sell_off + nslice, sizeof(total), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -269,7 +340,9 @@ static SpmvMat spmv_mat(const dd_ctx *h) {
     return {h->n, h->aptr, h->acol, h->aval, h->ell_col, h->ell_val, h->sell_row, h->sell_len, h->sell_off};
 }
 
-static int spmv_layout(const dd_ctx *h) { return h->ell_state == 1 ? (h->sell_row ? 2 : 1) : 0; }
+static int spmv_layout(const dd_ctx *h) {
+    return h->ell_state == 1 ? (h->sell_row ? (h->sell_spp ? 3 : 2) : 1) : 0;
+}
 
 // The block row a lane's wavefront slot (gw, rl) computes (-1: none), and
 // its product with x in components c.
@@ -306,12 +379,107 @@ __global__ __launch_bounds__(kRedT) void k_spmv(SpmvMat m, const double *__restr
     if (row >= 0) y[row * BS + c] = row_product<BS, LAYOUT>(m, x, gw, rl, row, c);
 }
 
+// Layout 3 (graph partitions): one workgroup per part.  The part's x is
+// staged in LDS (S*BS values, read once), then the wavefronts take the
+// part's slices in turn; a column inside the part reads x from LDS.  The
+// rows of a part keep their original, unordered numbering inside it, so a
+// row's neighbours lie anywhere in the part: in the global-memory form every
+// x_J is a cache line of its own.  MODE as in k_spmv_dots, 4 = y = A x only;
+// one partial sum per part.
+template <int BS, int MODE>
+__global__ __launch_bounds__(1024) void k_spmv_part(SpmvMat m, int S, int spp, const double *__restrict__ x,
+                                                   double *__restrict__ y, const double *__restrict__ w,
+                                                   double *__restrict__ r_out, double *__restrict__ r0_out,
+                                                   double *__restrict__ p_out, double *__restrict__ part,
+                                                   int part_stride, const int32_t *__restrict__ state) {
+    if (state != nullptr && *state != ST_RUN) return;
+    constexpr int RPW = kWave / BS;
+    constexpr int NV = MODE == 0 ? 1 : (MODE == 3 || MODE == 4 ? 1 : 2);
+    extern __shared__ double xs[];
+    const int64_t k = blockIdx.x, row0 = k * S;
+    {  // eight loads in flight per thread, positions past the end clamped and not stored
+        const int m = S * BS, nt = blockDim.x;
+        const double *xp = x + row0 * BS;
+        for (int i0 = threadIdx.x; i0 < m; i0 += 8 * nt) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = xp[min(i0 + u * nt, m - 1)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (i0 + u * nt < m) xs[i0 + u * nt] = v[u];
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int c = lane % BS, rl = lane / BS;
+    double acc[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+    for (int ls = wave; ls < spp; ls += nw) {
+        const int64_t g = k * spp + ls;
+        if (rl >= RPW) continue;
+        const int32_t row = m.srow[g * RPW + rl];
+        if (row < 0) continue;
+        const int len = m.slen[g * RPW + rl];
+        const double t = len == 0 ? 0.0
+                                  : sell_row_lds<BS>(m.ecol, m.eval, x, xs, row0, S, m.soff[g] * RPW,
+                                                     (int)(m.soff[g + 1] - m.soff[g]), rl, len, c);
+        const int64_t e = (int64_t)row * BS + c;
+        if constexpr (MODE == 4) {
+            y[e] = t;
+        } else if constexpr (MODE == 0) {
+            y[e] = t;
+            acc[0] += w[e] * t;
+        } else if constexpr (MODE == 1) {
+            y[e] = t;
+            acc[0] += t * w[e];
+            acc[1] += t * t;
+        } else if constexpr (MODE == 2) {
+            const double rr = w[e] - t;
+            r_out[e] = rr;
+            r0_out[e] = rr;
+            p_out[e] = rr;
+            acc[0] += rr * rr;
+            acc[1] += w[e] * w[e];
+        } else {
+            const double rr = w[e] - t;
+            acc[0] += rr * rr;
+        }
+    }
+    if constexpr (MODE != 4) block_partials<NV>(acc, part, part_stride);
+}
+
+template <int BS, int MODE>
+static void launch_spmv_part(const dd_ctx *h, const double *x, double *y, const double *w, double *r_out,
+                             double *r0_out, double *p_out, double *part, int stride, const int32_t *state,
+                             hipStream_t st) {
+    static bool done = false;
+    auto kern = k_spmv_part<BS, MODE>;
+    if (!done && hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, kPartLds) == hipSuccess)
+        done = true;
+    const int nt = std::min(1024, h->sell_spp * kWave);
+    kern<<<h->nsub, nt, h->S * BS * (int)sizeof(double), st>>>(spmv_mat(h), h->S, h->sell_spp, x, y, w, r_out,
+                                                               r0_out, p_out, part, stride, state);
+}
+
+// Partial sums one reducing SpMV launch leaves (one per workgroup, or one
+// per part for layout 3).
+static int spmv_partials(const dd_ctx *h) {
+    if (spmv_layout(h) == 3) return h->nsub;
+    const int rpb = (kWave / h->bs) * (kRedT / kWave);
+    return (int)((h->n + rpb - 1) / rpb);
+}
+
 template <int BS>
 static void launch_spmv_bs(dd_ctx *h, const double *x, double *y, hipStream_t st) {
     const int rpb = (kWave / BS) * (kRedT / kWave);
     const unsigned g = (unsigned)((h->n + rpb - 1) / rpb);
     const SpmvMat m = spmv_mat(h);
     switch (spmv_layout(h)) {
+        case 3:
+            launch_spmv_part<BS, 4>(h, x, y, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr, st);
+            break;
         case 2: k_spmv<BS, 2><<<g, kRedT, 0, st>>>(m, x, y); break;
         case 1: k_spmv<BS, 1><<<g, kRedT, 0, st>>>(m, x, y); break;
         default: k_spmv<BS, 0><<<g, kRedT, 0, st>>>(m, x, y);
@@ -379,6 +547,9 @@ static void spmv_dots(const dd_ctx *h, int grid, const double *x, double *y, con
                       hipStream_t st) {
     const SpmvMat m = spmv_mat(h);
     switch (spmv_layout(h)) {
+        case 3:
+            launch_spmv_part<BS, MODE>(h, x, y, w, r_out, r0_out, p_out, part, stride, state, st);
+            break;
         case 2:
             k_spmv_dots<BS, MODE, 2><<<grid, kRedT, 0, st>>>(m, x, y, w, r_out, r0_out, p_out, part, stride, state);
             break;
@@ -647,8 +818,7 @@ static int run_typed(dd_ctx *h, const KrylovWork &W, const double *b, double *x,
     const bool own = W.handle_owned;
     const bool profile = own && h->profile;
 
-    const int rpb = (kWave / BS) * (kRedT / kWave);
-    const int gsp = (int)((n + rpb - 1) / rpb);  // one partial per SpMV workgroup
+    const int gsp = spmv_partials(h);  // SpMV workgroups, and the partial sums they leave
     const int gvec = (int)std::min<int64_t>((m + kRedT - 1) / kRedT, kMaxGrid);
     const int sps = W.part_stride;
     // apply + SpMV in one launch (partials one per subdomain) where the

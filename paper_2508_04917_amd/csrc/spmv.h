@@ -154,6 +154,71 @@ __device__ __forceinline__ void sell_chunk(const int32_t *__restrict__ ecol, con
     }
 }
 
+// The same with the part's x in LDS (xs, rows row0 .. row0 + S - 1): a
+// column inside the part reads LDS; every lane also issues the global load,
+// at x_J for a column outside the part and at x_row0 (one line for the whole
+// wavefront) inside it, so the chunk stays straight-line code.
+template <int BS, int CH>
+__device__ __forceinline__ void sell_chunk_lds(const int32_t *__restrict__ ecol, const double *__restrict__ eval,
+                                               const double *__restrict__ x, const double *xs, int64_t row0, int S,
+                                               int64_t base, int k0, int q, int len, int c, double &acc) {
+    constexpr int RPW = 64 / BS, BB = BS * BS;
+    int32_t J[CH];
+    double v[CH][BS];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+        const int64_t s = base + (int64_t)min(k0 + j, len - 1) * RPW + q;
+        J[j] = ecol[s];
+        const double *blk = eval + s * BB + c * BS;
+#pragma unroll
+        for (int d = 0; d < BS; ++d) v[j][d] = blk[d];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    double xl[CH][BS], xg[CH][BS];
+    bool in[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+        const int64_t jl = (int64_t)J[j] - row0;
+        in[j] = jl >= 0 && jl < S;
+        const double *xb = x + (in[j] ? row0 : (int64_t)J[j]) * BS;
+        const double *lb = xs + (in[j] ? jl : 0) * BS;
+#pragma unroll
+        for (int d = 0; d < BS; ++d) {
+            xg[j][d] = xb[d];
+            xl[j][d] = lb[d];
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+        double t = 0.0;
+#pragma unroll
+        for (int d = 0; d < BS; ++d) t += v[j][d] * (in[j] ? xl[j][d] : xg[j][d]);
+        acc += k0 + j < len ? t : 0.0;
+    }
+}
+
+// Chunks of four positions here: each holds both x candidates, and the
+// part kernel's 1,024-lane workgroups leave 128 registers per lane.
+constexpr int kSellChunkLds = 4;
+
+template <int BS>
+__device__ __forceinline__ double sell_row_lds(const int32_t *__restrict__ ecol, const double *__restrict__ eval,
+                                               const double *__restrict__ x, const double *xs, int64_t row0, int S,
+                                               int64_t base, int w, int q, int len, int c) {
+    double acc = 0.0;
+    int k0 = 0;
+    for (; k0 + kSellChunkLds <= w; k0 += kSellChunkLds)
+        sell_chunk_lds<BS, kSellChunkLds>(ecol, eval, x, xs, row0, S, base, k0, q, len, c, acc);
+    switch (w - k0) {
+        case 1: sell_chunk_lds<BS, 1>(ecol, eval, x, xs, row0, S, base, k0, q, len, c, acc); break;
+        case 2: sell_chunk_lds<BS, 2>(ecol, eval, x, xs, row0, S, base, k0, q, len, c, acc); break;
+        case 3: sell_chunk_lds<BS, 3>(ecol, eval, x, xs, row0, S, base, k0, q, len, c, acc); break;
+        default: break;
+    }
+    return acc;
+}
+
 template <int BS>
 __device__ __forceinline__ double sell_row(const int32_t *__restrict__ ecol, const double *__restrict__ eval,
                                            const double *__restrict__ x, int64_t base, int w, int q, int len,

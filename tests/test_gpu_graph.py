@@ -58,10 +58,12 @@ def np_(t):
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_spmv_layouts(name):
-    """SpMV against the oracle on graph-partitioned matrices: the fixed-width
-    sliced ELL copy where rows hold at most 7 blocks, the copy with one width
-    per wavefront's rows where the k-nearest neighbour pattern gives longer
-    rows."""
+    """SpMV against the oracle on graph-partitioned matrices: for scalar rows,
+    part by part with the part's x in LDS (slices aligned to the parts) where
+    a part holds at least four wavefronts' rows and its x fits the LDS;
+    otherwise the fixed-width sliced ELL copy where rows hold at most 7
+    blocks, the copy with one width per wavefront's rows where rows are
+    longer."""
     p, s, st = case(name)
     x = np.random.default_rng(6).standard_normal(st.n * st.bs)
     y_o = st.spmv(x)
@@ -71,7 +73,9 @@ def test_spmv_layouts(name):
     longest = int(np.diff(st.aptr).max())
     print(f"[graph {name}] longest row {longest} blocks, layout {inf['spmv_layout']}", flush=True)
     assert inf["max_row_blocks"] == longest
-    assert inf["spmv_layout"] == (1 if longest <= 7 else 2)
+    S, bs = CASES[name][1], p.bs
+    part_local = bs == 1 and S >= 4 * 64 and S * 8 <= 163840 - 1024
+    assert inf["spmv_layout"] == (3 if part_local else (1 if longest <= 7 else 2))
 
 
 def test_worked_example_matches_oracle():

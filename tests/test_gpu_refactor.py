@@ -119,13 +119,15 @@ def test_refactor_state_and_errors():
     h.close()
 
 
-def test_refactor_graph_partition():
+@pytest.mark.parametrize("bs,spmv_layout", [(3, 2), (1, 3)])
+def test_refactor_graph_partition(bs, spmv_layout):
     """The same on a matrix without geometry (rows of up to 15 blocks): the
     apply's segmented slot layout and the SpMV's per-slice-width copy are
-    rewritten in place, and everything again equals a fresh setup."""
+    rewritten in place (for scalar rows the copy aligned to the parts), and
+    everything again equals a fresh setup."""
     import dataclasses
-    p1 = unstructured_problem(6000, seed=31, bs=3)
-    blocks = p1.val.reshape(-1, 3, 3)
+    p1 = unstructured_problem(6000, seed=31, bs=bs)
+    blocks = p1.val.reshape(-1, bs, bs)
     off = (p1.bcol != np.repeat(np.arange(p1.n), np.diff(p1.brow_ptr)))[:, None, None]
     scale = 1.0 - 0.2 * np.random.default_rng(32).random((blocks.shape[0], 1, 1))
     p2 = dataclasses.replace(p1, val=np.where(off, blocks * scale, blocks))
@@ -134,7 +136,7 @@ def test_refactor_graph_partition():
     inf = dd.dd_get_info(s.h)
     print(f"[refactor] graph: n {p1.n}, longest row {inf['max_row_blocks']} blocks, "
           f"apply layout {inf['apply_layout']}, SpMV layout {inf['spmv_layout']}", flush=True)
-    assert inf["apply_layout"] == 2 and inf["spmv_layout"] == 2
+    assert inf["apply_layout"] == 2 and inf["spmv_layout"] == spmv_layout
     b2 = cu(p2.b)
     s.solve(b2, rtol=1e-8)
     s.set_precision(dd.DD_MIXED)
