@@ -697,55 +697,95 @@ hipError_t launch_pack_slots(dd_ctx *h, int which, hipStream_t st) {
 // group that would not fit the chunk starts the next chunk of the level.
 // Only the last chunk of a level is followed by a barrier in the apply.  One
 // thread per subdomain walks its levels (count pass, then fill pass).
+// One workgroup per subdomain.  The rows of a level are taken kSegTile at a
+// time: every thread loads block counts and computes segment counts, one
+// thread places the tile's rows (the placement above, on LDS values only),
+// and every thread writes the tile's position map.
+constexpr int kSegTile = 1024;
+
 template <bool FILL>
-__global__ void k_seg_walk(int nsub, int S, int which, int mb, int cw, int rpw, const int32_t *__restrict__ off,
-                           const int32_t *__restrict__ lp, const int32_t *__restrict__ bptr, int32_t *npos,
-                           int32_t *nchk, const int32_t *__restrict__ gpos, const int32_t *__restrict__ gchk,
-                           int2 *pmap, int32_t *chk) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nsub) return;
+__global__ __launch_bounds__(256) void k_seg_walk(int S, int which, int mb, int cw, int rpw,
+                                                  const int32_t *__restrict__ off, const int32_t *__restrict__ lp,
+                                                  const int32_t *__restrict__ bptr, int32_t *npos, int32_t *nchk,
+                                                  const int32_t *__restrict__ gpos,
+                                                  const int32_t *__restrict__ gchk, int2 *pmap, int32_t *chk) {
+    __shared__ int m_s[kSegTile], at_s[kSegTile], pad_s[kSegTile];
+    __shared__ int32_t pos_s, nc_s, inchunk_s;
+    __shared__ bool open_s;
+    const int s = blockIdx.x, tid = threadIdx.x;
     const int32_t o = off[s];
     const int nl = off[s + 1] - o - 1;
     const int64_t base = (int64_t)s * S;
     const int32_t pb = FILL ? gpos[s] : 0, cb = FILL ? gchk[s] : 0;
-    int32_t pos = 0, nc = 0;
-    for (int l = 0; l < nl; ++l) {
-        int inchunk = 0;
-        bool open = false;  // a level's first position opens its first chunk
-        for (int32_t k = lp[o + l]; k < lp[o + l + 1]; ++k) {
-            const int64_t p = base + k;
-            const int32_t nb = bptr[p + 1] - bptr[p];
-            // a lower-sweep row without blocks keeps y_I = r_I: no position
-            // (a level of such rows, the lower sweep's first, has no chunk)
-            const int m = which == 0 ? (nb + mb - 1) / mb : 1 + (max(nb - mb, 0) + mb) / (mb + 1);
-            if (m == 0) continue;
-            int pad = (inchunk % rpw) + m > rpw ? rpw - inchunk % rpw : 0;
-            if (!open || inchunk + pad + m > cw) {  // the level's first or next chunk
-                if (FILL) chk[cb + nc] = pos;
-                ++nc;
-                inchunk = 0;
-                pad = 0;
-                open = true;
-            }
-            for (int q = 0; q < pad; ++q)
-                if (FILL) pmap[pb + pos + q] = make_int2(-1, 0);
-            pos += pad;
-            inchunk += pad;
-            for (int q = 0; q < m; ++q)
-                if (FILL) pmap[pb + pos + q] = make_int2((int32_t)p, q | (m << 8));
-            pos += m;
-            inchunk += m;
-        }
-        if (FILL && open) chk[cb + nc - 1] |= 1 << 30;  // barrier after the level's last chunk
+    if (tid == 0) {
+        pos_s = 0;
+        nc_s = 0;
     }
+    for (int l = 0; l < nl; ++l) {
+        if (tid == 0) {
+            inchunk_s = 0;
+            open_s = false;  // a level's first position opens its first chunk
+        }
+        const int32_t k0 = lp[o + l], k1 = lp[o + l + 1];
+        for (int32_t t0 = k0; t0 < k1; t0 += kSegTile) {
+            const int cnt = min(kSegTile, k1 - t0);
+            for (int i = tid; i < cnt; i += blockDim.x) {
+                const int64_t p = base + t0 + i;
+                const int32_t nb = bptr[p + 1] - bptr[p];
+                // a lower-sweep row without blocks keeps y_I = r_I: no position
+                // (a level of such rows, the lower sweep's first, has no chunk)
+                m_s[i] = which == 0 ? (nb + mb - 1) / mb : 1 + (max(nb - mb, 0) + mb) / (mb + 1);
+            }
+            __syncthreads();
+            if (tid == 0) {
+                int32_t pos = pos_s, nc = nc_s;
+                int inchunk = inchunk_s;
+                bool open = open_s;
+                for (int i = 0; i < cnt; ++i) {
+                    const int m = m_s[i];
+                    if (m == 0) continue;
+                    int pad = (inchunk % rpw) + m > rpw ? rpw - inchunk % rpw : 0;
+                    if (!open || inchunk + pad + m > cw) {  // the level's first or next chunk
+                        if (FILL) chk[cb + nc] = pos;
+                        ++nc;
+                        inchunk = 0;
+                        pad = 0;
+                        open = true;
+                    }
+                    pad_s[i] = pad;
+                    at_s[i] = pos + pad;  // the row's first segment
+                    pos += pad + m;
+                    inchunk += pad + m;
+                }
+                pos_s = pos;
+                nc_s = nc;
+                inchunk_s = inchunk;
+                open_s = open;
+            }
+            __syncthreads();
+            if (FILL)
+                for (int i = tid; i < cnt; i += blockDim.x) {
+                    const int m = m_s[i];
+                    if (m == 0) continue;
+                    const int32_t at = at_s[i];
+                    for (int q = 0; q < pad_s[i]; ++q) pmap[pb + at - pad_s[i] + q] = make_int2(-1, 0);
+                    for (int q = 0; q < m; ++q) pmap[pb + at + q] = make_int2((int32_t)(base + t0 + i), q | (m << 8));
+                }
+            __syncthreads();  // the tile's LDS values are reused by the next tile
+        }
+        if (FILL && tid == 0 && open_s) chk[cb + nc_s - 1] |= 1 << 30;  // barrier after the level's last chunk
+        __syncthreads();
+    }
+    if (tid != 0) return;
+    int32_t nc = nc_s;
     if (nc == 0) {  // no positions: one empty chunk, so the apply's table reads stay inside it
         if (FILL) chk[cb] = 1 << 30;
         ++nc;
     }
     if (FILL) {
-        chk[cb + nc] = pos;
+        chk[cb + nc] = pos_s;
     } else {
-        npos[s] = pos;
+        npos[s] = pos_s;
         nchk[s] = nc + 1;
     }
 }
@@ -825,8 +865,7 @@ hipError_t launch_seg_pack(dd_ctx *h, int which, hipStream_t st) {
 int build_seg_layout(dd_ctx *h, int which, int mb, int cw, int rpw, hipStream_t st) {
     Sweep &w = h->sw[which];
     const Levels &L = h->lev[which];
-    const int nsub = h->nsub, T = 256;
-    const unsigned gs = (unsigned)((nsub + T - 1) / T);
+    const int nsub = h->nsub;
     int32_t *npos = nullptr, *nchk = nullptr;
     int rc = h->alloc(&npos, nsub);
     if (!rc) rc = h->alloc(&nchk, nsub);
@@ -840,7 +879,7 @@ int build_seg_layout(dd_ctx *h, int which, int mb, int cw, int rpw, hipStream_t 
             h->allocs.erase(it);
         }
     };
-    k_seg_walk<false><<<gs, T, 0, st>>>(nsub, h->S, which, mb, cw, rpw, L.off, L.ptr, w.bptr, npos, nchk, nullptr,
+    k_seg_walk<false><<<nsub, 256, 0, st>>>(h->S, which, mb, cw, rpw, L.off, L.ptr, w.bptr, npos, nchk, nullptr,
                                         nullptr, nullptr, nullptr);
     hipError_t e = exclusive_scan(npos, w.gpos, nsub, h->scan_tmp, st);
     if (e == hipSuccess) e = exclusive_scan(nchk, w.gchk, nsub, h->scan_tmp, st);
@@ -858,7 +897,7 @@ int build_seg_layout(dd_ctx *h, int which, int mb, int cw, int rpw, hipStream_t 
     if (!rc) rc = h->alloc(&w.desc, tot[0]);
     if (!rc) rc = h->alloc(&w.sval64, (int64_t)tot[0] * (mb + which) * bb);
     if (rc) return rc;
-    k_seg_walk<true><<<gs, T, 0, st>>>(nsub, h->S, which, mb, cw, rpw, L.off, L.ptr, w.bptr, nullptr, nullptr, w.gpos,
+    k_seg_walk<true><<<nsub, 256, 0, st>>>(h->S, which, mb, cw, rpw, L.off, L.ptr, w.bptr, nullptr, nullptr, w.gpos,
                                        w.gchk, w.pmap, w.chk);
     e = hipGetLastError();
     if (e == hipSuccess) e = launch_seg_pack(h, which, st);
