@@ -193,6 +193,49 @@ def ablation(args, p, sub, ptr_d, col_d, val_d, dd, torch):
     print(json.dumps(out), flush=True)
 
 
+def rocsparse_scalar(p, ptr, col, val, r, z_ref, burst, rel, us_dd):
+    """rocSPARSE's scalar ILU0 (csrilu0, csrsv) on the CSR expansion of a
+    BSR matrix: the same preconditioner on a pattern of dense blocks."""
+    import torch
+    from paper_2508_04917_amd.rocsparse_ref import RocsparseILU0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rs = RocsparseILU0(p.n, p.bs, ptr, col, val, scalar=True)
+    setup = time.perf_counter() - t0
+    zs = torch.empty_like(r)
+    us_rs = burst(lambda: rs.apply(r, zs))
+    rs.close()
+    res = {"us": round(us_rs, 2), "setup_s": round(setup, 3), "rel_diff": rel(zs, z_ref),
+           "dd_apply_speedup": round(us_rs / us_dd, 2)}
+    log(f"  rocSPARSE scalar ILU0 (CSR expansion): {us_rs:.1f} us per apply ({us_rs / us_dd:.1f}x the DD apply), "
+        f"setup {setup:.2f} s, rel diff {res['rel_diff']:.1e}")
+    return res
+
+
+def rocsparse_permuted(p, ptr, col, val, n2o, r, z_ref, burst, rel, us_dd):
+    """rocSPARSE's ILU0 apply on P A P^T for the renumbering n2o (new ->
+    old block rows), timed like the others; its output, renumbered back, is
+    compared with z_ref (the apply of the same factors in the old order)."""
+    import torch
+    from paper_2508_04917_amd.rocsparse_ref import RocsparseILU0, permuted_matrix
+    pp, pc, pv = permuted_matrix(ptr, col, val, n2o, p.bs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rs = RocsparseILU0(p.n, p.bs, pp, pc, pv)
+    setup = time.perf_counter() - t0
+    rp = r.view(-1, p.bs)[n2o].reshape(-1).contiguous()
+    zp = torch.empty_like(r)
+    us_rs = burst(lambda: rs.apply(rp, zp))
+    zb = torch.empty_like(r)
+    zb.view(-1, p.bs)[n2o] = zp.view(-1, p.bs)
+    rs.close()
+    res = {"us": round(us_rs, 2), "setup_s": round(setup, 3), "rel_diff": rel(zb, z_ref),
+           "dd_apply_speedup": round(us_rs / us_dd, 2)}
+    log(f"  rocSPARSE ILU0, rows in level order: {us_rs:.1f} us per apply ({us_rs / us_dd:.1f}x the DD apply), "
+        f"rel diff {res['rel_diff']:.1e}")
+    return res
+
+
 def rocsparse_cmp(args, p, sub, ptr_d, col_d, val_d, dd, torch):
     """The paper's headline comparison (Section 5.2, Table 4) restated on this
     GPU: rocSPARSE's block ILU0 apply (two block triangular solves) as a black
@@ -200,7 +243,7 @@ def rocsparse_cmp(args, p, sub, ptr_d, col_d, val_d, dd, torch):
     and on the full matrix (global ILU0, against this library's
     level-scheduled global ILU0), outputs compared, bursts of applies timed
     with events."""
-    from paper_2508_04917_amd.rocsparse_ref import RocsparseILU0, dropped_matrix
+    from paper_2508_04917_amd.rocsparse_ref import RocsparseILU0, dropped_matrix, level_order
     h = dd.dd_partition(p.nx, p.ny, p.nz, p.bs, ptr_d, col_d, val_d, sub=sub)
     dd.ilu0_factor(h, dd.DD_FP64)
     inf = dd.dd_get_info(h)
@@ -244,6 +287,12 @@ def rocsparse_cmp(args, p, sub, ptr_d, col_d, val_d, dd, torch):
     log(f"rocSPARSE ILU0 on the decomposed matrix: {us_rs:.1f} us per apply ({us_rs / us:.1f}x the DD apply), "
         f"setup {setup:.2f} s, rel diff {rel(z_rs, z):.1e}")
     rs.close()
+    # the same matrix with its block rows sorted by level (every coupled pair
+    # keeps its order, so the factors are the same): the ordering under which
+    # a row-by-row triangular solve meets ready rows one after another
+    n2o = level_order(ptr_t, col_t)
+    out["rocsparse_decomposed_level_order"] = rocsparse_permuted(p, ptr_t, col_t, val_t, n2o, r, z, burst, rel, us)
+    out["rocsparse_decomposed_scalar"] = rocsparse_scalar(p, ptr_t, col_t, val_t, r, z, burst, rel, us)
     del ptr_t, col_t, val_t
 
     torch.cuda.synchronize()
@@ -274,6 +323,11 @@ def rocsparse_cmp(args, p, sub, ptr_d, col_d, val_d, dd, torch):
                                       "dd_apply_speedup": round(us_rsn / us, 2)}
     log(f"rocSPARSE ILU0 on the matrix in natural order: {us_rsn:.1f} us per apply ({us_rsn / us:.1f}x the DD apply)")
     rsn.close()
+    # the natural order's global ILU0 with the rows sorted by level (the
+    # grid's diagonal planes), checked against rocSPARSE's own apply in the
+    # natural order (the same factors)
+    n2o = level_order(ptr_d, col_d)
+    out["rocsparse_natural_level_order"] = rocsparse_permuted(p, ptr_d, col_d, val_d, n2o, r, z_rsn, burst, rel, us)
     h.close()
     print(json.dumps(out), flush=True)
 

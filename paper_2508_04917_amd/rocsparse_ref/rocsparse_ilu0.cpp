@@ -10,6 +10,12 @@
 //       analyses of both triangular solves on the stream, synchronises, and
 //       returns 0, or a negative code (message in rsr_last_error()); a zero
 //       pivot is an error.
+//   rsr_create_scalar(mb, nnzb, bs, ptr, col, val, stream, &out)
+//       the same through rocSPARSE's scalar routines: the BSR matrix is
+//       expanded to CSR (bsr2csr), then csrilu0 and two csrsv solves.  On a
+//       pattern of dense blocks the scalar ILU0 equals the block ILU0 (the
+//       fill stays inside the blocks), so both give the same preconditioner
+//       up to rounding.
 //   rsr_apply(h, r, z, stream)      z = U^{-1} L^{-1} r (r != z), asynchronous.
 //   rsr_destroy(h)
 #include <hip/hip_runtime.h>
@@ -39,12 +45,16 @@ struct Rsr {
     rocsparse_mat_descr dM = nullptr, dL = nullptr, dU = nullptr;
     rocsparse_mat_info info = nullptr;
     int32_t mb = 0, nnzb = 0, bs = 0;
+    bool scalar = false;  // CSR expansion and the scalar routines
     const int32_t *ptr = nullptr, *col = nullptr;
+    int32_t *sptr = nullptr, *scol = nullptr;  // the CSR expansion (scalar)
     double *val = nullptr, *tmp = nullptr;
     void *buf = nullptr;
 
     ~Rsr() {
         if (buf) (void)hipFree(buf);
+        if (sptr) (void)hipFree(sptr);
+        if (scol) (void)hipFree(scol);
         if (val) (void)hipFree(val);
         if (tmp) (void)hipFree(tmp);
         if (info) rocsparse_destroy_mat_info(info);
@@ -140,6 +150,15 @@ int rsr_apply(void *hv, const double *r, double *z, void *stream) {
     const double one = 1.0;
     const rocsparse_direction dir = rocsparse_direction_row;
     const rocsparse_operation none = rocsparse_operation_none;
+    if (h->scalar) {
+        rocsparse_status s = rocsparse_dcsrsv_solve(h->handle, none, h->mb, h->nnzb, &one, h->dL, h->val, h->ptr,
+                                                    h->col, h->info, r, h->tmp, rocsparse_solve_policy_auto, h->buf);
+        if (s != rocsparse_status_success) return fail("rsr_apply: lower csrsv status %d", (int)s);
+        s = rocsparse_dcsrsv_solve(h->handle, none, h->mb, h->nnzb, &one, h->dU, h->val, h->ptr, h->col, h->info,
+                                   h->tmp, z, rocsparse_solve_policy_auto, h->buf);
+        if (s != rocsparse_status_success) return fail("rsr_apply: upper csrsv status %d", (int)s);
+        return 0;
+    }
     rocsparse_status s = rocsparse_dbsrsv_solve(h->handle, dir, none, h->mb, h->nnzb, &one, h->dL, h->val, h->ptr,
                                                 h->col, h->bs, h->info, r, h->tmp, rocsparse_solve_policy_auto,
                                                 h->buf);
@@ -147,6 +166,65 @@ int rsr_apply(void *hv, const double *r, double *z, void *stream) {
     s = rocsparse_dbsrsv_solve(h->handle, dir, none, h->mb, h->nnzb, &one, h->dU, h->val, h->ptr, h->col, h->bs,
                                h->info, h->tmp, z, rocsparse_solve_policy_auto, h->buf);
     if (s != rocsparse_status_success) return fail("rsr_apply: upper bsrsv status %d", (int)s);
+    return 0;
+}
+
+int rsr_create_scalar(int32_t mb, int32_t nnzb, int32_t bs, const int32_t *ptr, const int32_t *col,
+                      const double *val, void *stream, void **out) {
+    if (!out || mb <= 0 || nnzb <= 0 || bs <= 0 || !ptr || !col || !val) return fail("rsr_create_scalar: bad arguments");
+    if ((int64_t)nnzb * bs * bs > INT32_MAX || (int64_t)mb * bs > INT32_MAX)
+        return fail("rsr_create_scalar: the CSR expansion exceeds 32-bit indices");
+    *out = nullptr;
+    Rsr *h = new Rsr;
+    h->scalar = true;
+    h->mb = mb * bs;           // scalar rows
+    h->nnzb = nnzb * bs * bs;  // scalar nonzeros
+    h->bs = 1;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int32_t m = h->mb, nnz = h->nnzb;
+    HP(hipMalloc(&h->val, (size_t)nnz * sizeof(double)));
+    HP(hipMalloc(&h->sptr, (size_t)(m + 1) * sizeof(int32_t)));
+    HP(hipMalloc(&h->scol, (size_t)nnz * sizeof(int32_t)));
+    HP(hipMalloc(&h->tmp, (size_t)m * sizeof(double)));
+    h->ptr = h->sptr;
+    h->col = h->scol;
+    RS(rocsparse_create_handle(&h->handle));
+    RS(rocsparse_set_stream(h->handle, st));
+    RS(rocsparse_create_mat_descr(&h->dM));
+    RS(rocsparse_create_mat_descr(&h->dL));
+    RS(rocsparse_set_mat_fill_mode(h->dL, rocsparse_fill_mode_lower));
+    RS(rocsparse_set_mat_diag_type(h->dL, rocsparse_diag_type_unit));
+    RS(rocsparse_create_mat_descr(&h->dU));
+    RS(rocsparse_set_mat_fill_mode(h->dU, rocsparse_fill_mode_upper));
+    RS(rocsparse_set_mat_diag_type(h->dU, rocsparse_diag_type_non_unit));
+    RS(rocsparse_create_mat_info(&h->info));
+    RS(rocsparse_dbsr2csr(h->handle, rocsparse_direction_row, mb, mb, h->dM, val, ptr, col, bs, h->dM, h->val,
+                          h->sptr, h->scol));
+    const rocsparse_operation none = rocsparse_operation_none;
+    size_t s0 = 0, s1 = 0, s2 = 0;
+    RS(rocsparse_dcsrilu0_buffer_size(h->handle, m, nnz, h->dM, h->val, h->sptr, h->scol, h->info, &s0));
+    RS(rocsparse_dcsrsv_buffer_size(h->handle, none, m, nnz, h->dL, h->val, h->sptr, h->scol, h->info, &s1));
+    RS(rocsparse_dcsrsv_buffer_size(h->handle, none, m, nnz, h->dU, h->val, h->sptr, h->scol, h->info, &s2));
+    size_t sz = s0 > s1 ? s0 : s1;
+    sz = sz > s2 ? sz : s2;
+    HP(hipMalloc(&h->buf, sz > 0 ? sz : 1));
+    RS(rocsparse_dcsrilu0_analysis(h->handle, m, nnz, h->dM, h->val, h->sptr, h->scol, h->info,
+                                   rocsparse_analysis_policy_reuse, rocsparse_solve_policy_auto, h->buf));
+    RS(rocsparse_dcsrsv_analysis(h->handle, none, m, nnz, h->dL, h->val, h->sptr, h->scol, h->info,
+                                 rocsparse_analysis_policy_reuse, rocsparse_solve_policy_auto, h->buf));
+    RS(rocsparse_dcsrsv_analysis(h->handle, none, m, nnz, h->dU, h->val, h->sptr, h->scol, h->info,
+                                 rocsparse_analysis_policy_reuse, rocsparse_solve_policy_auto, h->buf));
+    RS(rocsparse_dcsrilu0(h->handle, m, nnz, h->dM, h->val, h->sptr, h->scol, h->info, rocsparse_solve_policy_auto,
+                          h->buf));
+    rocsparse_int pos = -1;
+    const rocsparse_status zp = rocsparse_csrilu0_zero_pivot(h->handle, h->info, &pos);
+    if (zp == rocsparse_status_zero_pivot) {
+        delete h;
+        return fail("rsr_create_scalar: zero pivot in row %d", (int)pos);
+    }
+    RS(zp);
+    HP(hipStreamSynchronize(st));
+    *out = h;
     return 0;
 }
 

@@ -19,7 +19,8 @@ if not torch.cuda.is_available():  # pragma: no cover
     pytest.skip("no GPU", allow_module_level=True)
 
 from paper_2508_04917_amd import ddilu as dd  # noqa: E402
-from paper_2508_04917_amd.rocsparse_ref import RocsparseILU0, dropped_matrix  # noqa: E402
+from paper_2508_04917_amd.rocsparse_ref import (  # noqa: E402
+    RocsparseILU0, dropped_matrix, level_order, permuted_matrix)
 from paper_2508_04917_amd.solver import DDSolver  # noqa: E402
 
 CASES = {
@@ -48,10 +49,27 @@ def test_rocsparse_matches_dd_and_global(name):
         st = O.setup(p, (inf["sx"], inf["sy"], inf["sz"]))
         z_o = st.apply(r.cpu().numpy())
         assert np.linalg.norm(z_dd.cpu().numpy() - z_o) / np.linalg.norm(z_o) < 1e-12
-        # rocSPARSE on the decomposed matrix: the same preconditioner
-        rs = RocsparseILU0(p.n, p.bs, *dropped_matrix(ptr, col, val, S, p.bs))
+        # rocSPARSE on the decomposed matrix: the same preconditioner, through
+        # the block routines, the scalar routines on the CSR expansion, and
+        # the block routines with the rows in level order
+        dm = dropped_matrix(ptr, col, val, S, p.bs)
+        rs = RocsparseILU0(p.n, p.bs, *dm)
         try:
             assert rel(rs.apply(r), z_dd) < 1e-12
+        finally:
+            rs.close()
+        rs = RocsparseILU0(p.n, p.bs, *dm, scalar=True)
+        try:
+            assert rel(rs.apply(r), z_dd) < 1e-12
+        finally:
+            rs.close()
+        n2o = level_order(dm[0], dm[1])
+        rs = RocsparseILU0(p.n, p.bs, *permuted_matrix(*dm, n2o, p.bs))
+        try:
+            zp = rs.apply(r.view(-1, p.bs)[n2o].reshape(-1).contiguous())
+            zb = torch.empty_like(zp)
+            zb.view(-1, p.bs)[n2o] = zp.view(-1, p.bs)
+            assert rel(zb, z_dd) < 1e-12
         finally:
             rs.close()
         # rocSPARSE on the full matrix: global ILU0
