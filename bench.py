@@ -34,6 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+MALL_BYTES = 256 << 20  # MI355X last-level cache (Infinity Cache)
 METRIC = "trisolve GB/s & %HBM peak; BiCGSTAB s to 1e-8: learned+FP32 vs plain FP64"
 
 
@@ -68,7 +69,9 @@ def kernels_only(args, p, sub, ptr_d, col_d, val_d, dd, torch):
     """A plain device copy of known size (the reference for scaling hardware
     byte counters), then bursts of applies in each precision and of the
     SpMV, each burst timed with events on the stream the library launches
-    on."""
+    on.  An apply whose bytes would stay in the last-level cache is also
+    timed one apply at a time after a 1 GiB write."""
+    import numpy as np
     copy_elems = 1 << 28  # 2 GiB of FP64 read + 2 GiB written
     src = torch.ones(copy_elems, dtype=torch.float64, device="cuda:0")
     dst = torch.empty_like(src)
@@ -100,6 +103,22 @@ def kernels_only(args, p, sub, ptr_d, col_d, val_d, dd, torch):
         nbytes = dd.dd_get_info(h)["apply_bytes"]
         out[name] = {"us_per_apply": round(us, 2), "bytes_per_apply": nbytes, "GB/s": round(nbytes / us / 1e3, 1)}
         log(f"{name}: {us:.1f} us per apply, {nbytes / us / 1e3:.1f} GB/s")
+        if nbytes < MALL_BYTES:
+            # the apply's working set fits the 256 MB last-level cache, so a
+            # burst reads it from there (an effective rate, not HBM's): time
+            # each apply again after writing 1 GiB, which evicts it
+            flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0")
+            fev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.applies)]
+            for e in fev:
+                flush.fill_(1.0)
+                e[0].record()
+                dd.dd_trsv_apply(h, r, z)
+                e[1].record()
+            torch.cuda.synchronize()
+            fus = float(np.median([1e3 * e[0].elapsed_time(e[1]) for e in fev]))
+            del flush
+            out[name]["after_cache_flush"] = {"us_per_apply": round(fus, 2), "GB/s": round(nbytes / fus / 1e3, 1)}
+            log(f"{name} after a cache flush: {fus:.1f} us per apply, {nbytes / fus / 1e3:.1f} GB/s")
     # the learned correction on FP32 factors (the metric's learned leg), with
     # the shipped parameters; bytes as the mixed apply's plus 64 per face
     # (C_f in FP32, the face's column and r_J)
