@@ -436,6 +436,11 @@ static int build_slots(dd_ctx *h, hipStream_t st) {
         auto fits = [&](int mb) { return lo <= mb * kSegMax && up <= mb + (kSegMax - 1) * (mb + 1); };
         const int mb = fits(2) ? 2 : (fits(3) ? 3 : 0);
         if (!mb) return DD_OK;
+        // the walk counts positions in 32-bit integers: a row takes at most
+        // kSegMax segments and kSegMax - 1 padding positions, so stay on the
+        // plain loop where that bound could pass 2^31
+        for (int w = 0; w < 2; ++w)
+            if ((int64_t)(h->sw[w].nblk + h->n) * (2 * kSegMax) >= ((int64_t)1 << 31)) return DD_OK;
         const int rpw = kWave / h->bs, cw = rpw * (1024 / kWave);
         h->seg = mb;  // the packing reads it
         for (int w = 0; w < 2; ++w) {
