@@ -535,14 +535,16 @@ def host_cpu():
     return model, len(os.sched_getaffinity(0))
 
 
-def cpu_baseline(args, p, sub, bytes64, np):
+def cpu_baseline(args, p, sub, bytes64, np, gpu_iters=None):
     """The oracle timed on this host's CPU cores, on the same matrix: the
     DD-ILU0 apply single-threaded (the oracle's own whole-matrix call) and
     subdomain-parallel on every available core (one oracle call per
     subdomain's rows of the dropped matrix, which share no coupling; the
     calls release the GIL), bytes counted as for the GPU apply; plus the
     oracle's BiCGSTAB (setup and solve, single-threaded) on the 16^3 scalar
-    Laplacian and the 64^3 random-block operator."""
+    Laplacian and the 64^3 random-block operator, and a few iterations of
+    it on the same matrix (seconds per iteration, and the solve time that
+    rate gives at the GPU solve's iteration count)."""
     import concurrent.futures as cf
 
     import oracle as O
@@ -589,6 +591,17 @@ def cpu_baseline(args, p, sub, bytes64, np):
            "apply_ms": {"threads": round(dtn * 1e3, 2), "single": round(dt1 * 1e3, 2)},
            "setup_s": round(setup_s, 3), "solves": {}}
     log(f"cpu baseline apply: {dt1 * 1e3:.1f} ms single-threaded, {dtn * 1e3:.1f} ms on {threads} threads")
+    if args.cpu_iters > 0:
+        # the oracle's BiCGSTAB (single-threaded) for a bounded number of
+        # iterations on the bench matrix: its full solve would take minutes
+        t = time.perf_counter()
+        res = st.bicgstab(p.b, rtol=args.rtol, maxit=args.cpu_iters)
+        t_it = (time.perf_counter() - t) / max(res.iters, 1)
+        out["bicgstab"] = {"iterations_run": res.iters, "s_per_iteration": round(t_it, 3), "threads": 1}
+        if gpu_iters:
+            out["bicgstab"]["solve_s_at_gpu_iterations"] = round(t_it * gpu_iters, 1)
+            out["bicgstab"]["gpu_iterations"] = gpu_iters
+        log(f"cpu baseline BiCGSTAB on {p.nx}x{p.ny}x{p.nz}: {res.iters} iterations, {t_it:.2f} s each")
     if args.cpu_solves:
         for wname in ("laplacian16_scalar", "random64_bsr3"):
             q = make_workload(wname)
@@ -675,6 +688,8 @@ def main():
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--cpu-applies", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=2,
+                    help="iterations of the oracle's BiCGSTAB timed on the bench matrix (0: none)")
     ap.add_argument("--cpu-solves", type=int, default=1,
                     help="1: the CPU baseline also times the oracle's BiCGSTAB on the 16^3 scalar "
                          "and 64^3 random-block workloads")
@@ -920,7 +935,7 @@ def main():
             out["workloads"][wname] = compare_workload(args, wname, override, lic_params, dd, torch, np)
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args, p, tuple(subd), bytes64, np)
+        out["cpu_baseline"] = cpu_baseline(args, p, tuple(subd), bytes64, np, gpu_iters=recs[0]["fp64"]["iters"])
     print(json.dumps(out), flush=True)
 
 
