@@ -142,11 +142,51 @@ __device__ __forceinline__ void lic_finish(TC *__restrict__ y, const double *__r
 // The subdomain's slice of r into LDS: each thread issues kLoadU loads
 // before it waits for any (a plain strided loop would wait for every load
 // in turn), positions past the end clamped to a valid one and not stored.
+// With VEC, where the slice starts on a 16-byte boundary (an even number
+// of values before it), pairs of values move as one 16-byte access: half as
+// many load instructions for the same bytes in flight (an odd last value
+// moves on its own).  The apply with the learned correction keeps the
+// 8-byte accesses: with its face records in flight across the slice load,
+// the paired form measured far slower there (368 against 284 us per apply).
 constexpr int kLoadU = 8;
+constexpr int kLoadU2 = kLoadU / 2;
 
 template <typename TC>
+struct Pair;
+template <>
+struct Pair<double> {
+    using T = double2;
+};
+template <>
+struct Pair<float> {
+    using T = float2;
+};
+
+template <typename TC, bool VEC = false>
 __device__ __forceinline__ void load_slice(TC *__restrict__ y, const double *__restrict__ rs, int m, int tid,
                                            int nt) {
+    using P = typename Pair<TC>::T;
+    if (VEC && (reinterpret_cast<uintptr_t>(rs) & 15) == 0) {  // uniform over the workgroup
+        const int m2 = m >> 1;
+        const double2 *__restrict__ r2 = reinterpret_cast<const double2 *>(rs);
+        P *__restrict__ y2 = reinterpret_cast<P *>(y);
+        for (int i0 = tid; i0 < m2; i0 += kLoadU2 * nt) {
+            double2 v[kLoadU2];
+#pragma unroll
+            for (int u = 0; u < kLoadU2; ++u) v[u] = r2[min(i0 + u * nt, m2 - 1)];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < kLoadU2; ++u)
+                if (i0 + u * nt < m2) {
+                    P w;
+                    w.x = static_cast<TC>(v[u].x);
+                    w.y = static_cast<TC>(v[u].y);
+                    y2[i0 + u * nt] = w;
+                }
+        }
+        if ((m & 1) && tid == 0) y[m - 1] = static_cast<TC>(rs[m - 1]);
+        return;
+    }
     for (int i0 = tid; i0 < m; i0 += kLoadU * nt) {
         double v[kLoadU];
 #pragma unroll
@@ -158,10 +198,32 @@ __device__ __forceinline__ void load_slice(TC *__restrict__ y, const double *__r
     }
 }
 
-// LDS back to the subdomain's slice of z, kLoadU values per thread at a time.
-template <typename TC>
+// LDS back to the subdomain's slice of z, kLoadU values per thread at a
+// time (with VEC in pairs where the slice starts on a 16-byte boundary).
+template <typename TC, bool VEC = false>
 __device__ __forceinline__ void store_slice(double *__restrict__ zs, const TC *__restrict__ y, int m, int tid,
                                             int nt) {
+    using P = typename Pair<TC>::T;
+    if (VEC && (reinterpret_cast<uintptr_t>(zs) & 15) == 0) {  // uniform over the workgroup
+        const int m2 = m >> 1;
+        double2 *__restrict__ z2 = reinterpret_cast<double2 *>(zs);
+        const P *__restrict__ y2 = reinterpret_cast<const P *>(y);
+        for (int i0 = tid; i0 < m2; i0 += kLoadU2 * nt) {
+            P v[kLoadU2];
+#pragma unroll
+            for (int u = 0; u < kLoadU2; ++u) v[u] = y2[min(i0 + u * nt, m2 - 1)];
+#pragma unroll
+            for (int u = 0; u < kLoadU2; ++u)
+                if (i0 + u * nt < m2) {
+                    double2 w;
+                    w.x = static_cast<double>(v[u].x);
+                    w.y = static_cast<double>(v[u].y);
+                    z2[i0 + u * nt] = w;
+                }
+        }
+        if ((m & 1) && tid == 0) zs[m - 1] = static_cast<double>(y[m - 1]);
+        return;
+    }
     for (int i0 = tid; i0 < m; i0 += kLoadU * nt) {
         TC v[kLoadU];
 #pragma unroll
@@ -861,7 +923,7 @@ __device__ __forceinline__ void apply_slots_sub(
     LicState lst;
     LicPass<BS> lpass;
     if constexpr (LIC) lic_begin<BS>(lst, lpass, base, S, s, la, tid, nt);
-    load_slice<TC>(y, rs, S * BS, tid, nt);
+    load_slice<TC, !LIC>(y, rs, S * BS, tid, nt);
     __syncthreads();
     if constexpr (LIC) lic_finish<BS, TC>(y, r, lst, lpass, la, tid, nt);
     const int wrow0 = __builtin_amdgcn_readfirstlane(wave) * RPW;  // first slot of this wavefront
@@ -876,7 +938,7 @@ __device__ __forceinline__ void apply_slots_sub(
         sweep_slots<BS, TS, TC, MB, PD, true>(y, base, S, s, Uoff, Ulp, Udesc, Uval, slot, wrow0, lane_ok, c);
     }
     double *zs = z + base * BS;
-    store_slice<TC>(zs, y, S * BS, tid, nt);
+    store_slice<TC, !LIC>(zs, y, S * BS, tid, nt);
 }
 
 template <int BS, typename TS, typename TC, int NT, int MB, int PD, bool LIC, bool SEG = false>
