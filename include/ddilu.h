@@ -276,9 +276,12 @@ int dd_get_factors(dd_handle h, int32_t *ptr, int32_t *col, double *f,
  * workgroup per subdomain, the subdomain's vector resident in LDS:
  * forward y_I = r_I - sum_{J<I} L_IJ y_J, then
  * z_I = inv_D_I y_I - sum_{K>I} Uhat_IK z_K (the scaling is fused into the
- * upper sweep).  r, z: device double[n*bs] in REORDERED order; r != z.
- * With a learned correction set (lic_set_params), r is first replaced by
- * r + C r, C the per-face interface coupling.  Does not synchronise. */
+ * upper sweep).  r, z: device double[n*bs] in REORDERED order; r != z;
+ * 8-byte alignment suffices (subdomain slices that start on a 16-byte
+ * boundary move as 16-byte pairs, others value by value; the result is the
+ * same).  With a learned correction set (lic_set_params), r is first
+ * replaced by r + C r, C the per-face interface coupling.  Does not
+ * synchronise. */
 int dd_trsv_apply(dd_handle h, const double *r, double *z, void *hip_stream);
 
 /* y = A x with the full reordered matrix (device double[n*bs], reordered
