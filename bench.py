@@ -712,7 +712,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "single-GPU build: the apply and solver run on one GPU; "
+        print(json.dumps({"error": "the apply and the solver run on one GPU; "
                           "multi-GPU sharding is not implemented (run with --gpus 1)"}))
         sys.exit(2)
 
